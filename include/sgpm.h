@@ -1,0 +1,220 @@
+/*
+ * sgpm.h -- C-ABI of the MI355X (gfx950) implementation of the per-time-step
+ * hot path of the stochastic-Galerkin particle method (sG-PM) for the
+ * space-homogeneous semiclassical Boltzmann equation of electrons in a
+ * graphene nanoribbon with uncertain band gap and field
+ * (Medaglia, Nastasi, Romano, Zanella, arXiv:2404.19602).
+ *
+ * Problem statement (Sec. 4, "Semiclassical BE in the presence of
+ * uncertainties"): f(t,k,z) solves df/dt - (e/hbar) E(z).grad_k f = C[f,f]
+ * with a Fermi-Dirac initial datum at the band of width W(z); the quantities
+ * of interest are expectations over z of the velocity, current and energy
+ * moments (Sec. 4.2).  Each particle carries the gPC coefficients of its
+ * wave-vector k_i(z) (Sec. 4.1 eq. gPC); one step is the Galerkin drift
+ * followed by the nodal collision step of Algorithm 2 with the Pauli factor
+ * taken from the previous-step k-histogram (Sec. 3, eq. Pauli).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Units: energies in eV; wave-vectors as kappa = hbar v_F k in eV (the
+ *    paper states its grid in these units, L_k hbar v_F = 5 eV); fields in
+ *    V/m; times in s; velocities in m/s; current densities in A/m.
+ *  - Device memory is owned by the caller: sgpm_workspace_bytes() tells how
+ *    much, sgpm_create() receives a device pointer to it.  The library never
+ *    allocates device memory.  Host memory for outputs is owned by the caller.
+ *  - All device work is enqueued on the HIP stream given at creation
+ *    (hipStream_t passed as void*; NULL = the default stream).  Calls that
+ *    return host data synchronise that stream.
+ *  - Errors: every call returns an sgpm_status.  Arguments are validated
+ *    before any device work (SGPM_EINVAL).  A HIP failure returns
+ *    SGPM_EDEVICE and poisons the context: later calls return SGPM_ESTATE.
+ *    sgpm_last_error() gives a message.  No C++ exception crosses the ABI.
+ *  - A context is not thread-safe; use one context per host thread/stream.
+ *
+ * Layouts
+ * -------
+ *  - Uncertain variables z are uniform on [-1,1]^dim_z.  Nodes: tensor
+ *    Gauss-Legendre with nodes_1d points per dimension, node q = q1 + nodes_1d*q2
+ *    for dim_z = 2 (z_1 fastest); weights w_q sum to one.
+ *  - Basis: orthonormal Legendre products; for dim_z = 2 the total-degree
+ *    basis in graded order (t = 0..M; within t the exponent of z_1 runs from
+ *    t down to 0): (0,0),(1,0),(0,1),(2,0),(1,1),(0,2),...  P modes.
+ *  - State: structure of arrays, kx[h][i] then ky[h][i] for h < P, i < N
+ *    (FP64 in the host-facing calls regardless of the device precision).
+ *  - Histogram: uint32 H[q][r][l], r = x index, l = y index of the cell of
+ *    [-L_k, L_k]^2 split in nk x nk cells.
+ */
+#ifndef SGPM_H
+#define SGPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sgpm_ctx sgpm_ctx;
+
+typedef enum {
+    SGPM_OK = 0,
+    SGPM_EINVAL = 1,       /* invalid argument or descriptor                */
+    SGPM_ENOMEM = 2,       /* host allocation failed                        */
+    SGPM_EWORKSPACE = 3,   /* workspace missing, too small or misaligned    */
+    SGPM_EDEVICE = 4,      /* a HIP call failed (context is now poisoned)   */
+    SGPM_ESTATE = 5,       /* call not valid in the current state           */
+    SGPM_EUNSUPPORTED = 6  /* combination not supported by this build       */
+} sgpm_status;
+
+typedef enum { SGPM_FP64 = 0, SGPM_FP32 = 1 } sgpm_precision;
+
+/* Per-mechanism order of the rate vector (Sec. 3 eq. lambda). */
+enum { SGPM_AC = 0, SGPM_OP_EM = 1, SGPM_OP_AB = 2, SGPM_K_EM = 3, SGPM_K_AB = 4, SGPM_EDGE = 5 };
+
+/* Counters (sgpm_counters), cumulative since sgpm_init_particles/sgpm_set_state. */
+enum {
+    SGPM_CNT_COLLISIONS = 0,   /* collision iterations (per particle)            */
+    SGPM_CNT_EVENTS = 1,       /* non-self events at a node, before Pauli        */
+    SGPM_CNT_PAULI_REJ = 2,    /* node events rejected by the Pauli acceptance   */
+    SGPM_CNT_EDGE_EXH = 3,     /* edge angle proposals exhausted (kept as self)  */
+    SGPM_CNT_CMAX = 4,         /* particles that reached the collision cap       */
+    SGPM_CNT_OUT_OF_GRID = 5,  /* node values outside the histogram grid         */
+    SGPM_CNT_CANDIDATES = 6,   /* particles the rate bound could not clear       */
+    SGPM_N_COUNTERS = 8
+};
+
+/* One simulation instance.  Defaults in brackets are the paper's. */
+typedef struct {
+    int32_t dim_z;          /* number of uncertain inputs: 0, 1 or 2              */
+    int32_t degree;         /* gPC total degree M (P = M+1 for dim_z = 1)         */
+    int32_t nodes_1d;       /* Gauss-Legendre nodes per uncertain dimension       */
+    int32_t precision;      /* sgpm_precision of the particle state and kernels   */
+    int64_t n_particles;    /* N >= 1                                             */
+    int32_t gap_mode;       /* 0: band gap in eV, gap(z) = gap0 (1 + gap_rel z)     */
+                            /* 1: ribbon width in nm, W(z) = gap0 (1 + gap_rel z)   */
+    int32_t gap_dim;        /* component of z driving gap/width, -1: deterministic */
+    double gap0, gap_rel;
+    int32_t field_dim;      /* component of z driving the field, -1: deterministic */
+    double field0, field_rel; /* E_x(z) = field0 (1 + field_rel z), V/m           */
+    double fermi_eV;        /* Fermi level of the initial datum [0.4]              */
+    double temp_K;          /* lattice and initial temperature [300]               */
+    double alpha;           /* self-scattering parameter of eq. gamma_tot [0.1]     */
+    int32_t nk;             /* histogram cells per axis [240]                       */
+    double lk_eV;           /* grid half-width L_k hbar v_F [5]                     */
+    int32_t pauli;          /* 1: Pauli acceptance on [1]                           */
+    int32_t final_state;    /* 0: energy-conserving phonon final state [0]; 1: the  */
+                            /*    paper-literal |k| -/+ omega/v_F                   */
+    double rate_scale[6];   /* test knob per mechanism, 1 = physics                 */
+    uint64_t seed;          /* Philox key                                           */
+    uint32_t instance_id;   /* Philox counter word 3                                */
+    int32_t c_max;          /* cap on collisions per particle per step [32], <= 255 */
+    int32_t max_steps;      /* capacity of the moment record (steps after init)    */
+} sgpm_instance_desc;
+
+/* Fill a descriptor with the paper's defaults (Table 1 and Sec. 5). */
+void sgpm_default_desc(sgpm_instance_desc* d);
+
+/* Device workspace needed for n_inst instances (bytes, 256-byte aligned
+ * start required).  Returns SGPM_EINVAL for an invalid descriptor. */
+sgpm_status sgpm_workspace_bytes(const sgpm_instance_desc* descs, int32_t n_inst, size_t* bytes);
+
+/* Create a context over a caller-owned device workspace of ws_bytes bytes.
+ * Builds the FP64 set-up tables on the host (nodes, weights, basis, Galerkin
+ * field coefficients, rate constants of the Appendix, Fermi-Dirac CDF
+ * tables) and uploads them.  *out receives the context (host memory owned
+ * by the library, released by sgpm_destroy). */
+sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* dev_workspace,
+                        size_t ws_bytes, void* hip_stream, sgpm_ctx** out);
+
+/* Fermi-Dirac initial particles at every node, projected onto the gPC modes
+ * (Sec. 4 uncertain initial condition); builds H^0 and records the moments
+ * at t = 0.  Resets the step counter and the counters.  Asynchronous. */
+sgpm_status sgpm_init_particles(sgpm_ctx* ctx);
+
+/* Advance every instance by n_steps steps of length dt_s (Sec. 4.1: Galerkin
+ * drift, then the collision step of Algorithm 2 against H^n; H^{n+1} and the
+ * moments at t^{n+1} are built by the same pass).  Asynchronous. */
+sgpm_status sgpm_step(sgpm_ctx* ctx, double dt_s, int64_t n_steps);
+
+/* Global step counter (the random streams are keyed by it). */
+sgpm_status sgpm_step_count(const sgpm_ctx* ctx, int64_t* steps);
+
+/* Number of recorded times of instance inst (1 right after init/set_state,
+ * plus one per step since). */
+sgpm_status sgpm_record_length(const sgpm_ctx* ctx, int32_t inst, int64_t* len);
+
+/* Moments for recorded times t_first .. t_first+count-1 (time index 0 is
+ * t = 0, index n is after n steps).  per_node[count][Q][4]: V_x, V_y (m/s),
+ * mean energy (eV), J_x = -e n(z_q) V_x (A/m).  agg[count][SGPM_N_AGG]:
+ * expectations and variances over z by the nodal quadrature (Sec. 4.2) and
+ * Monte Carlo standard errors by batch means over particle batches.
+ * Either output may be NULL.  Synchronises the stream. */
+enum {
+    SGPM_AGG_E_VX = 0, SGPM_AGG_VAR_VX, SGPM_AGG_E_JX, SGPM_AGG_VAR_JX, SGPM_AGG_E_EN,
+    SGPM_AGG_VAR_EN, SGPM_AGG_SE_E_VX, SGPM_AGG_SE_VAR_VX, SGPM_AGG_SE_E_JX,
+    SGPM_AGG_SE_VAR_JX, SGPM_AGG_SE_E_EN, SGPM_AGG_SE_VAR_EN, SGPM_N_AGG
+};
+sgpm_status sgpm_moments(sgpm_ctx* ctx, int32_t inst, int64_t t_first, int64_t count,
+                         double* per_node, double* agg);
+
+/* Reconstructed energy distribution (Sec. 4.1 eq. f_gPC, binned in energy):
+ * nodes[Q][nbins] = fraction of particles whose energy at node q lies in bin
+ * b, per eV; modes[P][nbins] = sum_q w_q Psi_h(z_q) nodes[q][b].  Bins split
+ * [emin, emax) uniformly.  Either output may be NULL.  Synchronises. */
+sgpm_status sgpm_reconstruct_f(sgpm_ctx* ctx, int32_t inst, int32_t nbins, double emin_eV,
+                               double emax_eV, double* nodes, double* modes);
+
+/* Energy distribution of the particles reconstructed at arbitrary points z
+ * (k_i(z) = sum_h k_h Psi_h(z)); z[n_z][dim_z], out[n_z][nbins].  Positive
+ * by construction.  Synchronises. */
+sgpm_status sgpm_reconstruct_f_at(sgpm_ctx* ctx, int32_t inst, int32_t n_z, const double* z,
+                                  int32_t nbins, double emin_eV, double emax_eV, double* out);
+
+/* Copy the coefficients in or out (host FP64 arrays kx[P][N] then ky[P][N]
+ * in one buffer of 2*P*N doubles).  set_state rebuilds the histogram of the
+ * given state, records it as time index 0 and sets the step counter (the
+ * random streams depend on it).  Both synchronise. */
+sgpm_status sgpm_set_state(sgpm_ctx* ctx, int32_t inst, const double* khat, int64_t step);
+sgpm_status sgpm_get_state(sgpm_ctx* ctx, int32_t inst, double* khat);
+
+/* Current histogram H^n (uint32 [Q][nk][nk]) and per-node max (uint32 [Q]).
+ * Either may be NULL.  Synchronises. */
+sgpm_status sgpm_get_histogram(sgpm_ctx* ctx, int32_t inst, uint32_t* H, uint32_t* Hmax);
+
+/* Counters, uint64 [SGPM_N_COUNTERS].  Synchronises. */
+sgpm_status sgpm_counters(sgpm_ctx* ctx, int32_t inst, uint64_t* out);
+
+/* Sizes of instance inst: P modes, Q nodes. */
+sgpm_status sgpm_sizes(const sgpm_ctx* ctx, int32_t inst, int32_t* P, int32_t* Q);
+
+/* Host copies of the set-up tables of instance inst (any may be NULL):
+ * z[Q][2], w[Q], psi[Q][P], ehat[P], eps0[Q], width_m[Q], field[Q],
+ * density_m2[Q]. */
+sgpm_status sgpm_tables(const sgpm_ctx* ctx, int32_t inst, double* z, double* w, double* psi,
+                        double* ehat, double* eps0, double* width_m, double* field,
+                        double* density_m2);
+
+/* Launch shape: particles per workgroup chunk (multiple of 256) for the step
+ * kernel of instance inst; 0 restores the automatic choice.  The results do
+ * not depend on it except through the order of the FP64 moment sums. */
+sgpm_status sgpm_set_chunk(sgpm_ctx* ctx, int32_t inst, int32_t chunk);
+
+/* Average device time (ms) of the step kernel over the last sgpm_step call,
+ * measured with HIP events on the context's stream; 0 if none. */
+sgpm_status sgpm_last_step_ms(sgpm_ctx* ctx, double* ms_per_step);
+
+void sgpm_destroy(sgpm_ctx* ctx);
+const char* sgpm_last_error(const sgpm_ctx* ctx);
+const char* sgpm_status_string(sgpm_status s);
+
+/* Test hook: Philox4x32-10 over n counters on the device.  d_ctr[n][4],
+ * d_key[n][2], d_out[n][4] are device pointers; enqueued on hip_stream and
+ * synchronised.  Used to check the device generator against the published
+ * known answers. */
+sgpm_status sgpm_philox_device(const uint32_t* d_ctr, const uint32_t* d_key, uint32_t* d_out,
+                               int64_t n, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGPM_H */

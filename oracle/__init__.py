@@ -95,6 +95,7 @@ def lib():
         L.orc_edge_kappa_coef.restype = C.c_double
         L.orc_reconstruct_f.argtypes = [P, C.c_int, C.c_double, C.c_double, dp, dp]
         L.orc_reconstruct_f_at.argtypes = [P, dp, C.c_int, C.c_double, C.c_double, dp]
+        L.orc_init_particles.argtypes = [P, lp, C.c_long, dp, dp]
         L.orc_pauli_lookup.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_double]
         L.orc_pauli_lookup.restype = C.c_double
         L.orc_u52.argtypes = [C.c_uint32, C.c_uint32]
@@ -271,6 +272,14 @@ class OracleSim:
 
     def edge_angle(self, i: int, step: int, coll: int, kx: float, ky: float) -> float:
         return lib().orc_edge_angle(self._h, i, step, coll, kx, ky)
+
+    def init_particles(self, idx):
+        """Initial coefficients of the listed particles, [count][P] each."""
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        kx = np.zeros((len(idx), self.P)); ky = np.zeros((len(idx), self.P))
+        lib().orc_init_particles(self._h, idx.ctypes.data_as(C.POINTER(C.c_long)), len(idx),
+                                 _dp(kx), _dp(ky))
+        return kx, ky
 
     def pauli_lookup(self, q: int, kx: float, ky: float, dt: float) -> float:
         return lib().orc_pauli_lookup(self._h, q, kx, ky, dt)

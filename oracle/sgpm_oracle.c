@@ -724,24 +724,36 @@ void orc_moments(const orc_sim *s, double *out)
 /* by all nodes (the quantile map is smooth in z), then the nodal quadrature */
 /* projection onto the gPC modes.                                            */
 /* ------------------------------------------------------------------------ */
+static void init_one(const orc_sim *s, long i, double *chx, double *chy)
+{
+    double nx[ORC_QMAX], ny[ORC_QMAX];
+    uint32_t r[4];
+    draw(s, (uint32_t)i, 0xFFFFFFFFu, 0, PUR_INIT, r);
+    uint64_t m = u52_int(r[0], r[1]);
+    double theta = 2.0 * PI_D * orc_u52(r[2], r[3]);
+    for (int q = 0; q < s->Q; ++q) {
+        double eps = fd_inverse_cdf_m(s, q, m);
+        double e0 = s->eps0[q];
+        double kabs = sqrt((eps - e0) * (eps + e0));
+        nx[q] = kabs * cos(theta);
+        ny[q] = kabs * sin(theta);
+    }
+    project(s, nx, ny, chx, chy);
+}
+
+/* initial coefficients of the listed particles: out[count][P] */
+void orc_init_particles(const orc_sim *s, const long *idx, long count, double *kx, double *ky)
+{
+    for (long t = 0; t < count; ++t) init_one(s, idx[t], kx + t * s->P, ky + t * s->P);
+}
+
 void orc_init(orc_sim *s)
 {
-    int Q = s->Q, P = s->P;
+    int P = s->P;
     size_t N = (size_t)s->p.n_particles;
-    double nx[ORC_QMAX], ny[ORC_QMAX], chx[ORC_PMAX], chy[ORC_PMAX];
+    double chx[ORC_PMAX], chy[ORC_PMAX];
     for (size_t i = 0; i < N; ++i) {
-        uint32_t r[4];
-        draw(s, (uint32_t)i, 0xFFFFFFFFu, 0, PUR_INIT, r);
-        uint64_t m = u52_int(r[0], r[1]);
-        double theta = 2.0 * PI_D * orc_u52(r[2], r[3]);
-        for (int q = 0; q < Q; ++q) {
-            double eps = fd_inverse_cdf_m(s, q, m);
-            double e0 = s->eps0[q];
-            double kabs = sqrt((eps - e0) * (eps + e0));
-            nx[q] = kabs * cos(theta);
-            ny[q] = kabs * sin(theta);
-        }
-        project(s, nx, ny, chx, chy);
+        init_one(s, (long)i, chx, chy);
         for (int h = 0; h < P; ++h) { s->kx[h * N + i] = chx[h]; s->ky[h * N + i] = chy[h]; }
     }
     s->step = 0;

@@ -1,0 +1,789 @@
+// C-ABI of the sG-PM library: context management over a caller-owned device
+// workspace, set-up tables, launches of the gfx950 kernels and the host-side
+// finalisation of the moment record (expectations and variances over z by
+// the nodal quadrature, Sec. 4.2; Monte Carlo errors by batch means).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sgpm_internal.h"
+
+using namespace sgpm;
+
+namespace {
+
+constexpr double kECharge = 1.602176634e-19;
+constexpr int kMaxBins = 4096;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Instance {
+    sgpm_instance_desc d;
+    HostTables t;
+    int P = 1, Q = 1, nk = 0;
+    int64_t n = 0;
+    bool fp32 = false;
+    int64_t chunk = 256;
+    int nwg = 1, nb = 1;
+    int win = 0, win_r0 = 0, win_l0 = 0, hwin_words = 0;
+    int64_t hstride = 0;       // words per histogram buffer (padded)
+    int64_t step = 0;          // global step counter (random streams)
+    int64_t rec_base = 0;      // step counter of record index 0
+    bool initialised = false;
+    // device pointers
+    void* kx = nullptr;
+    void* ky = nullptr;
+    uint32_t* H = nullptr;     // [3][hstride]
+    uint32_t* Hmax = nullptr;  // [3][64]
+    double* partial = nullptr; // [nwg_max][Q][3]
+    double* record = nullptr;  // [max_steps+1][NB][Q][3]
+    uint32_t* done = nullptr;
+    unsigned long long* counters = nullptr;
+    unsigned long long* bins = nullptr;  // [max(Q,1)][kMaxBins]
+    double* zpsi = nullptr;    // [P] basis at a point + eps0 (reconstruction at z)
+    // tables
+    double* d_psi = nullptr; double* d_wpsi = nullptr; double* d_eps0 = nullptr;
+    double* d_eps0sq = nullptr; double* d_cedge = nullptr; double* d_vfield = nullptr;
+    double* d_ecos = nullptr;
+    float* f_psi = nullptr; float* f_wpsi = nullptr; float* f_eps0 = nullptr;
+    float* f_eps0sq = nullptr; float* f_cedge = nullptr; float* f_vfield = nullptr;
+    float* f_ecos = nullptr;
+    double* d_cdf_lo = nullptr; double* d_cdf_hi = nullptr; double* d_gl = nullptr;
+};
+
+// Bytes of every device region of one instance, in carving order.
+struct Layout {
+    size_t total = 0;
+    size_t off[32];
+    int k = 0;
+    size_t add(size_t bytes) {
+        size_t o = total;
+        off[k++] = o;
+        total = align256(total + (bytes ? bytes : 1));
+        return o;
+    }
+};
+
+int64_t auto_chunk(int64_t n) {
+    int64_t c = (n + 511) / 512;
+    c = (c + kBlock - 1) / kBlock * kBlock;
+    if (c < kBlock) c = kBlock;
+    if (c > 16384) c = 16384;
+    return c;
+}
+
+void window_for(int Q, int nk, int* win, int* r0, int* l0, int* words) {
+    int w = (int)std::floor(std::sqrt((double)kLdsHistBytes / (2.0 * Q)));
+    w &= ~1;
+    if (w > nk) w = nk & ~1;
+    if (w < 2) w = 2;
+    *win = w;
+    *r0 = (nk - w) / 2;
+    *l0 = (nk - w) / 2;
+    *words = (Q * w * w + 1) / 2;
+}
+
+Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
+    Layout L;
+    const size_t s = d.precision == SGPM_FP32 ? 4 : 8;
+    const size_t P = t.P, Q = t.Q, n = (size_t)d.n_particles;
+    const size_t hstride = ((size_t)Q * d.nk * d.nk + 63) / 64 * 64;
+    const size_t nwg_max = (n + kBlock - 1) / kBlock;
+    L.add(P * n * s);                                  // 0 kx
+    L.add(P * n * s);                                  // 1 ky
+    L.add(3 * hstride * 4);                            // 2 H
+    L.add(3 * 64 * 4 * ((Q + 63) / 64));               // 3 Hmax
+    L.add(nwg_max * Q * 3 * 8);                        // 4 partial
+    L.add(((size_t)d.max_steps + 1) * kNumBatches * Q * 3 * 8);  // 5 record
+    L.add(64);                                         // 6 done
+    L.add(SGPM_N_COUNTERS * 8);                        // 7 counters
+    L.add((size_t)Q * kMaxBins * 8);                   // 8 bins
+    L.add((P + 2) * 8);                                // 9 zpsi
+    L.add(Q * P * 8); L.add(Q * P * 8);                // 10,11 d_psi, d_wpsi
+    L.add(Q * 8); L.add(Q * 8); L.add(Q * 8); L.add(Q * 8);  // 12-15 eps0 eps0sq cedge vfield
+    L.add(32 * 8);                                     // 16 ecos
+    L.add(Q * P * 4); L.add(Q * P * 4);                // 17,18 f_psi f_wpsi
+    L.add(Q * 4); L.add(Q * 4); L.add(Q * 4); L.add(Q * 4);  // 19-22
+    L.add(32 * 4);                                     // 23 f_ecos
+    L.add(Q * (size_t)(t.cdf_np + 1) * 8);             // 24 cdf_lo
+    L.add(Q * (size_t)(t.cdf_np + 1) * 8);             // 25 cdf_hi
+    L.add(20 * 8);                                     // 26 gl
+    return L;
+}
+
+}  // namespace
+
+struct sgpm_ctx {
+    std::vector<Instance> inst;
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool poisoned = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+    int64_t timed_steps = 0;
+};
+
+namespace {
+
+sgpm_status fail(sgpm_ctx* c, sgpm_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+sgpm_status dev_fail(sgpm_ctx* c, hipError_t e, const char* where) {
+    c->poisoned = true;
+    c->err = std::string(where) + ": " + hipGetErrorString(e);
+    return SGPM_EDEVICE;
+}
+
+#define HIPCHK(ctx, call)                                     \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return dev_fail(ctx, e_, #call);\
+    } while (0)
+
+sgpm_status check_ctx(sgpm_ctx* c, int32_t inst) {
+    if (!c) return SGPM_EINVAL;
+    if (c->poisoned) return fail(c, SGPM_ESTATE, "context poisoned by an earlier device error");
+    if (inst < 0 || inst >= (int32_t)c->inst.size()) return fail(c, SGPM_EINVAL, "instance index out of range");
+    return SGPM_OK;
+}
+
+template <typename T>
+void fill_tab(const Instance& I, StepArgs<T>& a) {
+    if constexpr (sizeof(T) == 8) {
+        a.tab = DevTab<T>{I.d_psi, I.d_wpsi, I.d_eps0, I.d_eps0sq, I.d_cedge, I.d_vfield, I.d_ecos};
+    } else {
+        a.tab = DevTab<T>{I.f_psi, I.f_wpsi, I.f_eps0, I.f_eps0sq, I.f_cedge, I.f_vfield, I.f_ecos};
+    }
+}
+
+template <typename T>
+StepArgs<T> make_args(const Instance& I, double dt, bool drift, bool collide, int64_t step,
+                      int64_t rec_index) {
+    StepArgs<T> a;
+    std::memset(&a, 0, sizeof(a));
+    const HostTables& t = I.t;
+    const sgpm_instance_desc& d = I.d;
+    a.kx = static_cast<T*>(I.kx);
+    a.ky = static_cast<T*>(I.ky);
+    a.n = I.n;
+    a.P = I.P;
+    a.Q = I.Q;
+    fill_tab<T>(I, a);
+    a.drift_mask = 0;
+    for (int h = 0; h < I.P; ++h) {
+        const double v = (t.v_f * dt) * t.ehat[h];
+        a.drift[h] = (T)v;
+        if (v != 0.0 && h < 32) a.drift_mask |= 1u << h;
+    }
+    a.dt = (T)dt;
+    a.c_ac = (T)(d.rate_scale[0] * t.c_ac);
+    a.c_om = (T)(d.rate_scale[1] * t.c_o * (t.n_o + 1.0));
+    a.c_op = (T)(d.rate_scale[2] * t.c_o * t.n_o);
+    a.c_km = (T)(d.rate_scale[3] * t.c_k * (t.n_k + 1.0));
+    a.c_kp = (T)(d.rate_scale[4] * t.c_k * t.n_k);
+    a.hw_o = (T)t.hw_o;
+    a.hw_k = (T)t.hw_k;
+    a.edge_kap = (T)t.edge_kap;
+    a.alpha1 = (T)(1.0 + d.alpha);
+    a.v_f = (T)t.v_f;
+    // bound of max_q S_q as a function of the largest nodal energy
+    double cemax = 0.0, e0min = t.eps0[0];
+    for (int q = 0; q < I.Q; ++q) {
+        cemax = std::fmax(cemax, t.cedge[q]);
+        e0min = std::fmin(e0min, t.eps0[q]);
+    }
+    a.b_ac = (T)(d.rate_scale[0] * t.c_ac);
+    a.b_om = (T)(d.rate_scale[1] * t.c_o * (t.n_o + 1.0));
+    a.b_op = (T)(d.rate_scale[2] * t.c_o * t.n_o);
+    a.b_km = (T)(d.rate_scale[3] * t.c_k * (t.n_k + 1.0));
+    a.b_kp = (T)(d.rate_scale[4] * t.c_k * t.n_k);
+    a.b_edge = (T)(d.rate_scale[5] * cemax * 2.0 * 3.14159265358979323846);
+    a.b_thr_o = (T)(t.hw_o + e0min);
+    a.b_thr_k = (T)(t.hw_k + e0min);
+    a.b_margin = (T)(sizeof(T) == 8 ? 1.0 + 1e-9 : 1.0 + 1e-3);
+    if (sizeof(T) == 4) {
+        // float rounding of the thresholds must not lift them above the exact ones
+        a.b_thr_o = (T)((double)a.b_thr_o * (1.0 - 1e-6));
+        a.b_thr_k = (T)((double)a.b_thr_k * (1.0 - 1e-6));
+    }
+    a.lk = (T)d.lk_eV;
+    a.dk = (T)(2.0 * d.lk_eV / d.nk);
+    a.inv_dk = (T)(1.0 / (2.0 * d.lk_eV / d.nk));
+    a.nk = d.nk;
+    a.pauli = d.pauli;
+    a.final_state = d.final_state;
+    a.c_max = d.c_max;
+    a.seed_lo = (uint32_t)(d.seed & 0xFFFFFFFFu);
+    a.seed_hi = (uint32_t)(d.seed >> 32);
+    a.instance = d.instance_id;
+    a.step = (uint32_t)step;
+    const int rd = (int)(step % 3), ac = (int)((step + 1) % 3), cl = (int)((step + 2) % 3);
+    // for a rebuild (no collisions) the pass accumulates H of the current step
+    const int acc_buf = collide || drift ? ac : rd;
+    const int clr_buf = collide || drift ? cl : ac;
+    a.h_read = I.H + (size_t)rd * I.hstride;
+    a.hmax_read = I.Hmax + (size_t)rd * 64 * ((I.Q + 63) / 64);
+    a.h_acc = I.H + (size_t)acc_buf * I.hstride;
+    a.hmax_acc = I.Hmax + (size_t)acc_buf * 64 * ((I.Q + 63) / 64);
+    a.h_clr = I.H + (size_t)clr_buf * I.hstride;
+    a.hmax_clr = I.Hmax + (size_t)clr_buf * 64 * ((I.Q + 63) / 64);
+    a.clear_vec4 = I.hstride / 4;
+    a.win = I.win;
+    a.win_r0 = I.win_r0;
+    a.win_l0 = I.win_l0;
+    a.hwin_words = I.hwin_words;
+    a.partial = I.partial;
+    a.record = I.record + (size_t)rec_index * I.nb * I.Q * 3;
+    a.done = I.done;
+    a.nb = I.nb;
+    a.counters = I.counters;
+    a.chunk = I.chunk;
+    a.nwg = I.nwg;
+    a.do_drift = drift ? 1 : 0;
+    a.do_collide = collide ? 1 : 0;
+    return a;
+}
+
+int pmax_bucket(int P) { return P; }
+
+sgpm_status launch_pass(sgpm_ctx* c, Instance& I, double dt, bool drift, bool collide,
+                        int64_t step, int64_t rec_index) {
+    int e;
+    if (I.fp32) e = launch_step_f32(make_args<float>(I, dt, drift, collide, step, rec_index),
+                                    pmax_bucket(I.P), c->stream);
+    else e = launch_step_f64(make_args<double>(I, dt, drift, collide, step, rec_index),
+                             pmax_bucket(I.P), c->stream);
+    if (e != 0) return dev_fail(c, (hipError_t)e, "step kernel launch");
+    return SGPM_OK;
+}
+
+void set_chunk(Instance& I, int64_t chunk) {
+    I.chunk = chunk > 0 ? chunk : auto_chunk(I.n);
+    I.nwg = (int)((I.n + I.chunk - 1) / I.chunk);
+    I.nb = I.nwg < kNumBatches ? I.nwg : kNumBatches;
+}
+
+// rebuild H and record index 0 for the current state
+sgpm_status rebuild(sgpm_ctx* c, Instance& I) {
+    const size_t hm = (size_t)64 * ((I.Q + 63) / 64) * 4;
+    HIPCHK(c, hipMemsetAsync(I.H, 0, (size_t)3 * I.hstride * 4, c->stream));
+    HIPCHK(c, hipMemsetAsync(I.Hmax, 0, 3 * hm, c->stream));
+    HIPCHK(c, hipMemsetAsync(I.counters, 0, SGPM_N_COUNTERS * 8, c->stream));
+    HIPCHK(c, hipMemsetAsync(I.done, 0, 64, c->stream));
+    I.rec_base = I.step;
+    return launch_pass(c, I, 0.0, false, false, I.step, 0);
+}
+
+}  // namespace
+
+extern "C" {
+
+void sgpm_default_desc(sgpm_instance_desc* d) {
+    if (!d) return;
+    std::memset(d, 0, sizeof(*d));
+    d->dim_z = 0; d->degree = 0; d->nodes_1d = 1; d->precision = SGPM_FP64;
+    d->n_particles = 10000;
+    d->gap_mode = 0; d->gap_dim = -1; d->gap0 = 0.2; d->gap_rel = 0.0;
+    d->field_dim = -1; d->field0 = 1.0e6; d->field_rel = 0.0;
+    d->fermi_eV = 0.4; d->temp_K = 300.0; d->alpha = 0.1;
+    d->nk = 240; d->lk_eV = 5.0; d->pauli = 1; d->final_state = 0;
+    for (int m = 0; m < 6; ++m) d->rate_scale[m] = 1.0;
+    d->seed = 1; d->instance_id = 0; d->c_max = 32; d->max_steps = 1000;
+}
+
+const char* sgpm_status_string(sgpm_status s) {
+    switch (s) {
+    case SGPM_OK: return "ok";
+    case SGPM_EINVAL: return "invalid argument";
+    case SGPM_ENOMEM: return "out of host memory";
+    case SGPM_EWORKSPACE: return "workspace missing or too small";
+    case SGPM_EDEVICE: return "device error";
+    case SGPM_ESTATE: return "invalid state";
+    case SGPM_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+sgpm_status sgpm_workspace_bytes(const sgpm_instance_desc* descs, int32_t n_inst, size_t* bytes) {
+    if (!descs || n_inst < 1 || !bytes) return SGPM_EINVAL;
+    size_t total = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        HostTables t;
+        const char* why = build_tables(descs[k], t);
+        if (why[0]) return SGPM_EINVAL;
+        total += layout_of(descs[k], t).total;
+    }
+    *bytes = total;
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* ws, size_t ws_bytes,
+                        void* stream, sgpm_ctx** out) {
+    if (!out) return SGPM_EINVAL;
+    *out = nullptr;
+    if (!descs || n_inst < 1) return SGPM_EINVAL;
+    sgpm_ctx* c = new (std::nothrow) sgpm_ctx();
+    if (!c) return SGPM_ENOMEM;
+    c->stream = (hipStream_t)stream;
+    try {
+        c->inst.resize(n_inst);
+    } catch (...) {
+        delete c;
+        return SGPM_ENOMEM;
+    }
+    size_t need = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        Instance& I = c->inst[k];
+        I.d = descs[k];
+        const char* why = build_tables(I.d, I.t);
+        if (why[0]) {
+            fprintf(stderr, "sgpm_create: instance %d rejected: %s\n", k, why);
+            delete c;
+            return SGPM_EINVAL;
+        }
+        need += layout_of(I.d, I.t).total;
+    }
+    if (!ws || ((uintptr_t)ws & 255) != 0 || ws_bytes < need) {
+        fprintf(stderr, "sgpm_create: workspace %p of %zu bytes, need %zu (256-byte aligned)\n", ws,
+                ws_bytes, need);
+        delete c;
+        return SGPM_EWORKSPACE;
+    }
+    unsigned char* base = static_cast<unsigned char*>(ws);
+    for (int k = 0; k < n_inst; ++k) {
+        Instance& I = c->inst[k];
+        const HostTables& t = I.t;
+        Layout L = layout_of(I.d, t);
+        auto at = [&](int r) { return base + L.off[r]; };
+        I.P = t.P; I.Q = t.Q; I.nk = I.d.nk; I.n = I.d.n_particles;
+        I.fp32 = I.d.precision == SGPM_FP32;
+        I.hstride = ((int64_t)I.Q * I.nk * I.nk + 63) / 64 * 64;
+        I.kx = at(0); I.ky = at(1);
+        I.H = (uint32_t*)at(2); I.Hmax = (uint32_t*)at(3);
+        I.partial = (double*)at(4); I.record = (double*)at(5);
+        I.done = (uint32_t*)at(6); I.counters = (unsigned long long*)at(7);
+        I.bins = (unsigned long long*)at(8); I.zpsi = (double*)at(9);
+        I.d_psi = (double*)at(10); I.d_wpsi = (double*)at(11);
+        I.d_eps0 = (double*)at(12); I.d_eps0sq = (double*)at(13);
+        I.d_cedge = (double*)at(14); I.d_vfield = (double*)at(15); I.d_ecos = (double*)at(16);
+        I.f_psi = (float*)at(17); I.f_wpsi = (float*)at(18);
+        I.f_eps0 = (float*)at(19); I.f_eps0sq = (float*)at(20);
+        I.f_cedge = (float*)at(21); I.f_vfield = (float*)at(22); I.f_ecos = (float*)at(23);
+        I.d_cdf_lo = (double*)at(24); I.d_cdf_hi = (double*)at(25); I.d_gl = (double*)at(26);
+        base += L.total;
+        set_chunk(I, 0);
+        window_for(I.Q, I.nk, &I.win, &I.win_r0, &I.win_l0, &I.hwin_words);
+
+        // upload the tables (FP64 masters and FP32 copies)
+        const int Q = I.Q, P = I.P;
+        std::vector<double> eps0sq(Q), cedge(Q), vfield(Q), ecos(32, 0.0);
+        for (int q = 0; q < Q; ++q) {
+            eps0sq[q] = t.eps0[q] * t.eps0[q];
+            cedge[q] = I.d.rate_scale[5] * t.cedge[q];
+            vfield[q] = t.v_f * t.field[q];
+        }
+        for (int j = 0; j <= kEdgePts / 2; ++j) ecos[j] = t.edge_cos[j];
+        auto up = [&](void* dst, const void* src, size_t b) {
+            return hipMemcpyAsync(dst, src, b, hipMemcpyHostToDevice, c->stream);
+        };
+        auto tof = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+        std::vector<float> fpsi = tof(t.psi), fwpsi = tof(t.wpsi), feps0 = tof(t.eps0),
+                           feps0sq = tof(eps0sq), fcedge = tof(cedge), fvfield = tof(vfield),
+                           fecos = tof(ecos);
+        double gl[20];
+        for (int k2 = 0; k2 < 10; ++k2) { gl[k2] = t.gl10_x[k2]; gl[10 + k2] = t.gl10_w[k2]; }
+        hipError_t e = hipSuccess;
+        if (e == hipSuccess) e = up(I.d_psi, t.psi.data(), Q * P * 8);
+        if (e == hipSuccess) e = up(I.d_wpsi, t.wpsi.data(), Q * P * 8);
+        if (e == hipSuccess) e = up(I.d_eps0, t.eps0.data(), Q * 8);
+        if (e == hipSuccess) e = up(I.d_eps0sq, eps0sq.data(), Q * 8);
+        if (e == hipSuccess) e = up(I.d_cedge, cedge.data(), Q * 8);
+        if (e == hipSuccess) e = up(I.d_vfield, vfield.data(), Q * 8);
+        if (e == hipSuccess) e = up(I.d_ecos, ecos.data(), 32 * 8);
+        if (e == hipSuccess) e = up(I.f_psi, fpsi.data(), Q * P * 4);
+        if (e == hipSuccess) e = up(I.f_wpsi, fwpsi.data(), Q * P * 4);
+        if (e == hipSuccess) e = up(I.f_eps0, feps0.data(), Q * 4);
+        if (e == hipSuccess) e = up(I.f_eps0sq, feps0sq.data(), Q * 4);
+        if (e == hipSuccess) e = up(I.f_cedge, fcedge.data(), Q * 4);
+        if (e == hipSuccess) e = up(I.f_vfield, fvfield.data(), Q * 4);
+        if (e == hipSuccess) e = up(I.f_ecos, fecos.data(), 32 * 4);
+        if (e == hipSuccess) e = up(I.d_cdf_lo, t.cdf_lo.data(), t.cdf_lo.size() * 8);
+        if (e == hipSuccess) e = up(I.d_cdf_hi, t.cdf_hi.data(), t.cdf_hi.size() * 8);
+        if (e == hipSuccess) e = up(I.d_gl, gl, 20 * 8);
+        if (e == hipSuccess) e = hipMemsetAsync(I.done, 0, 64, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(I.counters, 0, SGPM_N_COUNTERS * 8, c->stream);
+        // host vectors above are released at scope end: wait for the copies
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            fprintf(stderr, "sgpm_create: %s\n", hipGetErrorString(e));
+            delete c;
+            return SGPM_EDEVICE;
+        }
+    }
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        delete c;
+        return SGPM_EDEVICE;
+    }
+    *out = c;
+    return SGPM_OK;
+}
+
+void sgpm_destroy(sgpm_ctx* c) {
+    if (!c) return;
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+}
+
+const char* sgpm_last_error(const sgpm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+sgpm_status sgpm_sizes(const sgpm_ctx* c, int32_t inst, int32_t* P, int32_t* Q) {
+    if (!c || inst < 0 || inst >= (int32_t)c->inst.size()) return SGPM_EINVAL;
+    if (P) *P = c->inst[inst].P;
+    if (Q) *Q = c->inst[inst].Q;
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_tables(const sgpm_ctx* c, int32_t inst, double* z, double* w, double* psi,
+                        double* ehat, double* eps0, double* width, double* field, double* density) {
+    if (!c || inst < 0 || inst >= (int32_t)c->inst.size()) return SGPM_EINVAL;
+    const HostTables& t = c->inst[inst].t;
+    auto cp = [](double* dst, const std::vector<double>& v) {
+        if (dst) std::memcpy(dst, v.data(), v.size() * sizeof(double));
+    };
+    cp(z, t.z); cp(w, t.w); cp(psi, t.psi); cp(ehat, t.ehat); cp(eps0, t.eps0);
+    cp(width, t.width); cp(field, t.field); cp(density, t.density);
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_set_chunk(sgpm_ctx* c, int32_t inst, int32_t chunk) {
+    sgpm_status s = check_ctx(c, inst);
+    if (s) return s;
+    if (chunk < 0 || chunk % kBlock != 0 || chunk > 65535)
+        return fail(c, SGPM_EINVAL, "chunk must be a multiple of 256 below 65536 (0 = automatic)");
+    Instance& I = c->inst[inst];
+    if (I.initialised && I.step != I.rec_base)
+        return fail(c, SGPM_ESTATE, "the launch shape can only change right after init/set_state");
+    set_chunk(I, chunk);
+    if (I.initialised) return rebuild(c, I);
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_init_particles(sgpm_ctx* c) {
+    if (!c) return SGPM_EINVAL;
+    if (c->poisoned) return fail(c, SGPM_ESTATE, "context poisoned");
+    for (Instance& I : c->inst) {
+        InitArgs a;
+        std::memset(&a, 0, sizeof(a));
+        if (I.fp32) { a.kx32 = (float*)I.kx; a.ky32 = (float*)I.ky; }
+        else { a.kx64 = (double*)I.kx; a.ky64 = (double*)I.ky; }
+        a.n = I.n; a.P = I.P; a.Q = I.Q;
+        a.wpsi = I.d_wpsi; a.eps0 = I.d_eps0; a.cdf_lo = I.d_cdf_lo; a.cdf_hi = I.d_cdf_hi;
+        a.gl = I.d_gl; a.cdf_np = I.t.cdf_np; a.cdf_h = I.t.cdf_h;
+        a.mu = I.d.fermi_eV; a.kT = I.t.kT;
+        a.seed_lo = (uint32_t)(I.d.seed & 0xFFFFFFFFu);
+        a.seed_hi = (uint32_t)(I.d.seed >> 32);
+        a.instance = I.d.instance_id;
+        int e = launch_init(a, c->stream);
+        if (e) return dev_fail(c, (hipError_t)e, "init kernel launch");
+        I.step = 0;
+        sgpm_status s = rebuild(c, I);
+        if (s) return s;
+        I.initialised = true;
+    }
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_step(sgpm_ctx* c, double dt, int64_t n_steps) {
+    if (!c) return SGPM_EINVAL;
+    if (c->poisoned) return fail(c, SGPM_ESTATE, "context poisoned");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(c, SGPM_EINVAL, "dt must be positive and finite");
+    if (n_steps < 0) return fail(c, SGPM_EINVAL, "n_steps must be >= 0");
+    for (Instance& I : c->inst) {
+        if (!I.initialised) return fail(c, SGPM_ESTATE, "call sgpm_init_particles or sgpm_set_state first");
+        if (I.step - I.rec_base + n_steps > I.d.max_steps)
+            return fail(c, SGPM_EINVAL, "n_steps exceeds the moment record capacity (max_steps)");
+        if (I.step + n_steps >= (int64_t)0xFFFFFFFFll)
+            return fail(c, SGPM_EINVAL, "step counter would reach the initialisation stream");
+    }
+    if (n_steps == 0) return SGPM_OK;
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    for (int64_t k = 0; k < n_steps; ++k) {
+        for (Instance& I : c->inst) {
+            sgpm_status s = launch_pass(c, I, dt, true, true, I.step, I.step - I.rec_base + 1);
+            if (s) return s;
+            I.step += 1;
+        }
+    }
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    c->timed = true;
+    c->timed_steps = n_steps;
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_last_step_ms(sgpm_ctx* c, double* ms) {
+    if (!c || !ms) return SGPM_EINVAL;
+    *ms = 0.0;
+    if (!c->timed || c->timed_steps <= 0) return SGPM_OK;
+    HIPCHK(c, hipEventSynchronize(c->ev1));
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, c->ev0, c->ev1));
+    *ms = (double)t / (double)c->timed_steps;
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_step_count(const sgpm_ctx* c, int64_t* steps) {
+    if (!c || !steps || c->inst.empty()) return SGPM_EINVAL;
+    *steps = c->inst[0].step;
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_record_length(const sgpm_ctx* c, int32_t inst, int64_t* len) {
+    if (!c || !len || inst < 0 || inst >= (int32_t)c->inst.size()) return SGPM_EINVAL;
+    const Instance& I = c->inst[inst];
+    *len = I.initialised ? I.step - I.rec_base + 1 : 0;
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_moments(sgpm_ctx* c, int32_t inst, int64_t first, int64_t count, double* per_node,
+                         double* agg) {
+    sgpm_status s = check_ctx(c, inst);
+    if (s) return s;
+    Instance& I = c->inst[inst];
+    if (!I.initialised) return fail(c, SGPM_ESTATE, "no particles yet");
+    const int64_t avail = I.step - I.rec_base + 1;
+    if (first < 0 || count < 0 || first + count > avail)
+        return fail(c, SGPM_EINVAL, "requested times outside the record");
+    if (count == 0) return SGPM_OK;
+    const int Q = I.Q, NB = I.nb;
+    const size_t per = (size_t)NB * Q * 3;
+    std::vector<double> rec;
+    try { rec.resize(per * count); } catch (...) { return SGPM_ENOMEM; }
+    HIPCHK(c, hipMemcpyAsync(rec.data(), I.record + per * first, per * count * 8,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // particles per batch: workgroup w belongs to batch w mod NB
+    std::vector<double> bn(NB, 0.0);
+    for (int w = 0; w < I.nwg; ++w) {
+        int64_t b0 = (int64_t)w * I.chunk, b1 = std::min<int64_t>(I.n, b0 + I.chunk);
+        bn[w % NB] += (double)(b1 - b0);
+    }
+    const double N = (double)I.n;
+    const std::vector<double>& wq = I.t.w;
+    const std::vector<double>& dens = I.t.density;
+    // aggregate of per-node values X_q: expectation and variance over z
+    auto ez = [&](const double* x) { double m = 0; for (int q = 0; q < Q; ++q) m += wq[q] * x[q]; return m; };
+    auto varz = [&](const double* x, double m) {
+        double v = 0; for (int q = 0; q < Q; ++q) v += wq[q] * (x[q] - m) * (x[q] - m); return v; };
+    std::vector<double> vx(Q), vy(Q), en(Q), jx(Q);
+    for (int64_t t = 0; t < count; ++t) {
+        const double* r = rec.data() + per * t;
+        for (int q = 0; q < Q; ++q) {
+            double sx = 0, sy = 0, se = 0;
+            for (int b = 0; b < NB; ++b) {
+                sx += r[((size_t)b * Q + q) * 3 + 0];
+                sy += r[((size_t)b * Q + q) * 3 + 1];
+                se += r[((size_t)b * Q + q) * 3 + 2];
+            }
+            vx[q] = sx / N; vy[q] = sy / N; en[q] = se / N;
+            jx[q] = -kECharge * dens[q] * vx[q];
+            if (per_node) {
+                double* o = per_node + ((size_t)t * Q + q) * 4;
+                o[0] = vx[q]; o[1] = vy[q]; o[2] = en[q]; o[3] = jx[q];
+            }
+        }
+        if (!agg) continue;
+        double* g = agg + (size_t)t * SGPM_N_AGG;
+        g[SGPM_AGG_E_VX] = ez(vx.data()); g[SGPM_AGG_VAR_VX] = varz(vx.data(), g[SGPM_AGG_E_VX]);
+        g[SGPM_AGG_E_JX] = ez(jx.data()); g[SGPM_AGG_VAR_JX] = varz(jx.data(), g[SGPM_AGG_E_JX]);
+        g[SGPM_AGG_E_EN] = ez(en.data()); g[SGPM_AGG_VAR_EN] = varz(en.data(), g[SGPM_AGG_E_EN]);
+        // batch means: the same aggregates from each batch's particles
+        double acc[6] = {0, 0, 0, 0, 0, 0}, acc2[6] = {0, 0, 0, 0, 0, 0};
+        int used = 0;
+        std::vector<double> bx(Q), bj(Q), be(Q);
+        for (int b = 0; b < NB; ++b) {
+            if (bn[b] <= 0) continue;
+            for (int q = 0; q < Q; ++q) {
+                bx[q] = r[((size_t)b * Q + q) * 3 + 0] / bn[b];
+                be[q] = r[((size_t)b * Q + q) * 3 + 2] / bn[b];
+                bj[q] = -kECharge * dens[q] * bx[q];
+            }
+            double v[6];
+            v[0] = ez(bx.data()); v[1] = varz(bx.data(), v[0]);
+            v[2] = ez(bj.data()); v[3] = varz(bj.data(), v[2]);
+            v[4] = ez(be.data()); v[5] = varz(be.data(), v[4]);
+            for (int k = 0; k < 6; ++k) { acc[k] += v[k]; acc2[k] += v[k] * v[k]; }
+            ++used;
+        }
+        for (int k = 0; k < 6; ++k) {
+            double se = 0.0;
+            if (used > 1) {
+                const double m = acc[k] / used;
+                const double var = std::fmax(acc2[k] / used - m * m, 0.0) * used / (used - 1.0);
+                se = std::sqrt(var / used);
+            }
+            g[SGPM_AGG_SE_E_VX + k] = se;
+        }
+    }
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_get_state(sgpm_ctx* c, int32_t inst, double* khat) {
+    sgpm_status s = check_ctx(c, inst);
+    if (s) return s;
+    if (!khat) return fail(c, SGPM_EINVAL, "null output");
+    Instance& I = c->inst[inst];
+    const size_t cnt = (size_t)I.P * I.n;
+    if (!I.fp32) {
+        HIPCHK(c, hipMemcpyAsync(khat, I.kx, cnt * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(khat + cnt, I.ky, cnt * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> tmp(2 * cnt);
+        HIPCHK(c, hipMemcpyAsync(tmp.data(), I.kx, cnt * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(tmp.data() + cnt, I.ky, cnt * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (size_t k = 0; k < 2 * cnt; ++k) khat[k] = (double)tmp[k];
+    }
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_set_state(sgpm_ctx* c, int32_t inst, const double* khat, int64_t step) {
+    sgpm_status s = check_ctx(c, inst);
+    if (s) return s;
+    if (!khat) return fail(c, SGPM_EINVAL, "null input");
+    if (step < 0 || step >= (int64_t)0xFFFFFFFFll) return fail(c, SGPM_EINVAL, "step out of range");
+    Instance& I = c->inst[inst];
+    const size_t cnt = (size_t)I.P * I.n;
+    for (size_t k = 0; k < 2 * cnt; ++k)
+        if (!std::isfinite(khat[k])) return fail(c, SGPM_EINVAL, "non-finite coefficient");
+    if (!I.fp32) {
+        HIPCHK(c, hipMemcpyAsync(I.kx, khat, cnt * 8, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(I.ky, khat + cnt, cnt * 8, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> tmp(2 * cnt);
+        for (size_t k = 0; k < 2 * cnt; ++k) tmp[k] = (float)khat[k];
+        HIPCHK(c, hipMemcpyAsync(I.kx, tmp.data(), cnt * 4, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(I.ky, tmp.data() + cnt, cnt * 4, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    I.step = step;
+    s = rebuild(c, I);
+    if (s) return s;
+    I.initialised = true;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_get_histogram(sgpm_ctx* c, int32_t inst, uint32_t* H, uint32_t* Hmax) {
+    sgpm_status s = check_ctx(c, inst);
+    if (s) return s;
+    Instance& I = c->inst[inst];
+    if (!I.initialised) return fail(c, SGPM_ESTATE, "no particles yet");
+    const int rd = (int)(I.step % 3);
+    if (H)
+        HIPCHK(c, hipMemcpyAsync(H, I.H + (size_t)rd * I.hstride, (size_t)I.Q * I.nk * I.nk * 4,
+                                 hipMemcpyDeviceToHost, c->stream));
+    if (Hmax)
+        HIPCHK(c, hipMemcpyAsync(Hmax, I.Hmax + (size_t)rd * 64 * ((I.Q + 63) / 64), (size_t)I.Q * 4,
+                                 hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_counters(sgpm_ctx* c, int32_t inst, uint64_t* out) {
+    sgpm_status s = check_ctx(c, inst);
+    if (s) return s;
+    if (!out) return fail(c, SGPM_EINVAL, "null output");
+    HIPCHK(c, hipMemcpyAsync(out, c->inst[inst].counters, SGPM_N_COUNTERS * 8, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SGPM_OK;
+}
+
+static sgpm_status energy_hist(sgpm_ctx* c, Instance& I, int Q, const double* psi, const double* eps0,
+                               int nbins, double emin, double emax, std::vector<unsigned long long>& out) {
+    EnergyHistArgs a;
+    a.kx = I.kx; a.ky = I.ky; a.fp32 = I.fp32 ? 1 : 0; a.n = I.n; a.P = I.P; a.Q = Q;
+    a.psi = psi; a.eps0 = eps0; a.nbins = nbins; a.emin = emin; a.width = (emax - emin) / nbins;
+    a.bins = I.bins;
+    HIPCHK(c, hipMemsetAsync(I.bins, 0, (size_t)Q * nbins * 8, c->stream));
+    int e = launch_energy_hist(a, c->stream);
+    if (e) return dev_fail(c, (hipError_t)e, "energy histogram launch");
+    out.assign((size_t)Q * nbins, 0ull);
+    HIPCHK(c, hipMemcpyAsync(out.data(), I.bins, (size_t)Q * nbins * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_reconstruct_f(sgpm_ctx* c, int32_t inst, int32_t nbins, double emin, double emax,
+                               double* nodes, double* modes) {
+    sgpm_status s = check_ctx(c, inst);
+    if (s) return s;
+    if (nbins < 1 || nbins > kMaxBins || !(emax > emin)) return fail(c, SGPM_EINVAL, "bad bins");
+    Instance& I = c->inst[inst];
+    if (!I.initialised) return fail(c, SGPM_ESTATE, "no particles yet");
+    std::vector<unsigned long long> b;
+    s = energy_hist(c, I, I.Q, I.d_psi, I.d_eps0, nbins, emin, emax, b);
+    if (s) return s;
+    const double width = (emax - emin) / nbins, N = (double)I.n;
+    std::vector<double> F((size_t)I.Q * nbins);
+    for (size_t k = 0; k < F.size(); ++k) F[k] = (double)b[k] / (N * width);
+    if (nodes) std::memcpy(nodes, F.data(), F.size() * 8);
+    if (modes)
+        for (int h = 0; h < I.P; ++h)
+            for (int j = 0; j < nbins; ++j) {
+                double acc = 0;
+                for (int q = 0; q < I.Q; ++q) acc += I.t.wpsi[q * I.P + h] * F[(size_t)q * nbins + j];
+                modes[(size_t)h * nbins + j] = acc;
+            }
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_reconstruct_f_at(sgpm_ctx* c, int32_t inst, int32_t n_z, const double* z, int32_t nbins,
+                                  double emin, double emax, double* out) {
+    sgpm_status s = check_ctx(c, inst);
+    if (s) return s;
+    if (nbins < 1 || nbins > kMaxBins || !(emax > emin) || n_z < 0 || (n_z > 0 && (!z || !out)))
+        return fail(c, SGPM_EINVAL, "bad arguments");
+    Instance& I = c->inst[inst];
+    if (!I.initialised) return fail(c, SGPM_ESTATE, "no particles yet");
+    const int dz = I.t.dim_z;
+    const double hvf_eVm = 6.62607015e-34 / (2 * 3.14159265358979323846) * I.t.v_f / kECharge;
+    for (int k = 0; k < n_z; ++k) {
+        double zz[2] = {0.0, 0.0};
+        for (int j = 0; j < dz; ++j) zz[j] = z[(size_t)k * dz + j];
+        std::vector<double> host(I.P + 1);
+        eval_basis_all(dz, I.P, zz, host.data());
+        double zg = I.d.gap_dim >= 0 ? zz[I.d.gap_dim] : 0.0;
+        double g = I.d.gap0 * (1.0 + I.d.gap_rel * zg);
+        if (!(g > 0)) return fail(c, SGPM_EINVAL, "gap not positive at the requested z");
+        host[I.P] = I.d.gap_mode == 0 ? 0.5 * g : 3.14159265358979323846 * hvf_eVm / (g * 1e-9);
+        HIPCHK(c, hipMemcpyAsync(I.zpsi, host.data(), (I.P + 1) * 8, hipMemcpyHostToDevice, c->stream));
+        std::vector<unsigned long long> b;
+        s = energy_hist(c, I, 1, I.zpsi, I.zpsi + I.P, nbins, emin, emax, b);
+        if (s) return s;
+        const double width = (emax - emin) / nbins, N = (double)I.n;
+        for (int j = 0; j < nbins; ++j) out[(size_t)k * nbins + j] = (double)b[j] / (N * width);
+    }
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_philox_device(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n,
+                               void* stream) {
+    if (n < 0 || (n > 0 && (!ctr || !key || !out))) return SGPM_EINVAL;
+    int e = launch_philox(ctr, key, out, n, stream);
+    if (e) return SGPM_EDEVICE;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SGPM_EDEVICE;
+    return SGPM_OK;
+}
+
+}  // extern "C"
