@@ -194,9 +194,11 @@ sgpm_status sgpm_tables(const sgpm_ctx* ctx, int32_t inst, double* z, double* w,
                         double* ehat, double* eps0, double* width_m, double* field,
                         double* density_m2);
 
-/* Launch shape: particles per workgroup chunk (multiple of 256) for the step
- * kernel of instance inst; 0 restores the automatic choice.  The results do
- * not depend on it except through the order of the FP64 moment sums. */
+/* Launch shape: particles per workgroup chunk (a multiple of 512, at most
+ * 32768) of the step kernels of instance inst; 0 restores the automatic
+ * choice.  Particle trajectories, histograms and counters do not depend on
+ * it; the FP64 moment sums only through their order.  Allowed right after
+ * init/set_state (the current time is re-recorded). */
 sgpm_status sgpm_set_chunk(sgpm_ctx* ctx, int32_t inst, int32_t chunk);
 
 /* Average device time (ms) of the step kernel over the last sgpm_step call,

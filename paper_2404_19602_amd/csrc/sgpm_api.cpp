@@ -28,7 +28,7 @@ struct Instance {
     int P = 1, Q = 1, nk = 0;
     int64_t n = 0;
     bool fp32 = false;
-    int64_t chunk = 256;
+    int64_t chunk = kBlock1;
     int nwg = 1, nb = 1;
     int win = 0, win_r0 = 0, win_l0 = 0, hwin_words = 0;
     int64_t hstride = 0;       // words per histogram buffer (padded)
@@ -42,7 +42,6 @@ struct Instance {
     uint32_t* Hmax = nullptr;  // [3][64]
     double* partial = nullptr; // [nwg_max][Q][3]
     double* record = nullptr;  // [max_steps+1][NB][Q][3]
-    uint32_t* done = nullptr;
     unsigned long long* counters = nullptr;
     unsigned long long* bins = nullptr;  // [max(Q,1)][kMaxBins]
     double* zpsi = nullptr;    // [P] basis at a point + eps0 (reconstruction at z)
@@ -54,12 +53,17 @@ struct Instance {
     float* f_eps0sq = nullptr; float* f_cedge = nullptr; float* f_vfield = nullptr;
     float* f_ecos = nullptr;
     double* d_cdf_lo = nullptr; double* d_cdf_hi = nullptr; double* d_gl = nullptr;
+    double* d_psimax = nullptr; float* f_psimax = nullptr;
+    Consts<double>* d_consts = nullptr; Consts<float>* f_consts = nullptr;
+    double* d_ehat = nullptr;
+    int* cand_idx = nullptr;   // [nwg][kWaves1][chunk / kWaves1]
+    int* cand_cnt = nullptr;   // [nwg][kWaves1]
 };
 
 // Bytes of every device region of one instance, in carving order.
 struct Layout {
     size_t total = 0;
-    size_t off[32];
+    size_t off[40];
     int k = 0;
     size_t add(size_t bytes) {
         size_t o = total;
@@ -70,15 +74,21 @@ struct Layout {
 };
 
 int64_t auto_chunk(int64_t n) {
+    // about two stream workgroups per compute unit, whole sub-tiles of 512
     int64_t c = (n + 511) / 512;
-    c = (c + kBlock - 1) / kBlock * kBlock;
-    if (c < kBlock) c = kBlock;
-    if (c > 16384) c = 16384;
+    c = (c + kBlock1 - 1) / kBlock1 * kBlock1;
+    if (c < kBlock1) c = kBlock1;
+    if (c > 32768) c = 32768;
     return c;
 }
 
-void window_for(int Q, int nk, int* win, int* r0, int* l0, int* words) {
-    int w = (int)std::floor(std::sqrt((double)kLdsHistBytes / (2.0 * Q)));
+// LDS histogram window of the stream kernel: the largest even square of
+// packed 16-bit counters per node that fits the budget left by the tables,
+// centred on the grid.
+void window_for(int P, int Q, int nk, bool fp32, int* win, int* r0, int* l0, int* words) {
+    const size_t fixed = k1_lds_bytes(P, Q, fp32 ? 1 : 0, 0) + 64;
+    const double room = fixed < (size_t)kLdsK1Bytes ? (double)(kLdsK1Bytes - fixed) : 0.0;
+    int w = (int)std::floor(std::sqrt(room / (2.0 * Q)));
     w &= ~1;
     if (w > nk) w = nk & ~1;
     if (w < 2) w = 2;
@@ -90,6 +100,7 @@ void window_for(int Q, int nk, int* win, int* r0, int* l0, int* words) {
 
 Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
     Layout L;
+    const size_t n_cand = (size_t)d.n_particles + 32768 + kBlock1;
     const size_t s = d.precision == SGPM_FP32 ? 4 : 8;
     const size_t P = t.P, Q = t.Q, n = (size_t)d.n_particles;
     const size_t hstride = ((size_t)Q * d.nk * d.nk + 63) / 64 * 64;
@@ -100,7 +111,7 @@ Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
     L.add(3 * 64 * 4 * ((Q + 63) / 64));               // 3 Hmax
     L.add(nwg_max * Q * 3 * 8);                        // 4 partial
     L.add(((size_t)d.max_steps + 1) * kNumBatches * Q * 3 * 8);  // 5 record
-    L.add(64);                                         // 6 done
+    L.add(64);                                         // 6 (spare)
     L.add(SGPM_N_COUNTERS * 8);                        // 7 counters
     L.add((size_t)Q * kMaxBins * 8);                   // 8 bins
     L.add((P + 2) * 8);                                // 9 zpsi
@@ -113,6 +124,11 @@ Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
     L.add(Q * (size_t)(t.cdf_np + 1) * 8);             // 24 cdf_lo
     L.add(Q * (size_t)(t.cdf_np + 1) * 8);             // 25 cdf_hi
     L.add(20 * 8);                                     // 26 gl
+    L.add(P * 8); L.add(P * 4);                        // 27,28 psimax d/f
+    L.add(sizeof(Consts<double>)); L.add(sizeof(Consts<float>));  // 29,30
+    L.add(P * 8);                                      // 31 ehat
+    L.add(n_cand * 4);                                 // 32 cand_idx
+    L.add(((size_t)d.n_particles / kBlock1 + 2) * kWaves1 * 4);  // 33 cand_cnt
     return L;
 }
 
@@ -155,111 +171,146 @@ sgpm_status check_ctx(sgpm_ctx* c, int32_t inst) {
 }
 
 template <typename T>
-void fill_tab(const Instance& I, StepArgs<T>& a) {
-    if constexpr (sizeof(T) == 8) {
-        a.tab = DevTab<T>{I.d_psi, I.d_wpsi, I.d_eps0, I.d_eps0sq, I.d_cedge, I.d_vfield, I.d_ecos};
-    } else {
-        a.tab = DevTab<T>{I.f_psi, I.f_wpsi, I.f_eps0, I.f_eps0sq, I.f_cedge, I.f_vfield, I.f_ecos};
+DevTab<T> dev_tab(const Instance& I) {
+    if constexpr (sizeof(T) == 8)
+        return DevTab<T>{I.d_psi, I.d_wpsi, I.d_eps0, I.d_eps0sq, I.d_cedge, I.d_vfield,
+                         I.d_ecos, I.d_psimax, I.d_consts};
+    else
+        return DevTab<T>{I.f_psi, I.f_wpsi, I.f_eps0, I.f_eps0sq, I.f_cedge, I.f_vfield,
+                         I.f_ecos, I.f_psimax, I.f_consts};
+}
+
+// Constants of the step kernels (rates of the Appendix with their test
+// scales, the rate bound, the grid).
+template <typename T>
+Consts<T> make_consts(const sgpm_instance_desc& d, const HostTables& t) {
+    Consts<T> c;
+    std::memset(&c, 0, sizeof(c));
+    c.c_ac = (T)(d.rate_scale[0] * t.c_ac);
+    c.c_om = (T)(d.rate_scale[1] * t.c_o * (t.n_o + 1.0));
+    c.c_op = (T)(d.rate_scale[2] * t.c_o * t.n_o);
+    c.c_km = (T)(d.rate_scale[3] * t.c_k * (t.n_k + 1.0));
+    c.c_kp = (T)(d.rate_scale[4] * t.c_k * t.n_k);
+    c.hw_o = (T)t.hw_o;
+    c.hw_k = (T)t.hw_k;
+    c.edge_kap = (T)t.edge_kap;
+    c.alpha1 = (T)(1.0 + d.alpha);
+    c.v_f = (T)t.v_f;
+    double cemax = 0.0, e0min = t.eps0[0], e0max = t.eps0[0];
+    for (int q = 0; q < t.Q; ++q) {
+        cemax = std::fmax(cemax, t.cedge[q]);
+        e0min = std::fmin(e0min, t.eps0[q]);
+        e0max = std::fmax(e0max, t.eps0[q]);
     }
+    const bool f32 = sizeof(T) == 4;
+    // every coefficient of the bound rounded up, thresholds rounded down
+    const double up = f32 ? 1.0 + 1e-6 : 1.0;
+    c.b_ac = (T)(up * d.rate_scale[0] * t.c_ac);
+    c.b_om = (T)(up * d.rate_scale[1] * t.c_o * (t.n_o + 1.0));
+    c.b_op = (T)(up * d.rate_scale[2] * t.c_o * t.n_o);
+    c.b_km = (T)(up * d.rate_scale[3] * t.c_k * (t.n_k + 1.0));
+    c.b_kp = (T)(up * d.rate_scale[4] * t.c_k * t.n_k);
+    c.b_edge = (T)(up * d.rate_scale[5] * cemax * 2.0 * 3.14159265358979323846);
+    c.b_thr_o = (T)((t.hw_o + e0min) * (f32 ? 1.0 - 1e-6 : 1.0));
+    c.b_thr_k = (T)((t.hw_k + e0min) * (f32 ? 1.0 - 1e-6 : 1.0));
+    c.b_margin = (T)(f32 ? 1.0 + 1e-3 : 1.0 + 1e-9);
+    c.eps0max_sq = (T)(e0max * e0max * (f32 ? 1.0 + 1e-6 : 1.0));
+    c.lk = (T)d.lk_eV;
+    c.dk = (T)(2.0 * d.lk_eV / d.nk);
+    c.inv_dk = (T)(1.0 / (2.0 * d.lk_eV / d.nk));
+    c.nk = d.nk;
+    c.pauli = d.pauli;
+    c.final_state = d.final_state;
+    c.c_max = d.c_max;
+    return c;
+}
+
+uint32_t* hbuf(const Instance& I, int64_t k) { return I.H + (size_t)(k % 3) * I.hstride; }
+uint32_t* hmbuf(const Instance& I, int64_t k) {
+    return I.Hmax + (size_t)(k % 3) * 64 * ((I.Q + 63) / 64);
 }
 
 template <typename T>
-StepArgs<T> make_args(const Instance& I, double dt, bool drift, bool collide, int64_t step,
-                      int64_t rec_index) {
-    StepArgs<T> a;
+K1Args<T> make_k1(const Instance& I, double dt, bool moving, int64_t step, uint32_t* h_acc) {
+    K1Args<T> a;
     std::memset(&a, 0, sizeof(a));
-    const HostTables& t = I.t;
-    const sgpm_instance_desc& d = I.d;
     a.kx = static_cast<T*>(I.kx);
     a.ky = static_cast<T*>(I.ky);
-    a.n = I.n;
-    a.P = I.P;
-    a.Q = I.Q;
-    fill_tab<T>(I, a);
-    a.drift_mask = 0;
-    for (int h = 0; h < I.P; ++h) {
-        const double v = (t.v_f * dt) * t.ehat[h];
-        a.drift[h] = (T)v;
-        if (v != 0.0 && h < 32) a.drift_mask |= 1u << h;
-    }
+    a.n = I.n; a.P = I.P; a.Q = I.Q;
+    a.tab = dev_tab<T>(I);
+    a.ehat = I.d_ehat;
+    a.vfdt = I.t.v_f * dt;
     a.dt = (T)dt;
-    a.c_ac = (T)(d.rate_scale[0] * t.c_ac);
-    a.c_om = (T)(d.rate_scale[1] * t.c_o * (t.n_o + 1.0));
-    a.c_op = (T)(d.rate_scale[2] * t.c_o * t.n_o);
-    a.c_km = (T)(d.rate_scale[3] * t.c_k * (t.n_k + 1.0));
-    a.c_kp = (T)(d.rate_scale[4] * t.c_k * t.n_k);
-    a.hw_o = (T)t.hw_o;
-    a.hw_k = (T)t.hw_k;
-    a.edge_kap = (T)t.edge_kap;
-    a.alpha1 = (T)(1.0 + d.alpha);
-    a.v_f = (T)t.v_f;
-    // bound of max_q S_q as a function of the largest nodal energy
-    double cemax = 0.0, e0min = t.eps0[0];
-    for (int q = 0; q < I.Q; ++q) {
-        cemax = std::fmax(cemax, t.cedge[q]);
-        e0min = std::fmin(e0min, t.eps0[q]);
-    }
-    a.b_ac = (T)(d.rate_scale[0] * t.c_ac);
-    a.b_om = (T)(d.rate_scale[1] * t.c_o * (t.n_o + 1.0));
-    a.b_op = (T)(d.rate_scale[2] * t.c_o * t.n_o);
-    a.b_km = (T)(d.rate_scale[3] * t.c_k * (t.n_k + 1.0));
-    a.b_kp = (T)(d.rate_scale[4] * t.c_k * t.n_k);
-    a.b_edge = (T)(d.rate_scale[5] * cemax * 2.0 * 3.14159265358979323846);
-    a.b_thr_o = (T)(t.hw_o + e0min);
-    a.b_thr_k = (T)(t.hw_k + e0min);
-    a.b_margin = (T)(sizeof(T) == 8 ? 1.0 + 1e-9 : 1.0 + 1e-3);
-    if (sizeof(T) == 4) {
-        // float rounding of the thresholds must not lift them above the exact ones
-        a.b_thr_o = (T)((double)a.b_thr_o * (1.0 - 1e-6));
-        a.b_thr_k = (T)((double)a.b_thr_k * (1.0 - 1e-6));
-    }
-    a.lk = (T)d.lk_eV;
-    a.dk = (T)(2.0 * d.lk_eV / d.nk);
-    a.inv_dk = (T)(1.0 / (2.0 * d.lk_eV / d.nk));
-    a.nk = d.nk;
-    a.pauli = d.pauli;
-    a.final_state = d.final_state;
-    a.c_max = d.c_max;
-    a.seed_lo = (uint32_t)(d.seed & 0xFFFFFFFFu);
-    a.seed_hi = (uint32_t)(d.seed >> 32);
-    a.instance = d.instance_id;
+    a.seed_lo = (uint32_t)(I.d.seed & 0xFFFFFFFFu);
+    a.seed_hi = (uint32_t)(I.d.seed >> 32);
+    a.instance = I.d.instance_id;
     a.step = (uint32_t)step;
-    const int rd = (int)(step % 3), ac = (int)((step + 1) % 3), cl = (int)((step + 2) % 3);
-    // for a rebuild (no collisions) the pass accumulates H of the current step
-    const int acc_buf = collide || drift ? ac : rd;
-    const int clr_buf = collide || drift ? cl : ac;
-    a.h_read = I.H + (size_t)rd * I.hstride;
-    a.hmax_read = I.Hmax + (size_t)rd * 64 * ((I.Q + 63) / 64);
-    a.h_acc = I.H + (size_t)acc_buf * I.hstride;
-    a.hmax_acc = I.Hmax + (size_t)acc_buf * 64 * ((I.Q + 63) / 64);
-    a.h_clr = I.H + (size_t)clr_buf * I.hstride;
-    a.hmax_clr = I.Hmax + (size_t)clr_buf * 64 * ((I.Q + 63) / 64);
-    a.clear_vec4 = I.hstride / 4;
-    a.win = I.win;
-    a.win_r0 = I.win_r0;
-    a.win_l0 = I.win_l0;
-    a.hwin_words = I.hwin_words;
+    a.h_acc = h_acc;
+    a.win = I.win; a.win_r0 = I.win_r0; a.win_l0 = I.win_l0; a.hwin_words = I.hwin_words;
     a.partial = I.partial;
-    a.record = I.record + (size_t)rec_index * I.nb * I.Q * 3;
-    a.done = I.done;
-    a.nb = I.nb;
+    a.cand_idx = I.cand_idx;
+    a.cand_cnt = I.cand_cnt;
+    a.cap_w = (int)(I.chunk / kWaves1);
     a.counters = I.counters;
     a.chunk = I.chunk;
-    a.nwg = I.nwg;
-    a.do_drift = drift ? 1 : 0;
-    a.do_collide = collide ? 1 : 0;
+    a.do_drift = moving ? 1 : 0;
+    a.do_collide = moving ? 1 : 0;
     return a;
 }
 
-int pmax_bucket(int P) { return P; }
+template <typename T>
+K2Args<T> make_k2(const Instance& I, double dt, int64_t step) {
+    K2Args<T> a;
+    std::memset(&a, 0, sizeof(a));
+    a.kx = static_cast<T*>(I.kx);
+    a.ky = static_cast<T*>(I.ky);
+    a.n = I.n; a.P = I.P; a.Q = I.Q;
+    int G = 1;
+    while (G < I.Q && G < 64) G <<= 1;
+    a.G = G;
+    a.tab = dev_tab<T>(I);
+    a.ehat = I.d_ehat;
+    a.vfdt = I.t.v_f * dt;
+    a.dt = (T)dt;
+    a.seed_lo = (uint32_t)(I.d.seed & 0xFFFFFFFFu);
+    a.seed_hi = (uint32_t)(I.d.seed >> 32);
+    a.instance = I.d.instance_id;
+    a.step = (uint32_t)step;
+    a.h_read = hbuf(I, step);
+    a.hmax_read = hmbuf(I, step);
+    a.h_acc = hbuf(I, step + 1);
+    a.partial = I.partial;
+    a.cand_idx = I.cand_idx;
+    a.cand_cnt = I.cand_cnt;
+    a.cap_w = (int)(I.chunk / kWaves1);
+    a.counters = I.counters;
+    a.chunk = I.chunk;
+    return a;
+}
 
-sgpm_status launch_pass(sgpm_ctx* c, Instance& I, double dt, bool drift, bool collide,
-                        int64_t step, int64_t rec_index) {
+K3Args make_k3(const Instance& I, int64_t built, int64_t clear, int64_t rec_index) {
+    K3Args a;
+    a.Q = I.Q; a.nk = I.nk;
+    a.h_acc = hbuf(I, built);
+    a.hmax_out = hmbuf(I, built);
+    a.h_clr = hbuf(I, clear);
+    a.partial = I.partial;
+    a.nwg = I.nwg; a.nb = I.nb;
+    a.record = I.record + (size_t)rec_index * I.nb * I.Q * 3;
+    return a;
+}
+
+// One time step of instance I: stream, colliders, finalize.
+sgpm_status launch_step(sgpm_ctx* c, Instance& I, double dt, int64_t step, int64_t rec_index) {
     int e;
-    if (I.fp32) e = launch_step_f32(make_args<float>(I, dt, drift, collide, step, rec_index),
-                                    pmax_bucket(I.P), c->stream);
-    else e = launch_step_f64(make_args<double>(I, dt, drift, collide, step, rec_index),
-                             pmax_bucket(I.P), c->stream);
+    if (I.fp32) {
+        e = launch_k1_f32(make_k1<float>(I, dt, true, step, hbuf(I, step + 1)), I.nwg, c->stream);
+        if (!e) e = launch_k2_f32(make_k2<float>(I, dt, step), I.nwg, c->stream);
+    } else {
+        e = launch_k1_f64(make_k1<double>(I, dt, true, step, hbuf(I, step + 1)), I.nwg, c->stream);
+        if (!e) e = launch_k2_f64(make_k2<double>(I, dt, step), I.nwg, c->stream);
+    }
+    if (!e) e = launch_k3(make_k3(I, step + 1, step + 2, rec_index), c->stream);
     if (e != 0) return dev_fail(c, (hipError_t)e, "step kernel launch");
     return SGPM_OK;
 }
@@ -270,15 +321,19 @@ void set_chunk(Instance& I, int64_t chunk) {
     I.nb = I.nwg < kNumBatches ? I.nwg : kNumBatches;
 }
 
-// rebuild H and record index 0 for the current state
+// histogram, its maximum and record index 0 for the current state
 sgpm_status rebuild(sgpm_ctx* c, Instance& I) {
     const size_t hm = (size_t)64 * ((I.Q + 63) / 64) * 4;
     HIPCHK(c, hipMemsetAsync(I.H, 0, (size_t)3 * I.hstride * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(I.Hmax, 0, 3 * hm, c->stream));
     HIPCHK(c, hipMemsetAsync(I.counters, 0, SGPM_N_COUNTERS * 8, c->stream));
-    HIPCHK(c, hipMemsetAsync(I.done, 0, 64, c->stream));
     I.rec_base = I.step;
-    return launch_pass(c, I, 0.0, false, false, I.step, 0);
+    int e;
+    if (I.fp32) e = launch_k1_f32(make_k1<float>(I, 0.0, false, I.step, hbuf(I, I.step)), I.nwg, c->stream);
+    else e = launch_k1_f64(make_k1<double>(I, 0.0, false, I.step, hbuf(I, I.step)), I.nwg, c->stream);
+    if (!e) e = launch_k3(make_k3(I, I.step, I.step + 1, 0), c->stream);
+    if (e != 0) return dev_fail(c, (hipError_t)e, "rebuild launch");
+    return SGPM_OK;
 }
 
 }  // namespace
@@ -368,7 +423,7 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         I.kx = at(0); I.ky = at(1);
         I.H = (uint32_t*)at(2); I.Hmax = (uint32_t*)at(3);
         I.partial = (double*)at(4); I.record = (double*)at(5);
-        I.done = (uint32_t*)at(6); I.counters = (unsigned long long*)at(7);
+        I.counters = (unsigned long long*)at(7);
         I.bins = (unsigned long long*)at(8); I.zpsi = (double*)at(9);
         I.d_psi = (double*)at(10); I.d_wpsi = (double*)at(11);
         I.d_eps0 = (double*)at(12); I.d_eps0sq = (double*)at(13);
@@ -377,9 +432,13 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         I.f_eps0 = (float*)at(19); I.f_eps0sq = (float*)at(20);
         I.f_cedge = (float*)at(21); I.f_vfield = (float*)at(22); I.f_ecos = (float*)at(23);
         I.d_cdf_lo = (double*)at(24); I.d_cdf_hi = (double*)at(25); I.d_gl = (double*)at(26);
+        I.d_psimax = (double*)at(27); I.f_psimax = (float*)at(28);
+        I.d_consts = (Consts<double>*)at(29); I.f_consts = (Consts<float>*)at(30);
+        I.d_ehat = (double*)at(31);
+        I.cand_idx = (int*)at(32); I.cand_cnt = (int*)at(33);
         base += L.total;
         set_chunk(I, 0);
-        window_for(I.Q, I.nk, &I.win, &I.win_r0, &I.win_l0, &I.hwin_words);
+        window_for(I.P, I.Q, I.nk, I.fp32, &I.win, &I.win_r0, &I.win_l0, &I.hwin_words);
 
         // upload the tables (FP64 masters and FP32 copies)
         const int Q = I.Q, P = I.P;
@@ -397,6 +456,14 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         std::vector<float> fpsi = tof(t.psi), fwpsi = tof(t.wpsi), feps0 = tof(t.eps0),
                            feps0sq = tof(eps0sq), fcedge = tof(cedge), fvfield = tof(vfield),
                            fecos = tof(ecos);
+        std::vector<double> psimax(P, 0.0);
+        for (int h = 0; h < P; ++h)
+            for (int q = 0; q < Q; ++q) psimax[h] = std::fmax(psimax[h], std::fabs(t.psi[q * P + h]));
+        // rounded up in FP32 so the coefficient bound stays an upper bound
+        std::vector<float> fpsimax(P);
+        for (int h = 0; h < P; ++h) fpsimax[h] = (float)(psimax[h] * (1.0 + 1e-6));
+        const Consts<double> cd = make_consts<double>(I.d, t);
+        const Consts<float> cf = make_consts<float>(I.d, t);
         double gl[20];
         for (int k2 = 0; k2 < 10; ++k2) { gl[k2] = t.gl10_x[k2]; gl[10 + k2] = t.gl10_w[k2]; }
         hipError_t e = hipSuccess;
@@ -417,7 +484,11 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         if (e == hipSuccess) e = up(I.d_cdf_lo, t.cdf_lo.data(), t.cdf_lo.size() * 8);
         if (e == hipSuccess) e = up(I.d_cdf_hi, t.cdf_hi.data(), t.cdf_hi.size() * 8);
         if (e == hipSuccess) e = up(I.d_gl, gl, 20 * 8);
-        if (e == hipSuccess) e = hipMemsetAsync(I.done, 0, 64, c->stream);
+        if (e == hipSuccess) e = up(I.d_psimax, psimax.data(), P * 8);
+        if (e == hipSuccess) e = up(I.f_psimax, fpsimax.data(), P * 4);
+        if (e == hipSuccess) e = up(I.d_consts, &cd, sizeof(cd));
+        if (e == hipSuccess) e = up(I.f_consts, &cf, sizeof(cf));
+        if (e == hipSuccess) e = up(I.d_ehat, t.ehat.data(), P * 8);
         if (e == hipSuccess) e = hipMemsetAsync(I.counters, 0, SGPM_N_COUNTERS * 8, c->stream);
         // host vectors above are released at scope end: wait for the copies
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -466,8 +537,8 @@ sgpm_status sgpm_tables(const sgpm_ctx* c, int32_t inst, double* z, double* w, d
 sgpm_status sgpm_set_chunk(sgpm_ctx* c, int32_t inst, int32_t chunk) {
     sgpm_status s = check_ctx(c, inst);
     if (s) return s;
-    if (chunk < 0 || chunk % kBlock != 0 || chunk > 65535)
-        return fail(c, SGPM_EINVAL, "chunk must be a multiple of 256 below 65536 (0 = automatic)");
+    if (chunk < 0 || chunk % kBlock1 != 0 || chunk > 32768)
+        return fail(c, SGPM_EINVAL, "chunk must be a multiple of 512 up to 32768 (0 = automatic)");
     Instance& I = c->inst[inst];
     if (I.initialised && I.step != I.rec_base)
         return fail(c, SGPM_ESTATE, "the launch shape can only change right after init/set_state");
@@ -517,7 +588,7 @@ sgpm_status sgpm_step(sgpm_ctx* c, double dt, int64_t n_steps) {
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     for (int64_t k = 0; k < n_steps; ++k) {
         for (Instance& I : c->inst) {
-            sgpm_status s = launch_pass(c, I, dt, true, true, I.step, I.step - I.rec_base + 1);
+            sgpm_status s = launch_step(c, I, dt, I.step, I.step - I.rec_base + 1);
             if (s) return s;
             I.step += 1;
         }

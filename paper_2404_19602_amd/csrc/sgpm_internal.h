@@ -12,13 +12,12 @@ namespace sgpm {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
-constexpr int kQueueCap = 2 * kBlock;  // LDS candidate queue
 constexpr int kMaxP = 32;            // largest gPC basis the kernels accept
 constexpr int kMaxQ = 128;           // largest node count
 constexpr int kEdgePts = 32;         // trapezoid points of the edge integral
 constexpr int kEdgeTries = 64;       // edge-angle proposals per collision
 constexpr int kNumBatches = 32;      // batch-means batches of the moment record
-constexpr int kLdsHistBytes = 56 * 1024;  // LDS budget of the histogram window
+constexpr int kLdsK1Bytes = 60 * 1024;   // LDS budget of a stream workgroup
 
 // Host FP64 set-up of one instance (Sec. 4.1 tables, Appendix rate constants).
 struct HostTables {
@@ -52,57 +51,95 @@ int num_modes(int dim_z, int degree);
 double basis_at(int dim_z, int h, const double* z);
 void eval_basis_all(int dim_z, int P, const double* z, double* out);
 
-// Device table blob of one instance (arrays are offsets into the blob).
+// Per-instance constants of the step kernels, resident in device memory and
+// staged into LDS by every workgroup (keeps them out of scalar registers).
+template <typename T>
+struct Consts {
+    T c_ac, c_om, c_op, c_km, c_kp;   // rate coefficients incl. Bose factors and scales
+    T hw_o, hw_k;
+    T edge_kap;                       // 2 a^2 / (hbar v_F)^2, 1/eV^2
+    T alpha1;                         // 1 + alpha
+    T v_f;                            // m/s
+    // upper bound of max_q sum_nu Gamma^nu as a function of an energy bound
+    T b_ac, b_om, b_op, b_km, b_kp, b_edge, b_thr_o, b_thr_k, b_margin;
+    T eps0max_sq;
+    T lk, dk, inv_dk;
+    int32_t nk, pauli, final_state, c_max;
+};
+
+// Device tables of one instance in one precision (all [Q][P] row-major).
 template <typename T>
 struct DevTab {
     const T* psi;      // [Q][P]
-    const T* wpsi;     // [Q][P]
+    const T* wpsi;     // [Q][P]   w_q Psi_h(z_q)
     const T* eps0;     // [Q]
     const T* eps0sq;   // [Q]
     const T* cedge;    // [Q] edge prefactor times its rate scale
-    const T* vfield;   // [Q] v_F E(z_q), eV/s
+    const T* vfield;   // [Q] v_F E(z_q)
     const T* edge_cos; // [17]
+    const T* psimax;   // [P] max_q |Psi_h(z_q)|
+    const Consts<T>* consts;
 };
 
+constexpr int kWaves1 = 8;            // waves per workgroup of the stream kernel
+constexpr int kBlock1 = 64 * kWaves1;
+
+// Stream kernel: every particle of a chunk, lane per particle.
 template <typename T>
-struct StepArgs {
+struct K1Args {
     T* kx;
     T* ky;
     int64_t n;
     int P, Q;
     DevTab<T> tab;
-    T drift[kMaxP];      // v_F dt E_h, eV
-    uint32_t drift_mask; // modes with a nonzero drift (h < 32)
+    const double* ehat;     // [P] Galerkin field coefficients (V/m)
+    double vfdt;            // v_F dt: drift of mode h is vfdt * ehat[h]
     T dt;
-    T c_ac, c_om, c_op, c_km, c_kp;   // rate coefficients incl. Bose factors and scales
-    T hw_o, hw_k;
-    T edge_kap;          // 2 a^2/(hbar v_F)^2
-    T alpha1;            // 1 + alpha
-    T v_f;               // m/s
-    // rigorous upper bound of max_q sum_nu Gamma^nu as a function of eps_max
-    T b_ac, b_om, b_op, b_km, b_kp, b_edge, b_thr_o, b_thr_k, b_margin;
-    T lk, dk, inv_dk;
-    int nk;
-    int pauli, final_state, c_max;
     uint32_t seed_lo, seed_hi, instance, step;
-    // histogram buffers: read H^n, accumulate H^{n+1}, clear the stale one
+    uint32_t* h_acc;        // H^{n+1}
+    int win, win_r0, win_l0, hwin_words;
+    double* partial;        // [nwg][Q][3]
+    int* cand_idx;          // [nwg][kWaves1][cap_w]
+    int* cand_cnt;          // [nwg][kWaves1]
+    int cap_w;
+    unsigned long long* counters;
+    int64_t chunk;
+    int do_drift, do_collide;
+};
+
+// Collider kernel: the candidates of one stream workgroup, a group of lanes
+// per candidate, one node per lane.
+template <typename T>
+struct K2Args {
+    T* kx;
+    T* ky;
+    int64_t n;
+    int P, Q, G;            // G: lanes per candidate (power of two)
+    DevTab<T> tab;
+    const double* ehat;
+    double vfdt;
+    T dt;
+    uint32_t seed_lo, seed_hi, instance, step;
     const uint32_t* h_read;
     const uint32_t* hmax_read;
     uint32_t* h_acc;
-    uint32_t* hmax_acc;
-    uint32_t* h_clr;
-    uint32_t* hmax_clr;
-    int64_t clear_vec4;  // uint4 stores to clear the stale buffer
-    int win, win_r0, win_l0, hwin_words;
-    // moments
-    double* partial;     // [nwg][Q][3]
-    double* record;      // [NB][Q][3] of this time index
-    uint32_t* done;
-    int nb;
-    unsigned long long* counters;  // [SGPM_N_COUNTERS]
+    double* partial;
+    const int* cand_idx;
+    const int* cand_cnt;
+    int cap_w;
+    unsigned long long* counters;
     int64_t chunk;
-    int nwg;
-    int do_drift, do_collide;
+};
+
+// Finalize kernel: one workgroup per node.
+struct K3Args {
+    int Q, nk;
+    const uint32_t* h_acc;  // histogram just built
+    uint32_t* hmax_out;     // its per-node maximum
+    uint32_t* h_clr;        // stale buffer cleared for the next step
+    const double* partial;  // [nwg][Q][3]
+    int nwg, nb;
+    double* record;         // [NB][Q][3]
 };
 
 struct InitArgs {
@@ -133,12 +170,16 @@ struct EnergyHistArgs {
 };
 
 // Kernel launchers (sgpm_kernels.hip).  Return hipError_t as int.
-int launch_step_f64(const StepArgs<double>& a, int pmax_bucket, void* stream);
-int launch_step_f32(const StepArgs<float>& a, int pmax_bucket, void* stream);
+int launch_k1_f64(const K1Args<double>& a, int nwg, void* stream);
+int launch_k1_f32(const K1Args<float>& a, int nwg, void* stream);
+int launch_k2_f64(const K2Args<double>& a, int nwg, void* stream);
+int launch_k2_f32(const K2Args<float>& a, int nwg, void* stream);
+int launch_k3(const K3Args& a, void* stream);
 int launch_init(const InitArgs& a, void* stream);
 int launch_energy_hist(const EnergyHistArgs& a, void* stream);
 int launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n,
                   void* stream);
-size_t step_lds_bytes(int Q, int hwin_words);
+size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words);
+size_t k2_lds_bytes(int P, int Q, int fp32);
 
 }  // namespace sgpm

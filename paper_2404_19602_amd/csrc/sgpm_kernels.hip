@@ -1,19 +1,23 @@
 // gfx950 kernels of the sG-PM hot path (arXiv:2404.19602, Algorithm 2).
 //
-// One launch of step_kernel advances one instance by one time step:
-//   - Galerkin drift of the coefficients (Sec. 4.1, electric forcing),
-//   - evaluation of k_i(z_q) at the Gauss nodes (eq. gPC),
-//   - collision decision: a rigorous upper bound of the node-maximum rate
-//     clears most particles without the exact rates (eq. deltat); the rest
-//     are compacted into an LDS queue and run the exact collision loop
-//     (mechanism selection eq. update_gPC, final states, Pauli acceptance
-//     eq. Pauli_gPC against H^n on the moved grid, projection eq. update_sG),
-//   - the histogram H^{n+1} of every node (eq. f_gPC) through a privatised
-//     LDS window flushed with global atomics, the per-node maximum through
-//     atomicMax of the values the atomics return,
-//   - FP64 per-node sums of v_x, v_y and the energy (Sec. 4.2), reduced in a
-//     fixed order by the last workgroup into the moment record,
-//   - clearing of the stale histogram buffer for the next step.
+// One time step of one instance is three launches:
+//  K1 stream   -- lane per particle over a chunk per workgroup: Galerkin drift
+//                 (Sec. 4.1), an upper bound of the node-maximum collision
+//                 rate from the coefficients (eq. deltat) that proves most
+//                 particles do not collide in this step; for those, the node
+//                 values k_i(z_q) (eq. gPC), their cells in H^{n+1} through a
+//                 privatised LDS window, and FP64 sums of v_x, v_y and the
+//                 energy per node (Sec. 4.2).  The others are listed, in a
+//                 fixed order, as collision candidates.
+//  K2 collide  -- the candidates of one K1 workgroup, a group of lanes per
+//                 candidate and one node per lane: exact node rates, the
+//                 node maximum, free flight, mechanism selection (eq.
+//                 update_gPC), final states, Pauli acceptance against H^n on
+//                 the moved grid (eq. Pauli_gPC) and the projection of eq.
+//                 update_sG as a group sum; then their H^{n+1} cells and sums.
+//  K3 finalize -- one workgroup per node: the maximum of H^{n+1}, clearing of
+//                 the stale buffer for the next step, and the fixed-order
+//                 reduction of the moment sums into the record.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -52,14 +56,14 @@ template <> __device__ __forceinline__ float uni<float>(uint32_t hi, uint32_t) {
     return ((float)(hi >> 9) + 0.5f) * 0x1p-23f;
 }
 
-template <typename T> struct Consts;
-template <> struct Consts<double> {
-    static constexpr double two_pi = 6.283185307179586476925286766559;
+template <typename T> struct Num;
+template <> struct Num<double> {
     static constexpr double trap = 6.283185307179586476925286766559 / kEdgePts;
+    static constexpr double eps = 2.220446049250313e-16;
 };
-template <> struct Consts<float> {
-    static constexpr float two_pi = 6.28318530717958647692f;
+template <> struct Num<float> {
     static constexpr float trap = 6.28318530717958647692f / kEdgePts;
+    static constexpr float eps = 1.1920929e-07f;
 };
 
 __device__ __forceinline__ double dlog(double x) { return log(x); }
@@ -69,433 +73,290 @@ __device__ __forceinline__ float dexp(float x) { return expf(x); }
 __device__ __forceinline__ void dsincospi(double x, double* s, double* c) { sincospi(x, s, c); }
 __device__ __forceinline__ void dsincospi(float x, float* s, float* c) { sincospif(x, s, c); }
 
-// Cell index floor((x + L)/dk) exactly as the quotient is rounded: the cheap
-// product by 1/dk is corrected by a true division only when it lies within
-// a few ulps of an integer.
+// floor((x + L)/dk) as the rounded quotient gives it: the product by 1/dk is
+// replaced by the true division only within a few ulps of an integer.
+// Outside [0, 2^30) (and NaN) -> -1.
 template <typename T>
 __device__ __forceinline__ int cell_coord(T x, T L, T dk, T inv_dk) {
     const T s = x + L;
     T qt = s * inv_dk;
     const T r = rint(qt);
-    if (fabs(qt - r) <= (T)8 * (T)(sizeof(T) == 8 ? 2.220446049250313e-16 : 1.1920929e-07) * fabs(qt) +
-                             (T)1e-30)
-        qt = s / dk;
+    if (fabs(qt - r) <= (T)8 * Num<T>::eps * fabs(qt) + (T)1e-30) qt = s / dk;
     const T f = floor(qt);
-    // outside the grid (including NaN) maps to -1
-    return (f >= (T)0 && f < (T)1e9) ? (int)f : -1;
+    return (f >= (T)0 && f < (T)1073741824) ? (int)f : -1;
 }
 
-// ------------------------------------------------------------ wave sums
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
 
-// ---------------------------------------------------------------- rates
-// The five closed-form phonon rates (Appendix) at energy e of node q, in the
-// order AC, OP-, OP+, K-, K+.
 template <typename T>
-__device__ __forceinline__ void phonon_rates(const StepArgs<T>& a, T e, T e0, T r[5]) {
-    r[0] = (e - e0 >= (T)0) ? a.c_ac * e : (T)0;
-    const T eom = e - a.hw_o, eop = e + a.hw_o, ekm = e - a.hw_k, ekp = e + a.hw_k;
-    r[1] = (eom - e0 >= (T)0) ? a.c_om * eom : (T)0;
-    r[2] = (eop - e0 >= (T)0) ? a.c_op * eop : (T)0;
-    r[3] = (ekm - e0 >= (T)0) ? a.c_km * ekm : (T)0;
-    r[4] = (ekp - e0 >= (T)0) ? a.c_kp * ekp : (T)0;
+__device__ __forceinline__ T group_max(T v, int G) {
+    for (int m = G >> 1; m >= 1; m >>= 1) {
+        const T o = __shfl_xor(v, m, G);
+        v = o > v ? o : v;
+    }
+    return v;
 }
 
-// Edge rate: cedge_q * eps * int_0^{2pi} exp(-kap (cos t - c)^2) dt by the
-// 32-point trapezoid rule, summed with the symmetry cos(t_j) = cos(t_{32-j}).
+// sum over the lanes of the group, the same value (the group's first lane's
+// result) delivered to every lane
 template <typename T>
-__device__ __forceinline__ T edge_rate(const StepArgs<T>& a, int q, T kx, T ky, T e) {
+__device__ __forceinline__ T group_sum(T v, int G) {
+    for (int m = G >> 1; m >= 1; m >>= 1) v += __shfl_xor(v, m, G);
+    return __shfl(v, 0, G);
+}
+
+// ------------------------------------------------------- rate evaluations
+// the five closed-form phonon rates (Appendix) at energy e of a node with
+// band minimum e0, order AC, OP-, OP+, K-, K+
+template <typename T>
+__device__ __forceinline__ void phonon_rates(const Consts<T>& c, T e, T e0, T r[5]) {
+    r[0] = (e - e0 >= (T)0) ? c.c_ac * e : (T)0;
+    const T eom = e - c.hw_o, eop = e + c.hw_o, ekm = e - c.hw_k, ekp = e + c.hw_k;
+    r[1] = (eom - e0 >= (T)0) ? c.c_om * eom : (T)0;
+    r[2] = (eop - e0 >= (T)0) ? c.c_op * eop : (T)0;
+    r[3] = (ekm - e0 >= (T)0) ? c.c_km * ekm : (T)0;
+    r[4] = (ekp - e0 >= (T)0) ? c.c_kp * ekp : (T)0;
+}
+
+// edge rate: cedge * eps * int_0^{2pi} exp(-kap (cos t - c)^2) dt by the
+// 32-point trapezoid rule, summed with cos(t_j) = cos(t_{32-j})
+template <typename T>
+__device__ __forceinline__ T edge_rate(const Consts<T>& c, const T* ecos, T cedge, T e0, T kx,
+                                       T ky, T e) {
     const T k2 = kx * kx + ky * ky;
     const T kabs = sqrt(k2);
-    const T c = kabs > (T)0 ? kx / kabs : (T)1;
-    const T kap = a.edge_kap * k2;
-    const T* cs = a.tab.edge_cos;
-    T d0 = cs[0] - c, d16 = cs[kEdgePts / 2] - c;
+    const T cin = kabs > (T)0 ? kx / kabs : (T)1;
+    const T kap = c.edge_kap * k2;
+    const T d0 = ecos[0] - cin, d16 = ecos[kEdgePts / 2] - cin;
     T acc = dexp(-kap * d0 * d0) + dexp(-kap * d16 * d16);
     T mid = (T)0;
 #pragma unroll
     for (int j = 1; j < kEdgePts / 2; ++j) {
-        const T d = cs[j] - c;
+        const T d = ecos[j] - cin;
         mid += dexp(-kap * d * d);
     }
     acc += (T)2 * mid;
-    const T e0 = a.tab.eps0[q];
-    return (e - e0 >= (T)0) ? a.tab.cedge[q] * e * (acc * Consts<T>::trap) : (T)0;
+    return (e - e0 >= (T)0) ? cedge * e * (acc * Num<T>::trap) : (T)0;
 }
 
-// Upper bound of max_q sum_nu Gamma^nu given the largest nodal energy: every
-// rate is non-decreasing in the energy, the angular edge integral is at most
-// 2 pi, and emission thresholds use the smallest band minimum.
+// Upper bound of (1 + alpha) max_q sum_nu Gamma^nu(z_q) given an upper bound
+// emax of every nodal energy: each rate is non-decreasing in the energy, the
+// angular edge integral is at most 2 pi, emission thresholds use the smallest
+// band minimum; the margin covers rounding.
 template <typename T>
-__device__ __forceinline__ T rate_bound(const StepArgs<T>& a, T emax) {
-    T s = a.b_ac * emax + a.b_op * (emax + a.hw_o) + a.b_kp * (emax + a.hw_k) + a.b_edge * emax;
-    if (emax >= a.b_thr_o) s += a.b_om * (emax - a.hw_o);
-    if (emax >= a.b_thr_k) s += a.b_km * (emax - a.hw_k);
-    return a.alpha1 * s * a.b_margin;
+__device__ __forceinline__ T rate_bound(const Consts<T>& c, T emax) {
+    T s = c.b_ac * emax + c.b_op * (emax + c.hw_o) + c.b_kp * (emax + c.hw_k) + c.b_edge * emax;
+    if (emax >= c.b_thr_o) s += c.b_om * (emax - c.hw_o);
+    if (emax >= c.b_thr_k) s += c.b_km * (emax - c.hw_k);
+    return c.alpha1 * s * c.b_margin;
 }
 
-// --------------------------------------------------------- LDS layout
-struct Lds {
-    uint32_t* hwin;     // packed 16-bit counters of the histogram window
-    int* queue;         // candidate particles (offset within the chunk)
-    double* macc;       // [waves][Q][3] moment sums
-    uint32_t* wgmax;    // [Q]
-    uint32_t* cnt;      // [8] counters + [8] queue length
-};
-
-__host__ __device__ inline size_t lds_offsets(int Q, int hwin_words, size_t* o_queue,
-                                              size_t* o_macc, size_t* o_wgmax, size_t* o_cnt) {
+// ======================================================= K1: stream kernel
+size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words) {
+    const size_t s = fp32 ? 4 : 8;
     size_t off = (size_t)hwin_words * 4;
     off = (off + 15) & ~(size_t)15;
-    *o_queue = off;
-    off += (size_t)kQueueCap * 4;
+    off += sizeof(Consts<double>);                       // consts (either precision fits)
     off = (off + 15) & ~(size_t)15;
-    *o_macc = off;
-    off += (size_t)kWaves * Q * 3 * 8;
-    *o_wgmax = off;
-    off += (size_t)Q * 4;
+    off += s * ((size_t)Q * P + Q + 2 * P);             // psi, eps0sq, psimax, drift
     off = (off + 15) & ~(size_t)15;
-    *o_cnt = off;
-    off += 16 * 4;
+    off += (size_t)kWaves1 * Q * 3 * 8;                  // per-wave moment sums
+    off += 16 * 4;                                       // counters
     return off;
 }
 
-size_t step_lds_bytes(int Q, int hwin_words) {
-    size_t a, b, c, d;
-    return lds_offsets(Q, hwin_words, &a, &b, &c, &d);
+template <typename T>
+struct K1Lds {
+    uint32_t* hwin;
+    Consts<T>* c;
+    T* psi; T* eps0sq; T* psimax; T* drift;
+    double* red;
+    uint32_t* cnt;
+};
+
+template <typename T>
+__device__ __forceinline__ K1Lds<T> k1_lds(unsigned char* smem, int P, int Q, int hwin_words) {
+    K1Lds<T> L;
+    size_t off = (size_t)hwin_words * 4;
+    off = (off + 15) & ~(size_t)15;
+    L.hwin = reinterpret_cast<uint32_t*>(smem);
+    L.c = reinterpret_cast<Consts<T>*>(smem + off);
+    off += sizeof(Consts<double>);
+    off = (off + 15) & ~(size_t)15;
+    L.psi = reinterpret_cast<T*>(smem + off);
+    L.eps0sq = L.psi + Q * P;
+    L.psimax = L.eps0sq + Q;
+    L.drift = L.psimax + P;
+    off += sizeof(T) * ((size_t)Q * P + Q + 2 * P);
+    off = (off + 15) & ~(size_t)15;
+    L.red = reinterpret_cast<double*>(smem + off);
+    off += (size_t)kWaves1 * Q * 3 * 8;
+    L.cnt = reinterpret_cast<uint32_t*>(smem + off);
+    return L;
 }
 
-// Bin one nodal value into the histogram of node q, and account the moments.
+// one nodal value into H^{n+1}: LDS window when inside it, else global
 template <typename T>
-__device__ __forceinline__ void bin_value(const StepArgs<T>& a, const Lds& s, int q, T kx, T ky) {
-    const int r = cell_coord<T>(kx, a.lk, a.dk, a.inv_dk);
-    const int l = cell_coord<T>(ky, a.lk, a.dk, a.inv_dk);
-    if (r < 0 || l < 0 || r >= a.nk || l >= a.nk) {
-        atomicAdd(&s.cnt[SGPM_CNT_OUT_OF_GRID], 1u);
+__device__ __forceinline__ void k1_bin(const K1Args<T>& a, const K1Lds<T>& L, const Consts<T>& c,
+                                       int q, T kx, T ky) {
+    const int r = cell_coord<T>(kx, c.lk, c.dk, c.inv_dk);
+    const int l = cell_coord<T>(ky, c.lk, c.dk, c.inv_dk);
+    if (r < 0 || l < 0 || r >= c.nk || l >= c.nk) {
+        atomicAdd(&L.cnt[SGPM_CNT_OUT_OF_GRID], 1u);
         return;
     }
     const int wr = r - a.win_r0, wl = l - a.win_l0;
-    if (wr >= 0 && wr < a.win && wl >= 0 && wl < a.win) {
+    if ((unsigned)wr < (unsigned)a.win && (unsigned)wl < (unsigned)a.win) {
         const int idx = (q * a.win + wr) * a.win + wl;
-        atomicAdd(&s.hwin[idx >> 1], (idx & 1) ? 65536u : 1u);
+        atomicAdd(&L.hwin[idx >> 1], (idx & 1) ? 65536u : 1u);
     } else {
-        const uint32_t old = atomicAdd(&a.h_acc[(size_t)q * a.nk * a.nk + (size_t)r * a.nk + l], 1u);
-        atomicMax(&s.wgmax[q], old + 1u);
+        atomicAdd(&a.h_acc[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l], 1u);
     }
 }
 
-// Evaluate the nodes of one particle's coefficients and add its nodal
-// values to the histogram and to the per-wave moment sums.  Must be called
-// by every lane of the wave (active = false contributes nothing).
-template <typename T, int PMAX>
-__device__ __forceinline__ void finalize_particle(const StepArgs<T>& a, const Lds& s,
-                                                  const T (&cx)[PMAX], const T (&cy)[PMAX],
-                                                  bool active) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int q = 0; q < a.Q; ++q) {
-        const T* ps = a.tab.psi + q * a.P;
-        T kx = (T)0, ky = (T)0;
-#pragma unroll
-        for (int h = 0; h < PMAX; ++h)
-            if (h < a.P) { kx += cx[h] * ps[h]; ky += cy[h] * ps[h]; }
-        double vx = 0.0, vy = 0.0, en = 0.0;
-        if (active) {
-            const T e = sqrt(kx * kx + ky * ky + a.tab.eps0sq[q]);
-            vx = (double)(a.v_f * kx / e);
-            vy = (double)(a.v_f * ky / e);
-            en = (double)e;
-            bin_value<T>(a, s, q, kx, ky);
-        }
-        vx = wave_sum(vx); vy = wave_sum(vy); en = wave_sum(en);
-        if (lane == 0) {
-            double* m = s.macc + ((size_t)wave * a.Q + q) * 3;
-            m[0] += vx; m[1] += vy; m[2] += en;
-        }
-    }
-}
-
-template <typename T, int PMAX>
-__device__ __forceinline__ void load_drift(const StepArgs<T>& a, int64_t i, T (&cx)[PMAX],
-                                           T (&cy)[PMAX]) {
-#pragma unroll
-    for (int h = 0; h < PMAX; ++h) {
-        if (h < a.P) {
-            cx[h] = a.kx[(size_t)h * a.n + i];
-            cy[h] = a.ky[(size_t)h * a.n + i];
-            if (a.do_drift) cx[h] -= a.drift[h];   // k_h^{n+1} = k_h^n - (e/hbar) dt E_h
-        } else {
-            cx[h] = (T)0; cy[h] = (T)0;
-        }
-    }
-}
-
-// Pauli occupation f = H^n / max H^n at the candidate's cell on the grid
-// moved with this step's drift (lookup at k' + v_F E(z_q) dt x^).
-template <typename T>
-__device__ __forceinline__ T pauli_f(const StepArgs<T>& a, int q, T px, T py) {
-    const uint32_t mx = a.hmax_read[q];
-    if (mx == 0u) return (T)0;
-    const T shift = a.tab.vfield[q] * a.dt;
-    const int r = cell_coord<T>(px + shift, a.lk, a.dk, a.inv_dk);
-    const int l = cell_coord<T>(py, a.lk, a.dk, a.inv_dk);
-    if (r < 0 || l < 0 || r >= a.nk || l >= a.nk) return (T)0;
-    const uint32_t h = a.h_read[(size_t)q * a.nk * a.nk + (size_t)r * a.nk + l];
-    return (T)h / (T)mx;
-}
-
-// Exact collision loop of one particle (Algorithm 2 inner while-loop); the
-// coefficients (already drifted) are updated in place.
-template <typename T, int PMAX>
-__device__ void collide(const StepArgs<T>& a, const Lds& s, int64_t i, T (&cx)[PMAX],
-                        T (&cy)[PMAX]) {
-    T tc = (T)0;
-    uint32_t c = 0;
-    const uint32_t ctr0 = (uint32_t)i;
-    for (;;) {
-        // Gamma~ = (1 + alpha) max_q sum_nu Gamma^nu(z_q)
-        T smax = (T)0;
-        for (int q = 0; q < a.Q; ++q) {
-            const T* ps = a.tab.psi + q * a.P;
-            T kx = (T)0, ky = (T)0;
-#pragma unroll
-            for (int h = 0; h < PMAX; ++h)
-                if (h < a.P) { kx += cx[h] * ps[h]; ky += cy[h] * ps[h]; }
-            const T e = sqrt(kx * kx + ky * ky + a.tab.eps0sq[q]);
-            T r[5];
-            phonon_rates<T>(a, e, a.tab.eps0[q], r);
-            T sum = (T)0;
-#pragma unroll
-            for (int m = 0; m < 5; ++m) sum += r[m];
-            sum += edge_rate<T>(a, q, kx, ky, e);
-            smax = sum > smax ? sum : smax;
-        }
-        const T G = a.alpha1 * smax;
-        const Words wx = philox10(ctr0, a.step, (c << 8) | kPurXi, a.instance, a.seed_lo, a.seed_hi);
-        const T xi = uni<T>(wx.w0, wx.w1);
-        const T dtc = -dlog(xi) / G;            // free flight, eq. dt with the node maximum
-        if (!(tc + dtc < a.dt)) break;
-        atomicAdd(&s.cnt[SGPM_CNT_COLLISIONS], 1u);
-
-        const Words ws = philox10(ctr0, a.step, (c << 8) | kPurSel, a.instance, a.seed_lo, a.seed_hi);
-        const T su = uni<T>(ws.w0, ws.w1), eta = uni<T>(ws.w2, ws.w3);
-        const Words wa = philox10(ctr0, a.step, (c << 8) | kPurAng, a.instance, a.seed_lo, a.seed_hi);
-        const T u1 = uni<T>(wa.w0, wa.w1), u2 = uni<T>(wa.w2, wa.w3);
-        // AC angle: twice the polar angle of a uniform point of the unit disk
-        // centred at (1,0) (density 1 + cos); cos/sin by the double angle.
-        T s_phi, c_phi;
-        dsincospi((T)2 * u2, &s_phi, &c_phi);
-        const T rr = sqrt(u1);
-        const T dx = (T)1 + rr * c_phi, dy = rr * s_phi;
-        const T n2 = dx * dx + dy * dy;
-        const T cac = (dx * dx - dy * dy) / n2, sac = ((T)2 * dx * dy) / n2;
-        T sop, cop;
-        dsincospi((T)2 * u1, &sop, &cop);       // OP angle 2 pi u1
-
-        T ax[PMAX], ay[PMAX];
-#pragma unroll
-        for (int h = 0; h < PMAX; ++h) { ax[h] = (T)0; ay[h] = (T)0; }
-        uint32_t nev = 0, nrej = 0, nexh = 0;
-        for (int q = 0; q < a.Q; ++q) {
-            const T* ps = a.tab.psi + q * a.P;
-            T kx = (T)0, ky = (T)0;
-#pragma unroll
-            for (int h = 0; h < PMAX; ++h)
-                if (h < a.P) { kx += cx[h] * ps[h]; ky += cy[h] * ps[h]; }
-            const T e0 = a.tab.eps0[q];
-            const T e = sqrt(kx * kx + ky * ky + a.tab.eps0sq[q]);
-            T r[5];
-            phonon_rates<T>(a, e, e0, r);
-            int ell = 7;
-            T cum = (T)0;
-#pragma unroll
-            for (int m = 0; m < 5; ++m) {
-                cum += r[m];
-                if (ell == 7 && su < cum / G) ell = m + 1;
-            }
-            if (ell == 7) {
-                cum += edge_rate<T>(a, q, kx, ky, e);
-                if (su < cum / G) ell = 6;
-            }
-            T nx = kx, ny = ky;
-            if (ell != 7) {
-                const T kabs = sqrt(kx * kx + ky * ky);
-                const T cin = kabs > (T)0 ? kx / kabs : (T)1;
-                const T sin_ = kabs > (T)0 ? ky / kabs : (T)0;
-                T px, py;
-                bool ok = true;
-                if (ell == 6) {
-                    // absolute final angle, density exp(-kap (cos t' - cos t_in)^2)
-                    const T kap = a.edge_kap * (kx * kx + ky * ky);
-                    ok = false;
-                    for (uint32_t j = 0; j < (uint32_t)kEdgeTries; ++j) {
-                        const Words we = philox10(ctr0, a.step, (c << 8) | (kPurEdge0 + j),
-                                                  a.instance, a.seed_lo, a.seed_hi);
-                        const T ut = uni<T>(we.w0, we.w1), v = uni<T>(we.w2, we.w3);
-                        T st, ct;
-                        dsincospi((T)2 * ut, &st, &ct);
-                        const T d = ct - cin;
-                        if (v < dexp(-kap * d * d)) {
-                            px = kabs * ct; py = kabs * st;
-                            ok = true;
-                            break;
-                        }
-                    }
-                    if (!ok) ++nexh;
-                } else {
-                    T ct, st, mag;
-                    if (ell == 1) { ct = cac; st = sac; mag = kabs; }
-                    else {
-                        const bool op = (ell == 2 || ell == 3);
-                        const T hw = op ? a.hw_o : a.hw_k;
-                        const T de = (ell == 2 || ell == 4) ? -hw : hw;
-                        if (op) { ct = cop; st = sop; } else { ct = -cac; st = -sac; }
-                        if (a.final_state == 1) {
-                            mag = kabs + de;
-                        } else {
-                            const T e1 = e + de;     // energy-conserving final state
-                            mag = sqrt((e1 - e0) * (e1 + e0));
-                        }
-                    }
-                    px = mag * (ct * cin - st * sin_);
-                    py = mag * (st * cin + ct * sin_);
-                }
-                if (ok) {
-                    ++nev;
-                    const T f = a.pauli ? pauli_f<T>(a, q, px, py) : (T)0;
-                    if (f < eta) { nx = px; ny = py; } else { ++nrej; }
-                }
-            }
-            const T* wp = a.tab.wpsi + q * a.P;
-#pragma unroll
-            for (int h = 0; h < PMAX; ++h)
-                if (h < a.P) { ax[h] += wp[h] * nx; ay[h] += wp[h] * ny; }
-        }
-        if (nev) atomicAdd(&s.cnt[SGPM_CNT_EVENTS], nev);
-        if (nrej) atomicAdd(&s.cnt[SGPM_CNT_PAULI_REJ], nrej);
-        if (nexh) atomicAdd(&s.cnt[SGPM_CNT_EDGE_EXH], nexh);
-#pragma unroll
-        for (int h = 0; h < PMAX; ++h) { cx[h] = ax[h]; cy[h] = ay[h]; }
-        tc += dtc;
-        ++c;
-        if (c >= (uint32_t)a.c_max) { atomicAdd(&s.cnt[SGPM_CNT_CMAX], 1u); break; }
-    }
-}
-
-// Run the exact collision loop on the first m queued candidates, one per lane.
-template <typename T, int PMAX>
-__device__ void process_queue(const StepArgs<T>& a, const Lds& s, int64_t begin, int m) {
-    const int tid = threadIdx.x;
-    const bool has = tid < m;
-    const int64_t i = has ? begin + s.queue[tid] : begin;
-    T cx[PMAX], cy[PMAX];
-    load_drift<T, PMAX>(a, i, cx, cy);
-    if (has) {
-        collide<T, PMAX>(a, s, i, cx, cy);
-#pragma unroll
-        for (int h = 0; h < PMAX; ++h)
-            if (h < a.P) { a.kx[(size_t)h * a.n + i] = cx[h]; a.ky[(size_t)h * a.n + i] = cy[h]; }
-    }
-    finalize_particle<T, PMAX>(a, s, cx, cy, has);
-}
-
-template <typename T, int PMAX>
-__global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs<T> a) {
+template <typename T, int PMAX, int QMAX>
+__global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T> a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    size_t oq, om, ow, oc;
-    lds_offsets(a.Q, a.hwin_words, &oq, &om, &ow, &oc);
-    Lds s;
-    s.hwin = reinterpret_cast<uint32_t*>(smem);
-    s.queue = reinterpret_cast<int*>(smem + oq);
-    s.macc = reinterpret_cast<double*>(smem + om);
-    s.wgmax = reinterpret_cast<uint32_t*>(smem + ow);
-    s.cnt = reinterpret_cast<uint32_t*>(smem + oc);
-    uint32_t* qlen = s.cnt + 8;
-    const int tid = threadIdx.x;
+    const int P = a.P, Q = a.Q;
+    const K1Lds<T> L = k1_lds<T>(smem, P, Q, a.hwin_words);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    for (int w = tid; w < a.hwin_words; w += kBlock) s.hwin[w] = 0u;
-    for (int w = tid; w < kWaves * a.Q * 3; w += kBlock) s.macc[w] = 0.0;
-    for (int w = tid; w < a.Q; w += kBlock) s.wgmax[w] = 0u;
-    if (tid < 16) s.cnt[tid] = 0u;
-
-    // clear the stale histogram buffer (it accumulates the next step)
-    {
-        uint4* hc = reinterpret_cast<uint4*>(a.h_clr);
-        const uint4 z = make_uint4(0u, 0u, 0u, 0u);
-        for (int64_t k = (int64_t)blockIdx.x * kBlock + tid; k < a.clear_vec4;
-             k += (int64_t)gridDim.x * kBlock)
-            hc[k] = z;
-        if (blockIdx.x == 0)
-            for (int w = tid; w < a.Q; w += kBlock) a.hmax_clr[w] = 0u;
+    for (int w = tid; w < a.hwin_words; w += kBlock1) L.hwin[w] = 0u;
+    if (tid == 0) *L.c = *a.tab.consts;
+    for (int k = tid; k < Q * P; k += kBlock1) L.psi[k] = a.tab.psi[k];
+    for (int k = tid; k < Q; k += kBlock1) L.eps0sq[k] = a.tab.eps0sq[k];
+    for (int k = tid; k < P; k += kBlock1) {
+        L.psimax[k] = a.tab.psimax[k];
+        L.drift[k] = a.do_drift ? (T)(a.vfdt * a.ehat[k]) : (T)0;
     }
+    for (int k = tid; k < kWaves1 * Q * 3; k += kBlock1) L.red[k] = 0.0;
+    if (tid < 16) L.cnt[tid] = 0u;
     __syncthreads();
+    const Consts<T>& c = *L.c;
 
     const int64_t begin = (int64_t)blockIdx.x * a.chunk;
     const int64_t end = begin + a.chunk < a.n ? begin + a.chunk : a.n;
-    const T vdt_margin = a.dt;
+    int* my_cand = a.cand_idx + ((size_t)blockIdx.x * kWaves1 + wave) * a.cap_w;
+    int ncand = 0;     // uniform per wave
 
-    for (int64_t base = begin; base < end; base += kBlock) {
+    double acc[QMAX > 0 ? QMAX : 1][3];
+    if constexpr (QMAX > 0) {
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) { acc[q][0] = 0.0; acc[q][1] = 0.0; acc[q][2] = 0.0; }
+    }
+
+    for (int64_t base = begin; base < end; base += kBlock1) {
         const int64_t i = base + tid;
         const bool act = i < end;
+        const int64_t ii = act ? i : begin;
         T cx[PMAX], cy[PMAX];
-        load_drift<T, PMAX>(a, act ? i : begin, cx, cy);
+#pragma unroll
+        for (int h = 0; h < PMAX; ++h) {
+            if (h < P) {
+                cx[h] = a.kx[(size_t)h * a.n + ii] - L.drift[h];   // k_h -= (e/hbar) dt E_h
+                cy[h] = a.ky[(size_t)h * a.n + ii];
+            } else {
+                cx[h] = (T)0; cy[h] = (T)0;
+            }
+        }
         bool cand = false;
         if (act && a.do_collide) {
-            // largest nodal energy -> rigorous rate bound -> can this particle
-            // collide in this step at all?  (no collision iff -log xi / G >= dt)
-            T e2max = (T)0;
-            for (int q = 0; q < a.Q; ++q) {
-                const T* ps = a.tab.psi + q * a.P;
-                T kx = (T)0, ky = (T)0;
-#pragma unroll
-                for (int h = 0; h < PMAX; ++h)
-                    if (h < a.P) { kx += cx[h] * ps[h]; ky += cy[h] * ps[h]; }
-                const T e2 = kx * kx + ky * ky + a.tab.eps0sq[q];
-                e2max = e2 > e2max ? e2 : e2max;
-            }
-            const T gb = rate_bound<T>(a, sqrt(e2max));
-            const Words wx = philox10((uint32_t)i, a.step, kPurXi, a.instance, a.seed_lo, a.seed_hi);
-            const T xlog = -dlog(uni<T>(wx.w0, wx.w1));
-            cand = !(xlog >= gb * vdt_margin);
-        }
-        if (act && !cand && a.do_drift) {
+            // |k(z_q)| <= sum_h |k_h| max_q |Psi_h(z_q)| per component
+            T bx = (T)0, by = (T)0;
 #pragma unroll
             for (int h = 0; h < PMAX; ++h)
-                if (h < a.P && ((a.drift_mask >> h) & 1u)) a.kx[(size_t)h * a.n + i] = cx[h];
+                if (h < P) { bx += fabs(cx[h]) * L.psimax[h]; by += fabs(cy[h]) * L.psimax[h]; }
+            const T emax = sqrt(bx * bx + by * by + c.eps0max_sq);
+            const T gb = rate_bound<T>(c, emax);
+            const Words wx = philox10((uint32_t)i, a.step, kPurXi, a.instance, a.seed_lo, a.seed_hi);
+            const T xlog = -dlog(uni<T>(wx.w0, wx.w1));
+            cand = !(xlog >= gb * a.dt);    // no collision iff -log(xi)/G~ >= dt
         }
-        finalize_particle<T, PMAX>(a, s, cx, cy, act && !cand);
+        const bool fin = act && !cand;
+        if (fin && a.do_drift) {
+#pragma unroll
+            for (int h = 0; h < PMAX; ++h)
+                if (h < P && L.drift[h] != (T)0) a.kx[(size_t)h * a.n + i] = cx[h];
+        }
+        // candidates of this wave, in lane order
+        const uint64_t mask = __ballot(cand);
         if (cand) {
-            const uint32_t slot = atomicAdd(qlen, 1u);
-            s.queue[slot] = (int)(i - begin);
-            atomicAdd(&s.cnt[SGPM_CNT_CANDIDATES], 1u);
+            const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+            my_cand[ncand + pos] = (int)(i - begin);
         }
-        __syncthreads();
-        const int pending = (int)*qlen;
-        if (pending >= kBlock) {
-            process_queue<T, PMAX>(a, s, begin, kBlock);
-            const int rest = pending - kBlock;
-            int moved = 0;
-            if (tid < rest) moved = s.queue[kBlock + tid];
-            __syncthreads();
-            if (tid < rest) s.queue[tid] = moved;
-            if (tid == 0) *qlen = (uint32_t)rest;
+        ncand += __popcll(mask);
+
+        // nodes of the particles that are final now
+        if constexpr (QMAX > 0) {
+#pragma unroll
+            for (int q = 0; q < QMAX; ++q) {
+                if (q < Q && fin) {
+                    const T* ps = L.psi + q * P;
+                    T kx = (T)0, ky = (T)0;
+#pragma unroll
+                    for (int h = 0; h < PMAX; ++h)
+                        if (h < P) { kx += cx[h] * ps[h]; ky += cy[h] * ps[h]; }
+                    const T e = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
+                    const T inv = (T)1 / e;
+                    acc[q][0] += (double)(c.v_f * kx * inv);
+                    acc[q][1] += (double)(c.v_f * ky * inv);
+                    acc[q][2] += (double)e;
+                    k1_bin<T>(a, L, c, q, kx, ky);
+                }
+            }
+        } else {
+            for (int q = 0; q < Q; ++q) {
+                double vx = 0.0, vy = 0.0, en = 0.0;
+                if (fin) {
+                    const T* ps = L.psi + q * P;
+                    T kx = (T)0, ky = (T)0;
+#pragma unroll
+                    for (int h = 0; h < PMAX; ++h)
+                        if (h < P) { kx += cx[h] * ps[h]; ky += cy[h] * ps[h]; }
+                    const T e = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
+                    const T inv = (T)1 / e;
+                    vx = (double)(c.v_f * kx * inv);
+                    vy = (double)(c.v_f * ky * inv);
+                    en = (double)e;
+                    k1_bin<T>(a, L, c, q, kx, ky);
+                }
+                vx = wave_sum(vx); vy = wave_sum(vy); en = wave_sum(en);
+                if (lane == 0) {
+                    double* m = L.red + ((size_t)wave * Q + q) * 3;
+                    m[0] += vx; m[1] += vy; m[2] += en;
+                }
+            }
         }
-        __syncthreads();
     }
-    {
-        const int pending = (int)*qlen;
-        if (pending > 0) process_queue<T, PMAX>(a, s, begin, pending);
+    if constexpr (QMAX > 0) {
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) {
+            if (q < Q) {
+                const double vx = wave_sum(acc[q][0]), vy = wave_sum(acc[q][1]),
+                             en = wave_sum(acc[q][2]);
+                if (lane == 0) {
+                    double* m = L.red + ((size_t)wave * Q + q) * 3;
+                    m[0] = vx; m[1] = vy; m[2] = en;
+                }
+            }
+        }
+    }
+    if (lane == 0) {
+        a.cand_cnt[(size_t)blockIdx.x * kWaves1 + wave] = ncand;
+        if (ncand) atomicAdd(&L.cnt[SGPM_CNT_CANDIDATES], (uint32_t)ncand);
     }
     __syncthreads();
 
-    // flush the LDS window: nonzero cells to global atomics, track the max
+    // flush the LDS window: nonzero cells to global atomics
     {
         const int wcells = a.win * a.win;
-        for (int w = tid; w < a.hwin_words; w += kBlock) {
-            const uint32_t v = s.hwin[w];
+        for (int w = tid; w < a.hwin_words; w += kBlock1) {
+            const uint32_t v = L.hwin[w];
             if (v == 0u) continue;
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
@@ -504,66 +365,411 @@ __global__ void __launch_bounds__(kBlock) step_kernel(const StepArgs<T> a) {
                 const int idx = 2 * w + half;
                 const int q = idx / wcells, rem = idx - q * wcells;
                 const int r = a.win_r0 + rem / a.win, l = a.win_l0 + rem % a.win;
-                const uint32_t old =
-                    atomicAdd(&a.h_acc[(size_t)q * a.nk * a.nk + (size_t)r * a.nk + l], cnt);
-                atomicMax(&s.wgmax[q], old + cnt);
+                atomicAdd(&a.h_acc[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l], cnt);
             }
         }
     }
-    __syncthreads();
-    for (int q = tid; q < a.Q; q += kBlock)
-        if (s.wgmax[q]) atomicMax(&a.hmax_acc[q], s.wgmax[q]);
-    if (tid < 8 && s.cnt[tid]) atomicAdd(&a.counters[tid], (unsigned long long)s.cnt[tid]);
-
-    // per-workgroup moment partials, then the last workgroup reduces them in
-    // a fixed order into the batches of the record
-    for (int k = tid; k < a.Q * 3; k += kBlock) {
+    // this workgroup's moment sums, waves in order
+    for (int k = tid; k < Q * 3; k += kBlock1) {
         double v = 0.0;
-        for (int wv = 0; wv < kWaves; ++wv) v += s.macc[wv * a.Q * 3 + k];
-        a.partial[(size_t)blockIdx.x * a.Q * 3 + k] = v;
+        for (int wv = 0; wv < kWaves1; ++wv) v += L.red[wv * Q * 3 + k];
+        a.partial[(size_t)blockIdx.x * Q * 3 + k] = v;
     }
-    __threadfence();
-    __syncthreads();
-    __shared__ int is_last;
-    if (tid == 0) is_last = (atomicAdd(a.done, 1u) == (uint32_t)(gridDim.x - 1));
-    __syncthreads();
-    if (is_last) {
-        __threadfence();
-        const int per = a.Q * 3;
-        for (int k = tid; k < a.nb * per; k += kBlock) {
-            const int b = k / per, rem = k - b * per;
-            double v = 0.0;
-            for (int w = b; w < (int)gridDim.x; w += a.nb)
-                v += __hip_atomic_load(&a.partial[(size_t)w * per + rem], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            a.record[k] = v;
-        }
-        if (tid == 0) *a.done = 0u;
-    }
+    if (tid < 8 && L.cnt[tid]) atomicAdd(&a.counters[tid], (unsigned long long)L.cnt[tid]);
+}
+
+// ===================================================== K2: collider kernel
+size_t k2_lds_bytes(int P, int Q, int fp32) {
+    const size_t s = fp32 ? 4 : 8;
+    size_t off = sizeof(Consts<double>);
+    off = (off + 15) & ~(size_t)15;
+    off += s * (2 * (size_t)Q * P + 4 * (size_t)Q + 32 + P);   // psi wpsi eps0 eps0sq cedge vfield ecos drift
+    off = (off + 15) & ~(size_t)15;
+    off += (size_t)2 * kBlock * 3 * 8;   // final sums of a pass, [groups][Q][3]
+    off += (size_t)Q * 3 * 8;            // running sums
+    off += 16 * 4 + (kWaves1 + 1) * 4;   // counters, candidate offsets
+    return off;
+}
+
+template <typename T>
+struct K2Lds {
+    Consts<T>* c;
+    T* psi; T* wpsi; T* eps0; T* eps0sq; T* cedge; T* vfield; T* ecos; T* drift;
+    double* pass;   // [groups per pass][Q][3]
+    double* run;    // [Q][3]
+    uint32_t* cnt;
+    int* off;       // [kWaves1 + 1]
+};
+
+template <typename T>
+__device__ __forceinline__ K2Lds<T> k2_lds(unsigned char* smem, int P, int Q) {
+    K2Lds<T> L;
+    size_t off = 0;
+    L.c = reinterpret_cast<Consts<T>*>(smem);
+    off = sizeof(Consts<double>);
+    off = (off + 15) & ~(size_t)15;
+    L.psi = reinterpret_cast<T*>(smem + off);
+    L.wpsi = L.psi + Q * P;
+    L.eps0 = L.wpsi + Q * P;
+    L.eps0sq = L.eps0 + Q;
+    L.cedge = L.eps0sq + Q;
+    L.vfield = L.cedge + Q;
+    L.ecos = L.vfield + Q;
+    L.drift = L.ecos + 32;
+    off += sizeof(T) * (2 * (size_t)Q * P + 4 * (size_t)Q + 32 + P);
+    off = (off + 15) & ~(size_t)15;
+    L.pass = reinterpret_cast<double*>(smem + off);
+    off += (size_t)2 * kBlock * 3 * 8;
+    L.run = reinterpret_cast<double*>(smem + off);
+    off += (size_t)Q * 3 * 8;
+    L.cnt = reinterpret_cast<uint32_t*>(smem + off);
+    off += 16 * 4;
+    L.off = reinterpret_cast<int*>(smem + off);
+    return L;
+}
+
+// Pauli occupation f = H^n / max H^n of node q at the candidate's cell on the
+// grid moved with this step's drift (lookup at k' + v_F E(z_q) dt x^)
+template <typename T>
+__device__ __forceinline__ T pauli_f(const K2Args<T>& a, const K2Lds<T>& L, const Consts<T>& c,
+                                     int q, T px, T py) {
+    const uint32_t mx = a.hmax_read[q];
+    if (mx == 0u) return (T)0;
+    const T shift = L.vfield[q] * a.dt;
+    const int r = cell_coord<T>(px + shift, c.lk, c.dk, c.inv_dk);
+    const int l = cell_coord<T>(py, c.lk, c.dk, c.inv_dk);
+    if (r < 0 || l < 0 || r >= c.nk || l >= c.nk) return (T)0;
+    const uint32_t h = a.h_read[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l];
+    return (T)h / (T)mx;
 }
 
 template <typename T, int PMAX>
-static int launch_step_t(const StepArgs<T>& a, void* stream) {
-    const size_t lds = step_lds_bytes(a.Q, a.hwin_words);
-    hipLaunchKernelGGL((step_kernel<T, PMAX>), dim3(a.nwg), dim3(kBlock), lds,
+__global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T> a) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int P = a.P, Q = a.Q, G = a.G;
+    const K2Lds<T> L = k2_lds<T>(smem, P, Q);
+    const int tid = threadIdx.x;
+    const int wg = blockIdx.x;
+
+    if (tid == 0) {
+        int s = 0;
+        for (int w = 0; w < kWaves1; ++w) {
+            L.off[w] = s;
+            s += a.cand_cnt[(size_t)wg * kWaves1 + w];
+        }
+        L.off[kWaves1] = s;
+    }
+    __syncthreads();
+    const int M = L.off[kWaves1];
+    if (M == 0) return;
+
+    if (tid == 0) *L.c = *a.tab.consts;
+    for (int k = tid; k < Q * P; k += kBlock) { L.psi[k] = a.tab.psi[k]; L.wpsi[k] = a.tab.wpsi[k]; }
+    for (int k = tid; k < Q; k += kBlock) {
+        L.eps0[k] = a.tab.eps0[k]; L.eps0sq[k] = a.tab.eps0sq[k];
+        L.cedge[k] = a.tab.cedge[k]; L.vfield[k] = a.tab.vfield[k];
+    }
+    for (int k = tid; k <= kEdgePts / 2; k += kBlock) L.ecos[k] = a.tab.edge_cos[k];
+    for (int k = tid; k < P; k += kBlock) L.drift[k] = (T)(a.vfdt * a.ehat[k]);
+    for (int k = tid; k < Q * 3; k += kBlock) L.run[k] = 0.0;
+    if (tid < 16) L.cnt[tid] = 0u;
+    __syncthreads();
+    const Consts<T>& c = *L.c;
+
+    const int g = tid % G;                // rank in the group = node handled
+    const int grp = tid / G;
+    const int per_pass = kBlock / G;
+    const int64_t begin = (int64_t)wg * a.chunk;
+
+    for (int p0 = 0; p0 < M; p0 += per_pass) {
+        const int cid = p0 + grp;
+        const bool has = cid < M;
+        int64_t i = begin;
+        if (has) {
+            int w = 0;
+            while (cid >= L.off[w + 1]) ++w;
+            i = begin + a.cand_idx[((size_t)wg * kWaves1 + w) * a.cap_w + (cid - L.off[w])];
+        }
+        T cx[PMAX], cy[PMAX];
+#pragma unroll
+        for (int h = 0; h < PMAX; ++h) {
+            if (h < P) {
+                cx[h] = a.kx[(size_t)h * a.n + i] - L.drift[h];
+                cy[h] = a.ky[(size_t)h * a.n + i];
+            } else {
+                cx[h] = (T)0; cy[h] = (T)0;
+            }
+        }
+        if (has) {
+            T tc = (T)0;
+            uint32_t coll = 0;
+            const uint32_t ctr0 = (uint32_t)i;
+            for (;;) {
+                // Gamma~ = (1 + alpha) max over the nodes of sum_nu Gamma^nu
+                T smax = (T)0;
+                for (int q = g; q < Q; q += G) {
+                    const T* ps = L.psi + q * P;
+                    T kx = (T)0, ky = (T)0;
+#pragma unroll
+                    for (int h = 0; h < PMAX; ++h)
+                        if (h < P) { kx += cx[h] * ps[h]; ky += cy[h] * ps[h]; }
+                    const T e = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
+                    T r[5];
+                    phonon_rates<T>(c, e, L.eps0[q], r);
+                    T sum = (T)0;
+#pragma unroll
+                    for (int m = 0; m < 5; ++m) sum += r[m];
+                    sum += edge_rate<T>(c, L.ecos, L.cedge[q], L.eps0[q], kx, ky, e);
+                    smax = sum > smax ? sum : smax;
+                }
+                smax = group_max<T>(smax, G);
+                const T Gt = c.alpha1 * smax;
+                const Words wx = philox10(ctr0, a.step, (coll << 8) | kPurXi, a.instance, a.seed_lo,
+                                          a.seed_hi);
+                const T dtc = -dlog(uni<T>(wx.w0, wx.w1)) / Gt;   // eq. dt, node maximum
+                if (!(tc + dtc < a.dt)) break;
+                if (g == 0) atomicAdd(&L.cnt[SGPM_CNT_COLLISIONS], 1u);
+
+                const Words ws = philox10(ctr0, a.step, (coll << 8) | kPurSel, a.instance, a.seed_lo,
+                                          a.seed_hi);
+                const T su = uni<T>(ws.w0, ws.w1), eta = uni<T>(ws.w2, ws.w3);
+                const Words wa = philox10(ctr0, a.step, (coll << 8) | kPurAng, a.instance, a.seed_lo,
+                                          a.seed_hi);
+                const T u1 = uni<T>(wa.w0, wa.w1), u2 = uni<T>(wa.w2, wa.w3);
+                // AC angle: twice the polar angle of a uniform point of the unit
+                // disk centred at (1,0) (density 1 + cos), by the double angle
+                T s_phi, c_phi;
+                dsincospi((T)2 * u2, &s_phi, &c_phi);
+                const T rr = sqrt(u1);
+                const T dx = (T)1 + rr * c_phi, dy = rr * s_phi;
+                const T n2 = dx * dx + dy * dy;
+                const T cac = (dx * dx - dy * dy) / n2, sac = ((T)2 * dx * dy) / n2;
+                T sop, cop;
+                dsincospi((T)2 * u1, &sop, &cop);    // OP angle 2 pi u1
+
+                T px_new[PMAX], py_new[PMAX];
+#pragma unroll
+                for (int h = 0; h < PMAX; ++h) { px_new[h] = (T)0; py_new[h] = (T)0; }
+                uint32_t nev = 0, nrej = 0, nexh = 0;
+                for (int q = g; q < Q; q += G) {
+                    const T* ps = L.psi + q * P;
+                    T kx = (T)0, ky = (T)0;
+#pragma unroll
+                    for (int h = 0; h < PMAX; ++h)
+                        if (h < P) { kx += cx[h] * ps[h]; ky += cy[h] * ps[h]; }
+                    const T e0 = L.eps0[q];
+                    const T e = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
+                    T r[5];
+                    phonon_rates<T>(c, e, e0, r);
+                    int ell = 7;
+                    T cum = (T)0;
+#pragma unroll
+                    for (int m = 0; m < 5; ++m) {
+                        cum += r[m];
+                        if (ell == 7 && su < cum / Gt) ell = m + 1;
+                    }
+                    if (ell == 7) {
+                        cum += edge_rate<T>(c, L.ecos, L.cedge[q], e0, kx, ky, e);
+                        if (su < cum / Gt) ell = 6;
+                    }
+                    T nx = kx, ny = ky;
+                    if (ell != 7) {
+                        const T kabs = sqrt(kx * kx + ky * ky);
+                        const T cin = kabs > (T)0 ? kx / kabs : (T)1;
+                        const T sin_ = kabs > (T)0 ? ky / kabs : (T)0;
+                        T px = kx, py = ky;
+                        bool ok = true;
+                        if (ell == 6) {
+                            // absolute final angle, density exp(-kap (cos t' - cos t_in)^2)
+                            const T kap = c.edge_kap * (kx * kx + ky * ky);
+                            ok = false;
+                            for (uint32_t j = 0; j < (uint32_t)kEdgeTries; ++j) {
+                                const Words we = philox10(ctr0, a.step, (coll << 8) | (kPurEdge0 + j),
+                                                          a.instance, a.seed_lo, a.seed_hi);
+                                const T ut = uni<T>(we.w0, we.w1), v = uni<T>(we.w2, we.w3);
+                                T st, ct;
+                                dsincospi((T)2 * ut, &st, &ct);
+                                const T d = ct - cin;
+                                if (v < dexp(-kap * d * d)) {
+                                    px = kabs * ct; py = kabs * st;
+                                    ok = true;
+                                    break;
+                                }
+                            }
+                            if (!ok) ++nexh;
+                        } else {
+                            T ct, st, mag;
+                            if (ell == 1) { ct = cac; st = sac; mag = kabs; }
+                            else {
+                                const bool op = (ell == 2 || ell == 3);
+                                const T hw = op ? c.hw_o : c.hw_k;
+                                const T de = (ell == 2 || ell == 4) ? -hw : hw;
+                                if (op) { ct = cop; st = sop; } else { ct = -cac; st = -sac; }
+                                if (c.final_state == 1) {
+                                    mag = kabs + de;
+                                } else {
+                                    const T e1 = e + de;     // energy-conserving final state
+                                    mag = sqrt((e1 - e0) * (e1 + e0));
+                                }
+                            }
+                            px = mag * (ct * cin - st * sin_);
+                            py = mag * (st * cin + ct * sin_);
+                        }
+                        if (ok) {
+                            ++nev;
+                            const T f = c.pauli ? pauli_f<T>(a, L, c, q, px, py) : (T)0;
+                            if (f < eta) { nx = px; ny = py; } else { ++nrej; }
+                        }
+                    }
+                    const T* wp = L.wpsi + q * P;
+#pragma unroll
+                    for (int h = 0; h < PMAX; ++h)
+                        if (h < P) { px_new[h] += wp[h] * nx; py_new[h] += wp[h] * ny; }
+                }
+                if (nev) atomicAdd(&L.cnt[SGPM_CNT_EVENTS], nev);
+                if (nrej) atomicAdd(&L.cnt[SGPM_CNT_PAULI_REJ], nrej);
+                if (nexh) atomicAdd(&L.cnt[SGPM_CNT_EDGE_EXH], nexh);
+                // k_h = sum_q w_q Psi_h(z_q) k_q  (group sum over the nodes)
+#pragma unroll
+                for (int h = 0; h < PMAX; ++h) {
+                    if (h < P) {
+                        cx[h] = group_sum<T>(px_new[h], G);
+                        cy[h] = group_sum<T>(py_new[h], G);
+                    }
+                }
+                tc += dtc;
+                ++coll;
+                if (coll >= (uint32_t)c.c_max) {
+                    if (g == 0) atomicAdd(&L.cnt[SGPM_CNT_CMAX], 1u);
+                    break;
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < PMAX; ++h)
+                if (h < P && (h % G) == g) {
+                    a.kx[(size_t)h * a.n + i] = cx[h];
+                    a.ky[(size_t)h * a.n + i] = cy[h];
+                }
+        }
+        // final node values: H^{n+1} cells and the pass's sums per (candidate, node)
+        for (int q = g; q < Q; q += G) {
+            double vx = 0.0, vy = 0.0, en = 0.0;
+            if (has) {
+                const T* ps = L.psi + q * P;
+                T kx = (T)0, ky = (T)0;
+#pragma unroll
+                for (int h = 0; h < PMAX; ++h)
+                    if (h < P) { kx += cx[h] * ps[h]; ky += cy[h] * ps[h]; }
+                const T e = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
+                const T inv = (T)1 / e;
+                const int r = cell_coord<T>(kx, c.lk, c.dk, c.inv_dk);
+                const int l = cell_coord<T>(ky, c.lk, c.dk, c.inv_dk);
+                if (r < 0 || l < 0 || r >= c.nk || l >= c.nk)
+                    atomicAdd(&L.cnt[SGPM_CNT_OUT_OF_GRID], 1u);
+                else
+                    atomicAdd(&a.h_acc[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l], 1u);
+                vx = (double)(c.v_f * kx * inv);
+                vy = (double)(c.v_f * ky * inv);
+                en = (double)e;
+            }
+            double* dst = L.pass + ((size_t)grp * Q + q) * 3;
+            dst[0] = vx; dst[1] = vy; dst[2] = en;
+        }
+        __syncthreads();
+        // running sums per node, candidates in list order
+        for (int k = tid; k < Q * 3; k += kBlock) {
+            const int q = k / 3, o = k % 3;
+            double s = L.run[k];
+            for (int gg = 0; gg < per_pass && p0 + gg < M; ++gg) s += L.pass[((size_t)gg * Q + q) * 3 + o];
+            L.run[k] = s;
+        }
+        __syncthreads();
+    }
+    // add the candidates' sums to the stream workgroup's partial sums
+    for (int k = tid; k < Q * 3; k += kBlock) a.partial[(size_t)wg * Q * 3 + k] += L.run[k];
+    if (tid < 8 && L.cnt[tid]) atomicAdd(&a.counters[tid], (unsigned long long)L.cnt[tid]);
+}
+
+// ===================================================== K3: finalize kernel
+__global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args a) {
+    const int q = blockIdx.x, tid = threadIdx.x;
+    const size_t cells = (size_t)a.nk * a.nk;
+    const uint32_t* h = a.h_acc + (size_t)q * cells;
+    uint32_t* z = a.h_clr + (size_t)q * cells;
+    uint32_t m = 0;
+    for (size_t k = tid; k < cells; k += kBlock) {
+        const uint32_t v = h[k];
+        m = v > m ? v : m;
+        z[k] = 0u;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint32_t o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+    }
+    __shared__ uint32_t wm[kWaves];
+    if ((tid & 63) == 0) wm[tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t mm = 0;
+        for (int w = 0; w < kWaves; ++w) mm = wm[w] > mm ? wm[w] : mm;
+        a.hmax_out[q] = mm;
+    }
+    // moment record: batch b collects the workgroups w = b (mod NB), in order
+    for (int k = tid; k < a.nb * 3; k += kBlock) {
+        const int b = k / 3, o = k % 3;
+        double s = 0.0;
+        for (int w = b; w < a.nwg; w += a.nb) s += a.partial[((size_t)w * a.Q + q) * 3 + o];
+        a.record[((size_t)b * a.Q + q) * 3 + o] = s;
+    }
+}
+
+// ------------------------------------------------------------ launchers
+template <typename T, int PMAX, int QMAX>
+static int launch_k1_t(const K1Args<T>& a, int nwg, void* stream) {
+    const size_t lds = k1_lds_bytes(a.P, a.Q, sizeof(T) == 4, a.hwin_words);
+    hipLaunchKernelGGL((k1_stream<T, PMAX, QMAX>), dim3(nwg), dim3(kBlock1), lds,
                        (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 
-int launch_step_f64(const StepArgs<double>& a, int pmax, void* stream) {
-    if (pmax <= 1) return launch_step_t<double, 1>(a, stream);
-    if (pmax <= 4) return launch_step_t<double, 4>(a, stream);
-    if (pmax <= 8) return launch_step_t<double, 8>(a, stream);
-    if (pmax <= 16) return launch_step_t<double, 16>(a, stream);
-    return launch_step_t<double, 32>(a, stream);
+template <typename T, int PMAX>
+static int launch_k1_q(const K1Args<T>& a, int nwg, void* stream) {
+    if (a.Q <= 1) return launch_k1_t<T, PMAX, 1>(a, nwg, stream);
+    if (a.Q <= 8) return launch_k1_t<T, PMAX, 8>(a, nwg, stream);
+    if (a.Q <= 16) return launch_k1_t<T, PMAX, 16>(a, nwg, stream);
+    return launch_k1_t<T, PMAX, 0>(a, nwg, stream);
 }
 
-int launch_step_f32(const StepArgs<float>& a, int pmax, void* stream) {
-    if (pmax <= 1) return launch_step_t<float, 1>(a, stream);
-    if (pmax <= 4) return launch_step_t<float, 4>(a, stream);
-    if (pmax <= 8) return launch_step_t<float, 8>(a, stream);
-    if (pmax <= 16) return launch_step_t<float, 16>(a, stream);
-    return launch_step_t<float, 32>(a, stream);
+template <typename T>
+static int launch_k1_any(const K1Args<T>& a, int nwg, void* stream) {
+    if (a.P <= 1) return launch_k1_q<T, 1>(a, nwg, stream);
+    if (a.P <= 8) return launch_k1_q<T, 8>(a, nwg, stream);
+    if (a.P <= 16) return launch_k1_q<T, 16>(a, nwg, stream);
+    return launch_k1_q<T, 32>(a, nwg, stream);
+}
+
+int launch_k1_f64(const K1Args<double>& a, int nwg, void* s) { return launch_k1_any<double>(a, nwg, s); }
+int launch_k1_f32(const K1Args<float>& a, int nwg, void* s) { return launch_k1_any<float>(a, nwg, s); }
+
+template <typename T>
+static int launch_k2_any(const K2Args<T>& a, int nwg, void* stream) {
+    const size_t lds = k2_lds_bytes(a.P, a.Q, sizeof(T) == 4);
+    const dim3 grid(nwg), blk(kBlock);
+    const hipStream_t s = (hipStream_t)stream;
+    if (a.P <= 1) hipLaunchKernelGGL((k2_collide<T, 1>), grid, blk, lds, s, a);
+    else if (a.P <= 8) hipLaunchKernelGGL((k2_collide<T, 8>), grid, blk, lds, s, a);
+    else if (a.P <= 16) hipLaunchKernelGGL((k2_collide<T, 16>), grid, blk, lds, s, a);
+    else hipLaunchKernelGGL((k2_collide<T, 32>), grid, blk, lds, s, a);
+    return (int)hipGetLastError();
+}
+
+int launch_k2_f64(const K2Args<double>& a, int nwg, void* s) { return launch_k2_any<double>(a, nwg, s); }
+int launch_k2_f32(const K2Args<float>& a, int nwg, void* s) { return launch_k2_any<float>(a, nwg, s); }
+
+int launch_k3(const K3Args& a, void* stream) {
+    hipLaunchKernelGGL(k3_finalize, dim3(a.Q), dim3(kBlock), 0, (hipStream_t)stream, a);
+    return (int)hipGetLastError();
 }
 
 // -------------------------------------------------------- initial datum
@@ -588,7 +794,6 @@ __device__ double fd_inverse(const InitArgs& a, int q, uint64_t m) {
     const bool upper = m >= (1ull << 51);
     const double target = upper ? ((double)((1ull << 52) - 1ull - m) + 0.5) * 0x1p-52 * Z
                                 : ((double)m + 0.5) * 0x1p-52 * Z;
-    // panel j with lo[j] <= target < lo[j+1]  (or hi[j+1] <= target < hi[j])
     int j0 = 0, j1 = np - 1;
     while (j0 < j1) {
         const int mid = (j0 + j1 + 1) >> 1;
@@ -596,9 +801,10 @@ __device__ double fd_inverse(const InitArgs& a, int q, uint64_t m) {
         if (right) j0 = mid; else j1 = mid - 1;
     }
     const int j = j0;
-    double xa = e0 + j * a.cdf_h, xb = e0 + (j + 1) * a.cdf_h;
+    const double xa = e0 + j * a.cdf_h, xb = e0 + (j + 1) * a.cdf_h;
     double ba = xa, bb = xb;      // bracket
-    double fracv = upper ? (hi[j] - target) / (hi[j] - hi[j + 1]) : (target - lo[j]) / (lo[j + 1] - lo[j]);
+    double fracv = upper ? (hi[j] - target) / (hi[j] - hi[j + 1])
+                         : (target - lo[j]) / (lo[j + 1] - lo[j]);
     fracv = fmin(fmax(fracv, 0.0), 1.0);
     double e = xa + fracv * (xb - xa);
     for (int it = 0; it < 60; ++it) {
@@ -608,7 +814,7 @@ __device__ double fd_inverse(const InitArgs& a, int q, uint64_t m) {
         const double g = fd_w(e, a.mu, a.kT);
         double en = (g > 0.0) ? e - F / g : 0.5 * (ba + bb);
         if (!(en > ba && en < bb)) en = 0.5 * (ba + bb);
-        if (en == e || bb - ba <= 0.0) break;
+        if (en == e || !(bb > ba)) break;
         if (fabs(en - e) <= 2e-16 * e) { e = en; break; }
         e = en;
     }

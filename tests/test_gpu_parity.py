@@ -121,7 +121,7 @@ STEP_CASES = {
     "sg_2d_q64": (small_cfg(dim_z=2, degree=4, nodes_1d=8, gap_dim=0, gap0=0.3, gap_rel=0.15,
                             field_dim=1, field0=1.5e6, field_rel=0.2, n_particles=3_000), 25, None),
     "hot_field_small_grid": (small_cfg(dim_z=1, degree=2, nodes_1d=3, gap_dim=0, gap_rel=0.2,
-                                       field0=3e7, n_particles=5_000, nk=64, lk_eV=1.2), 120, 256),
+                                       field0=3e7, n_particles=5_000, nk=64, lk_eV=1.2), 120, 512),
     "pauli_off_literal": (small_cfg(dim_z=1, degree=3, nodes_1d=4, gap_dim=0, gap_rel=0.1,
                                     pauli=0, final_state=1, field0=5e6, n_particles=5_000), 80,
                           None),
@@ -179,7 +179,7 @@ def test_chunk_invariance(sg):
     cfg = small_cfg(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1, n_particles=30_000,
                     field0=2e6)
     states = []
-    for chunk in (256, 1024, 8192):
+    for chunk in (512, 1024, 8192):
         sim = sg.Simulation(cfg, max_steps=60)
         sim.set_chunk(chunk)
         sim.init_particles()
