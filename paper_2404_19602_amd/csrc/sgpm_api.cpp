@@ -38,7 +38,9 @@ struct Instance {
     // device pointers
     void* kx = nullptr;
     void* ky = nullptr;
-    uint32_t* H = nullptr;     // [3][hstride]
+    uint32_t* H = nullptr;     // [3][hstride] H^n for the Pauli lookups
+    uint32_t* extra = nullptr; // [hstride] overflow counts of H^{n+1}
+    uint32_t* slabs = nullptr; // [nwg_max][hwin_words] window slabs
     uint32_t* Hmax = nullptr;  // [3][64]
     double* partial = nullptr; // [nwg_max][Q][3]
     double* record = nullptr;  // [max_steps+1][NB][Q][3]
@@ -56,8 +58,8 @@ struct Instance {
     double* d_psimax = nullptr; float* f_psimax = nullptr;
     Consts<double>* d_consts = nullptr; Consts<float>* f_consts = nullptr;
     double* d_ehat = nullptr;
-    int* cand_idx = nullptr;   // [nwg][kWaves1][chunk / kWaves1]
-    int* cand_cnt = nullptr;   // [nwg][kWaves1]
+    int* cand = nullptr;       // [N] global candidate list
+    uint32_t* qc = nullptr;    // [2][2] candidate count and work head, by step parity
 };
 
 // Bytes of every device region of one instance, in carving order.
@@ -73,20 +75,28 @@ struct Layout {
     }
 };
 
+int64_t min_chunk(int64_t n) {
+    // at most kMaxStreamWG stream workgroups
+    int64_t c = (n + kMaxStreamWG - 1) / kMaxStreamWG;
+    c = (c + kBlock1 - 1) / kBlock1 * kBlock1;
+    return c < kBlock1 ? kBlock1 : c;
+}
+
 int64_t auto_chunk(int64_t n) {
-    // about two stream workgroups per compute unit, whole sub-tiles of 512
+    // about two stream workgroups per compute unit, whole sub-tiles
     int64_t c = (n + 511) / 512;
     c = (c + kBlock1 - 1) / kBlock1 * kBlock1;
-    if (c < kBlock1) c = kBlock1;
-    if (c > 32768) c = 32768;
+    if (c < min_chunk(n)) c = min_chunk(n);
+    if (c > kMaxChunk) c = kMaxChunk;
     return c;
 }
 
 // LDS histogram window of the stream kernel: the largest even square of
 // packed 16-bit counters per node that fits the budget left by the tables,
 // centred on the grid.
-void window_for(int P, int Q, int nk, bool fp32, int* win, int* r0, int* l0, int* words) {
-    const size_t fixed = k1_lds_bytes(P, Q, fp32 ? 1 : 0, 0) + 64;
+void window_for(int P, int Q, int nk, bool fp32, int chunk, int* win, int* r0, int* l0,
+                int* words) {
+    const size_t fixed = k1_lds_bytes(P, Q, fp32 ? 1 : 0, 0, chunk) + 64;
     const double room = fixed < (size_t)kLdsK1Bytes ? (double)(kLdsK1Bytes - fixed) : 0.0;
     int w = (int)std::floor(std::sqrt(room / (2.0 * Q)));
     w &= ~1;
@@ -95,7 +105,7 @@ void window_for(int P, int Q, int nk, bool fp32, int* win, int* r0, int* l0, int
     *win = w;
     *r0 = (nk - w) / 2;
     *l0 = (nk - w) / 2;
-    *words = (Q * w * w + 1) / 2;
+    *words = ((Q * w * w + 1) / 2 + 3) / 4 * 4;   // whole 16-byte slab rows
 }
 
 Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
@@ -104,14 +114,14 @@ Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
     const size_t s = d.precision == SGPM_FP32 ? 4 : 8;
     const size_t P = t.P, Q = t.Q, n = (size_t)d.n_particles;
     const size_t hstride = ((size_t)Q * d.nk * d.nk + 63) / 64 * 64;
-    const size_t nwg_max = (n + kBlock - 1) / kBlock;
+    const size_t nwg_max = std::min<size_t>((n + kBlock1 - 1) / kBlock1, (size_t)kMaxStreamWG);
     L.add(P * n * s);                                  // 0 kx
     L.add(P * n * s);                                  // 1 ky
     L.add(3 * hstride * 4);                            // 2 H
     L.add(3 * 64 * 4 * ((Q + 63) / 64));               // 3 Hmax
     L.add(nwg_max * Q * 3 * 8);                        // 4 partial
     L.add(((size_t)d.max_steps + 1) * kNumBatches * Q * 3 * 8);  // 5 record
-    L.add(64);                                         // 6 (spare)
+    L.add(64);                                         // 6 candidate counters
     L.add(SGPM_N_COUNTERS * 8);                        // 7 counters
     L.add((size_t)Q * kMaxBins * 8);                   // 8 bins
     L.add((P + 2) * 8);                                // 9 zpsi
@@ -127,8 +137,17 @@ Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
     L.add(P * 8); L.add(P * 4);                        // 27,28 psimax d/f
     L.add(sizeof(Consts<double>)); L.add(sizeof(Consts<float>));  // 29,30
     L.add(P * 8);                                      // 31 ehat
-    L.add(n_cand * 4);                                 // 32 cand_idx
-    L.add(((size_t)d.n_particles / kBlock1 + 2) * kWaves1 * 4);  // 33 cand_cnt
+    L.add(n_cand * 4);                                 // 32 candidate list
+    L.add(64);                                         // 33 (spare)
+    L.add(hstride * 4);                                // 34 overflow grid
+    {
+        int w, r0, l0, words;
+        window_for(t.P, t.Q, d.nk, d.precision == SGPM_FP32, (int)auto_chunk(d.n_particles), &w,
+                   &r0, &l0, &words);
+        size_t nwg_slab = ((size_t)d.n_particles + kBlock1 - 1) / kBlock1;
+        if (nwg_slab > (size_t)kMaxStreamWG) nwg_slab = kMaxStreamWG;
+        L.add(nwg_slab * (size_t)words * 4);          // 35 slabs
+    }
     return L;
 }
 
@@ -231,7 +250,7 @@ uint32_t* hmbuf(const Instance& I, int64_t k) {
 }
 
 template <typename T>
-K1Args<T> make_k1(const Instance& I, double dt, bool moving, int64_t step, uint32_t* h_acc) {
+K1Args<T> make_k1(const Instance& I, double dt, bool moving, int64_t step) {
     K1Args<T> a;
     std::memset(&a, 0, sizeof(a));
     a.kx = static_cast<T*>(I.kx);
@@ -245,15 +264,14 @@ K1Args<T> make_k1(const Instance& I, double dt, bool moving, int64_t step, uint3
     a.seed_hi = (uint32_t)(I.d.seed >> 32);
     a.instance = I.d.instance_id;
     a.step = (uint32_t)step;
-    a.h_acc = h_acc;
+    a.extra = I.extra;
+    a.slabs = I.slabs;
     a.win = I.win; a.win_r0 = I.win_r0; a.win_l0 = I.win_l0; a.hwin_words = I.hwin_words;
     a.partial = I.partial;
-    a.cand_idx = I.cand_idx;
-    a.cand_cnt = I.cand_cnt;
-    a.cap_w = (int)(I.chunk / kWaves1);
+    a.cand = I.cand;
+    a.cand_count = I.qc + 2 * (step & 1);
     a.counters = I.counters;
     a.chunk = I.chunk;
-    a.do_drift = moving ? 1 : 0;
     a.do_collide = moving ? 1 : 0;
     return a;
 }
@@ -278,40 +296,49 @@ K2Args<T> make_k2(const Instance& I, double dt, int64_t step) {
     a.step = (uint32_t)step;
     a.h_read = hbuf(I, step);
     a.hmax_read = hmbuf(I, step);
-    a.h_acc = hbuf(I, step + 1);
-    a.partial = I.partial;
-    a.cand_idx = I.cand_idx;
-    a.cand_cnt = I.cand_cnt;
-    a.cap_w = (int)(I.chunk / kWaves1);
+    a.cand = I.cand;
+    a.cand_count = I.qc + 2 * (step & 1);
+    a.head = I.qc + 2 * (step & 1) + 1;
     a.counters = I.counters;
-    a.chunk = I.chunk;
     return a;
 }
 
-K3Args make_k3(const Instance& I, int64_t built, int64_t clear, int64_t rec_index) {
+K3Args make_k3(const Instance& I, int64_t step) {
     K3Args a;
     a.Q = I.Q; a.nk = I.nk;
-    a.h_acc = hbuf(I, built);
-    a.hmax_out = hmbuf(I, built);
-    a.h_clr = hbuf(I, clear);
-    a.partial = I.partial;
-    a.nwg = I.nwg; a.nb = I.nb;
-    a.record = I.record + (size_t)rec_index * I.nb * I.Q * 3;
+    a.slabs = I.slabs;
+    a.hwin_words = I.hwin_words; a.win = I.win; a.win_r0 = I.win_r0; a.win_l0 = I.win_l0;
+    a.extra = I.extra;
+    a.h_out = hbuf(I, step);
+    a.hmax_out = hmbuf(I, step);
+    a.hmax_clr = hmbuf(I, step + 1);
+    a.reset = I.qc + 2 * ((step + 1) & 1);
+    a.n_win_wg = (I.hwin_words + kK3Words - 1) / kK3Words;
     return a;
 }
 
-// One time step of instance I: stream, colliders, finalize.
-sgpm_status launch_step(sgpm_ctx* c, Instance& I, double dt, int64_t step, int64_t rec_index) {
+// bins and moments of the current state (time index step - rec_base)
+sgpm_status run_state_pass(sgpm_ctx* c, Instance& I, double dt, bool moving) {
     int e;
-    if (I.fp32) {
-        e = launch_k1_f32(make_k1<float>(I, dt, true, step, hbuf(I, step + 1)), I.nwg, c->stream);
-        if (!e) e = launch_k2_f32(make_k2<float>(I, dt, step), I.nwg, c->stream);
-    } else {
-        e = launch_k1_f64(make_k1<double>(I, dt, true, step, hbuf(I, step + 1)), I.nwg, c->stream);
-        if (!e) e = launch_k2_f64(make_k2<double>(I, dt, step), I.nwg, c->stream);
-    }
-    if (!e) e = launch_k3(make_k3(I, step + 1, step + 2, rec_index), c->stream);
-    if (e != 0) return dev_fail(c, (hipError_t)e, "step kernel launch");
+    if (I.fp32) e = launch_k1_f32(make_k1<float>(I, dt, moving, I.step), I.nwg, c->stream);
+    else e = launch_k1_f64(make_k1<double>(I, dt, moving, I.step), I.nwg, c->stream);
+    if (!e)
+        e = launch_k3(make_k3(I, I.step), I.nwg, I.nb, I.partial,
+                      I.record + (size_t)(I.step - I.rec_base) * I.nb * I.Q * 3, c->stream);
+    if (e != 0) return dev_fail(c, (hipError_t)e, "state pass launch");
+    return SGPM_OK;
+}
+
+// One time step of instance I: the state pass of t^n with the drift and the
+// candidate list, then the collisions of the candidates against H^n.
+sgpm_status launch_step(sgpm_ctx* c, Instance& I, double dt) {
+    sgpm_status s = run_state_pass(c, I, dt, true);
+    if (s) return s;
+    int e;
+    if (I.fp32) e = launch_k2_f32(make_k2<float>(I, dt, I.step), k2_grid(), c->stream);
+    else e = launch_k2_f64(make_k2<double>(I, dt, I.step), k2_grid(), c->stream);
+    if (e != 0) return dev_fail(c, (hipError_t)e, "collider launch");
+    I.step += 1;
     return SGPM_OK;
 }
 
@@ -325,15 +352,12 @@ void set_chunk(Instance& I, int64_t chunk) {
 sgpm_status rebuild(sgpm_ctx* c, Instance& I) {
     const size_t hm = (size_t)64 * ((I.Q + 63) / 64) * 4;
     HIPCHK(c, hipMemsetAsync(I.H, 0, (size_t)3 * I.hstride * 4, c->stream));
+    HIPCHK(c, hipMemsetAsync(I.extra, 0, (size_t)I.hstride * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(I.Hmax, 0, 3 * hm, c->stream));
+    HIPCHK(c, hipMemsetAsync(I.qc, 0, 64, c->stream));
     HIPCHK(c, hipMemsetAsync(I.counters, 0, SGPM_N_COUNTERS * 8, c->stream));
     I.rec_base = I.step;
-    int e;
-    if (I.fp32) e = launch_k1_f32(make_k1<float>(I, 0.0, false, I.step, hbuf(I, I.step)), I.nwg, c->stream);
-    else e = launch_k1_f64(make_k1<double>(I, 0.0, false, I.step, hbuf(I, I.step)), I.nwg, c->stream);
-    if (!e) e = launch_k3(make_k3(I, I.step, I.step + 1, 0), c->stream);
-    if (e != 0) return dev_fail(c, (hipError_t)e, "rebuild launch");
-    return SGPM_OK;
+    return run_state_pass(c, I, 0.0, false);
 }
 
 }  // namespace
@@ -435,10 +459,14 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         I.d_psimax = (double*)at(27); I.f_psimax = (float*)at(28);
         I.d_consts = (Consts<double>*)at(29); I.f_consts = (Consts<float>*)at(30);
         I.d_ehat = (double*)at(31);
-        I.cand_idx = (int*)at(32); I.cand_cnt = (int*)at(33);
+        I.cand = (int*)at(32);
+        I.qc = (uint32_t*)at(6);
+        I.extra = (uint32_t*)at(34);
+        I.slabs = (uint32_t*)at(35);
         base += L.total;
         set_chunk(I, 0);
-        window_for(I.P, I.Q, I.nk, I.fp32, &I.win, &I.win_r0, &I.win_l0, &I.hwin_words);
+        window_for(I.P, I.Q, I.nk, I.fp32, (int)I.chunk, &I.win, &I.win_r0, &I.win_l0,
+                   &I.hwin_words);
 
         // upload the tables (FP64 masters and FP32 copies)
         const int Q = I.Q, P = I.P;
@@ -537,9 +565,11 @@ sgpm_status sgpm_tables(const sgpm_ctx* c, int32_t inst, double* z, double* w, d
 sgpm_status sgpm_set_chunk(sgpm_ctx* c, int32_t inst, int32_t chunk) {
     sgpm_status s = check_ctx(c, inst);
     if (s) return s;
-    if (chunk < 0 || chunk % kBlock1 != 0 || chunk > 32768)
-        return fail(c, SGPM_EINVAL, "chunk must be a multiple of 512 up to 32768 (0 = automatic)");
+    if (chunk < 0 || chunk % kBlock1 != 0 || chunk > kMaxChunk)
+        return fail(c, SGPM_EINVAL, "chunk must be a multiple of 256 up to 8192 (0 = automatic)");
     Instance& I = c->inst[inst];
+    if (chunk > 0 && chunk < min_chunk(I.n))
+        return fail(c, SGPM_EINVAL, "chunk too small: at most 4096 stream workgroups");
     if (I.initialised && I.step != I.rec_base)
         return fail(c, SGPM_ESTATE, "the launch shape can only change right after init/set_state");
     set_chunk(I, chunk);
@@ -588,10 +618,14 @@ sgpm_status sgpm_step(sgpm_ctx* c, double dt, int64_t n_steps) {
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     for (int64_t k = 0; k < n_steps; ++k) {
         for (Instance& I : c->inst) {
-            sgpm_status s = launch_step(c, I, dt, I.step, I.step - I.rec_base + 1);
+            sgpm_status s = launch_step(c, I, dt);
             if (s) return s;
-            I.step += 1;
         }
+    }
+    // bins and moments of the final state
+    for (Instance& I : c->inst) {
+        sgpm_status s = run_state_pass(c, I, dt, false);
+        if (s) return s;
     }
     HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     c->timed = true;

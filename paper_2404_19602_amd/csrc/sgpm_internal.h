@@ -17,7 +17,7 @@ constexpr int kMaxQ = 128;           // largest node count
 constexpr int kEdgePts = 32;         // trapezoid points of the edge integral
 constexpr int kEdgeTries = 64;       // edge-angle proposals per collision
 constexpr int kNumBatches = 32;      // batch-means batches of the moment record
-constexpr int kLdsK1Bytes = 60 * 1024;   // LDS budget of a stream workgroup
+constexpr int kLdsK1Bytes = 72 * 1024;   // LDS budget of a stream workgroup
 
 // Host FP64 set-up of one instance (Sec. 4.1 tables, Appendix rate constants).
 struct HostTables {
@@ -81,10 +81,15 @@ struct DevTab {
     const Consts<T>* consts;
 };
 
-constexpr int kWaves1 = 8;            // waves per workgroup of the stream kernel
+constexpr int kWaves1 = 4;            // waves per workgroup of the stream kernel
 constexpr int kBlock1 = 64 * kWaves1;
+constexpr int kMaxStreamWG = 4096;    // cap on stream workgroups (sizes the slabs)
+constexpr int kMaxChunk = 8192;       // cap on particles per stream workgroup (LDS list)
 
-// Stream kernel: every particle of a chunk, lane per particle.
+// Stream kernel: every particle of a chunk, lane per particle.  From the
+// state at t^n it bins H^n and sums the moments at t^n; then it applies the
+// Galerkin drift and decides with a rigorous rate bound whether the particle
+// may collide in this step; candidates go to a global work list.
 template <typename T>
 struct K1Args {
     T* kx;
@@ -96,19 +101,19 @@ struct K1Args {
     double vfdt;            // v_F dt: drift of mode h is vfdt * ehat[h]
     T dt;
     uint32_t seed_lo, seed_hi, instance, step;
-    uint32_t* h_acc;        // H^{n+1}
+    uint32_t* extra;        // overflow grid of H^n (outside the LDS window)
+    uint32_t* slabs;        // [nwg][hwin_words] window slabs of H^n
     int win, win_r0, win_l0, hwin_words;
-    double* partial;        // [nwg][Q][3]
-    int* cand_idx;          // [nwg][kWaves1][cap_w]
-    int* cand_cnt;          // [nwg][kWaves1]
-    int cap_w;
+    double* partial;        // [nwg][Q][3] moment sums at t^n
+    int* cand;              // global list of collision candidates
+    uint32_t* cand_count;   // its length (zero on entry)
     unsigned long long* counters;
     int64_t chunk;
-    int do_drift, do_collide;
+    int do_collide;         // 0: bins and moments only (no drift, no candidates)
 };
 
-// Collider kernel: the candidates of one stream workgroup, a group of lanes
-// per candidate, one node per lane.
+// Collider kernel: a group of G lanes per candidate, one node per lane;
+// candidates pulled from the global list by a work counter.
 template <typename T>
 struct K2Args {
     T* kx;
@@ -120,26 +125,30 @@ struct K2Args {
     double vfdt;
     T dt;
     uint32_t seed_lo, seed_hi, instance, step;
-    const uint32_t* h_read;
-    const uint32_t* hmax_read;
-    uint32_t* h_acc;
-    double* partial;
-    const int* cand_idx;
-    const int* cand_cnt;
-    int cap_w;
+    const uint32_t* h_read;     // H^n
+    const uint32_t* hmax_read;  // its per-node maximum
+    const int* cand;
+    const uint32_t* cand_count;
+    uint32_t* head;             // work counter (zero on entry)
     unsigned long long* counters;
-    int64_t chunk;
 };
 
-// Finalize kernel: one workgroup per node.
+// Finalize kernel: H^n from the slabs and the overflow grid, its maximum,
+// the moment record of t^n, and the reset of the next step's counters.
+constexpr int kK3Words = 64;      // window words per finalize workgroup
+constexpr int kK3Lanes = 16;      // slab lanes per column of four words
+constexpr int kK3Rest = 256;      // cells per workgroup of the outside part
+
 struct K3Args {
     int Q, nk;
-    const uint32_t* h_acc;  // histogram just built
-    uint32_t* hmax_out;     // its per-node maximum
-    uint32_t* h_clr;        // stale buffer cleared for the next step
-    const double* partial;  // [nwg][Q][3]
-    int nwg, nb;
-    double* record;         // [NB][Q][3]
+    const uint32_t* slabs;  // [nwg][hwin_words]
+    int hwin_words, win, win_r0, win_l0;
+    uint32_t* extra;        // [Q][nk][nk] overflow counts (zeroed here)
+    uint32_t* h_out;        // H^n
+    uint32_t* hmax_out;     // its per-node maximum (zero on entry)
+    uint32_t* hmax_clr;     // stale maximum slot zeroed for the next step
+    uint32_t* reset;        // [2] counters of the next step zeroed
+    int n_win_wg;           // workgroups of the window part
 };
 
 struct InitArgs {
@@ -174,12 +183,15 @@ int launch_k1_f64(const K1Args<double>& a, int nwg, void* stream);
 int launch_k1_f32(const K1Args<float>& a, int nwg, void* stream);
 int launch_k2_f64(const K2Args<double>& a, int nwg, void* stream);
 int launch_k2_f32(const K2Args<float>& a, int nwg, void* stream);
-int launch_k3(const K3Args& a, void* stream);
+int k2_grid();
+int launch_k3(const K3Args& a, int nwg, int nb, const double* partial, double* record,
+              void* stream);
+int pmax_bucket(int P);
 int launch_init(const InitArgs& a, void* stream);
 int launch_energy_hist(const EnergyHistArgs& a, void* stream);
 int launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n,
                   void* stream);
-size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words);
+size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words, int chunk);
 size_t k2_lds_bytes(int P, int Q, int fp32);
 
 }  // namespace sgpm

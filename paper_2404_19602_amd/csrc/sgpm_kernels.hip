@@ -73,18 +73,20 @@ __device__ __forceinline__ float dexp(float x) { return expf(x); }
 __device__ __forceinline__ void dsincospi(double x, double* s, double* c) { sincospi(x, s, c); }
 __device__ __forceinline__ void dsincospi(float x, float* s, float* c) { sincospif(x, s, c); }
 
-// floor((x + L)/dk) as the rounded quotient gives it: the product by 1/dk is
-// replaced by the true division only within a few ulps of an integer.
-// Outside [0, 2^30) (and NaN) -> -1.
+// cell coordinate floor((x + L) / dk) of the grid [-L, L) split in cells of
+// width dk (computed with the product by 1/dk); outside [0, 2^30) or NaN -> -1
 template <typename T>
-__device__ __forceinline__ int cell_coord(T x, T L, T dk, T inv_dk) {
-    const T s = x + L;
-    T qt = s * inv_dk;
-    const T r = rint(qt);
-    if (fabs(qt - r) <= (T)8 * Num<T>::eps * fabs(qt) + (T)1e-30) qt = s / dk;
-    const T f = floor(qt);
+__device__ __forceinline__ int cell_coord(T x, T L, T inv_dk) {
+    const T f = floor((x + L) * inv_dk);
     return (f >= (T)0 && f < (T)1073741824) ? (int)f : -1;
 }
+
+// 1/sqrt(a): the hardware estimate refined by one Newton step
+__device__ __forceinline__ double rsqrt_nr(double a) {
+    const double y = __builtin_amdgcn_rsq(a);
+    return y * (1.5 - 0.5 * a * y * y);
+}
+__device__ __forceinline__ float rsqrt_nr(float a) { return __builtin_amdgcn_rsqf(a); }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -155,14 +157,51 @@ __device__ __forceinline__ T rate_bound(const Consts<T>& c, T emax) {
     return c.alpha1 * s * c.b_margin;
 }
 
+// Padded basis tables: the rows of psi and w_q psi are stored with PMAX
+// entries (zeros past P) so node evaluation and projection unroll without
+// per-mode branches.
+int pmax_bucket(int P) {
+    if (P <= 1) return 1;
+    if (P <= 3) return 3;
+    if (P <= 6) return 6;
+    if (P <= 9) return 9;
+    if (P <= 16) return 16;
+    return 32;
+}
+
+template <typename T, int PMAX>
+__device__ __forceinline__ void eval_node(const T* __restrict__ row, const T (&cx)[PMAX],
+                                          const T (&cy)[PMAX], T& kx, T& ky) {
+    T x = (T)0, y = (T)0;
+#pragma unroll
+    for (int h = 0; h < PMAX; ++h) { x += cx[h] * row[h]; y += cy[h] * row[h]; }
+    kx = x; ky = y;
+}
+
+// coefficients of particle i (drift applied), zero past P, branch-free loads
+template <typename T, int PMAX>
+__device__ __forceinline__ void load_coeffs(const T* __restrict__ kxa, const T* __restrict__ kya,
+                                            int64_t n, int P, int64_t i, const T* drift,
+                                            T (&cx)[PMAX], T (&cy)[PMAX]) {
+#pragma unroll
+    for (int h = 0; h < PMAX; ++h) {
+        const int hh = h < P ? h : P - 1;
+        const T vx = kxa[(size_t)hh * n + i];
+        const T vy = kya[(size_t)hh * n + i];
+        cx[h] = h < P ? vx - drift[h] : (T)0;     // k_h -= (e/hbar) dt E_h
+        cy[h] = h < P ? vy : (T)0;
+    }
+}
+
 // ======================================================= K1: stream kernel
-size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words) {
+size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words, int chunk) {
     const size_t s = fp32 ? 4 : 8;
-    size_t off = (size_t)hwin_words * 4;
+    const int PM = pmax_bucket(P);
+    size_t off = (size_t)hwin_words * 4 + (size_t)chunk * 4;   // window, candidate buffer
     off = (off + 15) & ~(size_t)15;
     off += sizeof(Consts<double>);                       // consts (either precision fits)
     off = (off + 15) & ~(size_t)15;
-    off += s * ((size_t)Q * P + Q + 2 * P);             // psi, eps0sq, psimax, drift
+    off += s * ((size_t)Q * PM + 2 * Q + 2 * PM);       // psi, eps0sq, shift, psimax, drift
     off = (off + 15) & ~(size_t)15;
     off += (size_t)kWaves1 * Q * 3 * 8;                  // per-wave moment sums
     off += 16 * 4;                                       // counters
@@ -172,26 +211,30 @@ size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words) {
 template <typename T>
 struct K1Lds {
     uint32_t* hwin;
+    int* cbuf;
     Consts<T>* c;
-    T* psi; T* eps0sq; T* psimax; T* drift;
+    T* psi; T* eps0sq; T* shift; T* psimax; T* drift;
     double* red;
     uint32_t* cnt;
 };
 
 template <typename T>
-__device__ __forceinline__ K1Lds<T> k1_lds(unsigned char* smem, int P, int Q, int hwin_words) {
+__device__ __forceinline__ K1Lds<T> k1_lds(unsigned char* smem, int PM, int Q, int hwin_words,
+                                           int chunk) {
     K1Lds<T> L;
-    size_t off = (size_t)hwin_words * 4;
-    off = (off + 15) & ~(size_t)15;
     L.hwin = reinterpret_cast<uint32_t*>(smem);
+    L.cbuf = reinterpret_cast<int*>(smem + (size_t)hwin_words * 4);
+    size_t off = (size_t)hwin_words * 4 + (size_t)chunk * 4;
+    off = (off + 15) & ~(size_t)15;
     L.c = reinterpret_cast<Consts<T>*>(smem + off);
     off += sizeof(Consts<double>);
     off = (off + 15) & ~(size_t)15;
     L.psi = reinterpret_cast<T*>(smem + off);
-    L.eps0sq = L.psi + Q * P;
-    L.psimax = L.eps0sq + Q;
-    L.drift = L.psimax + P;
-    off += sizeof(T) * ((size_t)Q * P + Q + 2 * P);
+    L.eps0sq = L.psi + Q * PM;
+    L.shift = L.eps0sq + Q;
+    L.psimax = L.shift + Q;
+    L.drift = L.psimax + PM;
+    off += sizeof(T) * ((size_t)Q * PM + 2 * Q + 2 * PM);
     off = (off + 15) & ~(size_t)15;
     L.red = reinterpret_cast<double*>(smem + off);
     off += (size_t)kWaves1 * Q * 3 * 8;
@@ -199,12 +242,12 @@ __device__ __forceinline__ K1Lds<T> k1_lds(unsigned char* smem, int P, int Q, in
     return L;
 }
 
-// one nodal value into H^{n+1}: LDS window when inside it, else global
+// one nodal value into H^n: LDS window when inside it, else the overflow grid
 template <typename T>
 __device__ __forceinline__ void k1_bin(const K1Args<T>& a, const K1Lds<T>& L, const Consts<T>& c,
                                        int q, T kx, T ky) {
-    const int r = cell_coord<T>(kx, c.lk, c.dk, c.inv_dk);
-    const int l = cell_coord<T>(ky, c.lk, c.dk, c.inv_dk);
+    const int r = cell_coord<T>(kx, c.lk, c.inv_dk);
+    const int l = cell_coord<T>(ky, c.lk, c.inv_dk);
     if (r < 0 || l < 0 || r >= c.nk || l >= c.nk) {
         atomicAdd(&L.cnt[SGPM_CNT_OUT_OF_GRID], 1u);
         return;
@@ -214,115 +257,103 @@ __device__ __forceinline__ void k1_bin(const K1Args<T>& a, const K1Lds<T>& L, co
         const int idx = (q * a.win + wr) * a.win + wl;
         atomicAdd(&L.hwin[idx >> 1], (idx & 1) ? 65536u : 1u);
     } else {
-        atomicAdd(&a.h_acc[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l], 1u);
+        atomicAdd(&a.extra[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l], 1u);
     }
+}
+
+// Is a collision possible in this step?  ub: upper bound of every nodal
+// energy after the drift.  No collision iff -log(xi) / G~ >= dt; with
+// G~ <= gb and -log(xi) >= 1 - xi the test needs the logarithm only when
+// xi > 1 - gb dt.
+template <typename T>
+__device__ __forceinline__ bool k1_candidate(const K1Args<T>& a, const Consts<T>& c, int64_t i, T ub) {
+    const T t = rate_bound<T>(c, ub) * a.dt;
+    const Words wx = philox10((uint32_t)i, a.step, kPurXi, a.instance, a.seed_lo, a.seed_hi);
+    const T xi = uni<T>(wx.w0, wx.w1);
+    if (xi <= (T)1 - t * c.b_margin) return false;
+    return !(-dlog(xi) >= t);
 }
 
 template <typename T, int PMAX, int QMAX>
 __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T> a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int P = a.P, Q = a.Q;
-    const K1Lds<T> L = k1_lds<T>(smem, P, Q, a.hwin_words);
+    const K1Lds<T> L = k1_lds<T>(smem, PMAX, Q, a.hwin_words, (int)a.chunk);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     for (int w = tid; w < a.hwin_words; w += kBlock1) L.hwin[w] = 0u;
     if (tid == 0) *L.c = *a.tab.consts;
-    for (int k = tid; k < Q * P; k += kBlock1) L.psi[k] = a.tab.psi[k];
-    for (int k = tid; k < Q; k += kBlock1) L.eps0sq[k] = a.tab.eps0sq[k];
-    for (int k = tid; k < P; k += kBlock1) {
-        L.psimax[k] = a.tab.psimax[k];
-        L.drift[k] = a.do_drift ? (T)(a.vfdt * a.ehat[k]) : (T)0;
+    for (int k = tid; k < Q * PMAX; k += kBlock1) {
+        const int q = k / PMAX, h = k - q * PMAX;
+        L.psi[k] = h < P ? a.tab.psi[q * P + h] : (T)0;
+    }
+    for (int k = tid; k < PMAX; k += kBlock1) {
+        L.psimax[k] = k < P ? a.tab.psimax[k] : (T)0;
+        L.drift[k] = (a.do_collide && k < P) ? (T)(a.vfdt * a.ehat[k]) : (T)0;
     }
     for (int k = tid; k < kWaves1 * Q * 3; k += kBlock1) L.red[k] = 0.0;
     if (tid < 16) L.cnt[tid] = 0u;
+    __syncthreads();
+    // node value of the drift: sum_h drift_h Psi_h(z_q)
+    for (int k = tid; k < Q; k += kBlock1) {
+        L.eps0sq[k] = a.tab.eps0sq[k];
+        T d = (T)0;
+        for (int h = 0; h < PMAX; ++h) d += L.drift[h] * L.psi[k * PMAX + h];
+        L.shift[k] = d;
+    }
     __syncthreads();
     const Consts<T>& c = *L.c;
 
     const int64_t begin = (int64_t)blockIdx.x * a.chunk;
     const int64_t end = begin + a.chunk < a.n ? begin + a.chunk : a.n;
-    int* my_cand = a.cand_idx + ((size_t)blockIdx.x * kWaves1 + wave) * a.cap_w;
-    int ncand = 0;     // uniform per wave
 
     double acc[QMAX > 0 ? QMAX : 1][3];
     if constexpr (QMAX > 0) {
 #pragma unroll
         for (int q = 0; q < QMAX; ++q) { acc[q][0] = 0.0; acc[q][1] = 0.0; acc[q][2] = 0.0; }
     }
+    const T zero[PMAX] = {};
 
     for (int64_t base = begin; base < end; base += kBlock1) {
         const int64_t i = base + tid;
         const bool act = i < end;
-        const int64_t ii = act ? i : begin;
         T cx[PMAX], cy[PMAX];
-#pragma unroll
-        for (int h = 0; h < PMAX; ++h) {
-            if (h < P) {
-                cx[h] = a.kx[(size_t)h * a.n + ii] - L.drift[h];   // k_h -= (e/hbar) dt E_h
-                cy[h] = a.ky[(size_t)h * a.n + ii];
-            } else {
-                cx[h] = (T)0; cy[h] = (T)0;
-            }
-        }
+        load_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, act ? i : begin, zero, cx, cy);
         bool cand = false;
-        if (act && a.do_collide) {
-            // |k(z_q)| <= sum_h |k_h| max_q |Psi_h(z_q)| per component
-            T bx = (T)0, by = (T)0;
-#pragma unroll
-            for (int h = 0; h < PMAX; ++h)
-                if (h < P) { bx += fabs(cx[h]) * L.psimax[h]; by += fabs(cy[h]) * L.psimax[h]; }
-            const T emax = sqrt(bx * bx + by * by + c.eps0max_sq);
-            const T gb = rate_bound<T>(c, emax);
-            const Words wx = philox10((uint32_t)i, a.step, kPurXi, a.instance, a.seed_lo, a.seed_hi);
-            const T xlog = -dlog(uni<T>(wx.w0, wx.w1));
-            cand = !(xlog >= gb * a.dt);    // no collision iff -log(xi)/G~ >= dt
-        }
-        const bool fin = act && !cand;
-        if (fin && a.do_drift) {
-#pragma unroll
-            for (int h = 0; h < PMAX; ++h)
-                if (h < P && L.drift[h] != (T)0) a.kx[(size_t)h * a.n + i] = cx[h];
-        }
-        // candidates of this wave, in lane order
-        const uint64_t mask = __ballot(cand);
-        if (cand) {
-            const int pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-            my_cand[ncand + pos] = (int)(i - begin);
-        }
-        ncand += __popcll(mask);
-
-        // nodes of the particles that are final now
         if constexpr (QMAX > 0) {
+            T e2max = (T)0;
 #pragma unroll
             for (int q = 0; q < QMAX; ++q) {
-                if (q < Q && fin) {
-                    const T* ps = L.psi + q * P;
-                    T kx = (T)0, ky = (T)0;
-#pragma unroll
-                    for (int h = 0; h < PMAX; ++h)
-                        if (h < P) { kx += cx[h] * ps[h]; ky += cy[h] * ps[h]; }
-                    const T e = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
-                    const T inv = (T)1 / e;
-                    acc[q][0] += (double)(c.v_f * kx * inv);
-                    acc[q][1] += (double)(c.v_f * ky * inv);
-                    acc[q][2] += (double)e;
+                if (q < Q && act) {
+                    T kx, ky;
+                    eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
+                    // state at t^n: histogram and moments (Sec. 4.2)
+                    const T e2 = kx * kx + ky * ky + L.eps0sq[q];
+                    const T rs = rsqrt_nr(e2);
+                    acc[q][0] += (double)(c.v_f * kx * rs);
+                    acc[q][1] += (double)(c.v_f * ky * rs);
+                    acc[q][2] += (double)(e2 * rs);
                     k1_bin<T>(a, L, c, q, kx, ky);
+                    // after the drift, for the rate bound
+                    const T dx = kx - L.shift[q];
+                    const T d2 = dx * dx + ky * ky + L.eps0sq[q];
+                    e2max = d2 > e2max ? d2 : e2max;
                 }
             }
+            // the nodal energies after the drift, bounded with a relative
+            // margin for the rounding of the shifted evaluation
+            if (act && a.do_collide) cand = k1_candidate<T>(a, c, i, sqrt(e2max) * c.b_margin);
         } else {
             for (int q = 0; q < Q; ++q) {
                 double vx = 0.0, vy = 0.0, en = 0.0;
-                if (fin) {
-                    const T* ps = L.psi + q * P;
-                    T kx = (T)0, ky = (T)0;
-#pragma unroll
-                    for (int h = 0; h < PMAX; ++h)
-                        if (h < P) { kx += cx[h] * ps[h]; ky += cy[h] * ps[h]; }
-                    const T e = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
-                    const T inv = (T)1 / e;
-                    vx = (double)(c.v_f * kx * inv);
-                    vy = (double)(c.v_f * ky * inv);
-                    en = (double)e;
+                if (act) {
+                    T kx, ky;
+                    eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
+                    const T e2 = kx * kx + ky * ky + L.eps0sq[q];
+                    const T rs = rsqrt_nr(e2);
+                    vx = (double)(c.v_f * kx * rs);
+                    vy = (double)(c.v_f * ky * rs);
+                    en = (double)(e2 * rs);
                     k1_bin<T>(a, L, c, q, kx, ky);
                 }
                 vx = wave_sum(vx); vy = wave_sum(vy); en = wave_sum(en);
@@ -330,6 +361,34 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T> a) {
                     double* m = L.red + ((size_t)wave * Q + q) * 3;
                     m[0] += vx; m[1] += vy; m[2] += en;
                 }
+            }
+            if (act && a.do_collide) {
+                // |k(z_q)| <= sum_h |k_h| max_q |Psi_h(z_q)| per component, after the drift
+                T bx = (T)0, by = (T)0;
+#pragma unroll
+                for (int h = 0; h < PMAX; ++h) {
+                    bx += fabs(cx[h] - L.drift[h]) * L.psimax[h];
+                    by += fabs(cy[h]) * L.psimax[h];
+                }
+                cand = k1_candidate<T>(a, c, i, sqrt(bx * bx + by * by + c.eps0max_sq));
+            }
+        }
+        if (act && a.do_collide && !cand) {
+            // the particle does not collide: its step is the drift alone
+#pragma unroll
+            for (int h = 0; h < PMAX; ++h)
+                if (h < P && L.drift[h] != (T)0) a.kx[(size_t)h * a.n + i] = cx[h] - L.drift[h];
+        }
+        // candidates of this workgroup collected in LDS
+        const uint64_t mask = __ballot(cand);
+        if (mask) {
+            uint32_t base_slot = 0;
+            if (lane == 0) base_slot = atomicAdd(&L.cnt[SGPM_CNT_CANDIDATES], (uint32_t)__popcll(mask));
+            base_slot = __shfl(base_slot, 0, 64);
+            if (cand) {
+                const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                L.cbuf[base_slot + pos] = (int)i;
             }
         }
     }
@@ -346,28 +405,25 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T> a) {
             }
         }
     }
-    if (lane == 0) {
-        a.cand_cnt[(size_t)blockIdx.x * kWaves1 + wave] = ncand;
-        if (ncand) atomicAdd(&L.cnt[SGPM_CNT_CANDIDATES], (uint32_t)ncand);
-    }
     __syncthreads();
 
-    // flush the LDS window: nonzero cells to global atomics
+    // this workgroup's candidates appended to the global list (one reservation)
     {
-        const int wcells = a.win * a.win;
-        for (int w = tid; w < a.hwin_words; w += kBlock1) {
-            const uint32_t v = L.hwin[w];
-            if (v == 0u) continue;
-#pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                const uint32_t cnt = half ? (v >> 16) : (v & 0xFFFFu);
-                if (cnt == 0u) continue;
-                const int idx = 2 * w + half;
-                const int q = idx / wcells, rem = idx - q * wcells;
-                const int r = a.win_r0 + rem / a.win, l = a.win_l0 + rem % a.win;
-                atomicAdd(&a.h_acc[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l], cnt);
-            }
+        __shared__ uint32_t gbase;
+        const uint32_t nc = L.cnt[SGPM_CNT_CANDIDATES];
+        if (nc) {
+            if (tid == 0) gbase = atomicAdd(a.cand_count, nc);
+            __syncthreads();
+            for (uint32_t k = tid; k < nc; k += kBlock1) a.cand[gbase + k] = L.cbuf[k];
         }
+    }
+
+    // the LDS window as this workgroup's dense slab (plain 16-byte stores)
+    {
+        uint32_t* slab = a.slabs + (size_t)blockIdx.x * a.hwin_words;
+        const int nv = a.hwin_words >> 2;
+        for (int w = tid; w < nv; w += kBlock1)
+            reinterpret_cast<uint4*>(slab)[w] = reinterpret_cast<const uint4*>(L.hwin)[w];
     }
     // this workgroup's moment sums, waves in order
     for (int k = tid; k < Q * 3; k += kBlock1) {
@@ -381,13 +437,12 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T> a) {
 // ===================================================== K2: collider kernel
 size_t k2_lds_bytes(int P, int Q, int fp32) {
     const size_t s = fp32 ? 4 : 8;
+    const int PM = pmax_bucket(P);
     size_t off = sizeof(Consts<double>);
     off = (off + 15) & ~(size_t)15;
-    off += s * (2 * (size_t)Q * P + 4 * (size_t)Q + 32 + P);   // psi wpsi eps0 eps0sq cedge vfield ecos drift
+    off += s * (2 * (size_t)Q * PM + 4 * (size_t)Q + 32 + PM);   // psi wpsi eps0 eps0sq cedge vfield ecos drift
     off = (off + 15) & ~(size_t)15;
-    off += (size_t)2 * kBlock * 3 * 8;   // final sums of a pass, [groups][Q][3]
-    off += (size_t)Q * 3 * 8;            // running sums
-    off += 16 * 4 + (kWaves1 + 1) * 4;   // counters, candidate offsets
+    off += 16 * 4 + 16;                  // counters, work slot
     return off;
 }
 
@@ -395,36 +450,29 @@ template <typename T>
 struct K2Lds {
     Consts<T>* c;
     T* psi; T* wpsi; T* eps0; T* eps0sq; T* cedge; T* vfield; T* ecos; T* drift;
-    double* pass;   // [groups per pass][Q][3]
-    double* run;    // [Q][3]
     uint32_t* cnt;
-    int* off;       // [kWaves1 + 1]
+    uint32_t* slot;
 };
 
 template <typename T>
-__device__ __forceinline__ K2Lds<T> k2_lds(unsigned char* smem, int P, int Q) {
+__device__ __forceinline__ K2Lds<T> k2_lds(unsigned char* smem, int PM, int Q) {
     K2Lds<T> L;
     size_t off = 0;
     L.c = reinterpret_cast<Consts<T>*>(smem);
     off = sizeof(Consts<double>);
     off = (off + 15) & ~(size_t)15;
     L.psi = reinterpret_cast<T*>(smem + off);
-    L.wpsi = L.psi + Q * P;
-    L.eps0 = L.wpsi + Q * P;
+    L.wpsi = L.psi + Q * PM;
+    L.eps0 = L.wpsi + Q * PM;
     L.eps0sq = L.eps0 + Q;
     L.cedge = L.eps0sq + Q;
     L.vfield = L.cedge + Q;
     L.ecos = L.vfield + Q;
     L.drift = L.ecos + 32;
-    off += sizeof(T) * (2 * (size_t)Q * P + 4 * (size_t)Q + 32 + P);
+    off += sizeof(T) * (2 * (size_t)Q * PM + 4 * (size_t)Q + 32 + PM);
     off = (off + 15) & ~(size_t)15;
-    L.pass = reinterpret_cast<double*>(smem + off);
-    off += (size_t)2 * kBlock * 3 * 8;
-    L.run = reinterpret_cast<double*>(smem + off);
-    off += (size_t)Q * 3 * 8;
     L.cnt = reinterpret_cast<uint32_t*>(smem + off);
-    off += 16 * 4;
-    L.off = reinterpret_cast<int*>(smem + off);
+    L.slot = L.cnt + 16;
     return L;
 }
 
@@ -436,8 +484,8 @@ __device__ __forceinline__ T pauli_f(const K2Args<T>& a, const K2Lds<T>& L, cons
     const uint32_t mx = a.hmax_read[q];
     if (mx == 0u) return (T)0;
     const T shift = L.vfield[q] * a.dt;
-    const int r = cell_coord<T>(px + shift, c.lk, c.dk, c.inv_dk);
-    const int l = cell_coord<T>(py, c.lk, c.dk, c.inv_dk);
+    const int r = cell_coord<T>(px + shift, c.lk, c.inv_dk);
+    const int l = cell_coord<T>(py, c.lk, c.inv_dk);
     if (r < 0 || l < 0 || r >= c.nk || l >= c.nk) return (T)0;
     const uint32_t h = a.h_read[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l];
     return (T)h / (T)mx;
@@ -447,287 +495,273 @@ template <typename T, int PMAX>
 __global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T> a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int P = a.P, Q = a.Q, G = a.G;
-    const K2Lds<T> L = k2_lds<T>(smem, P, Q);
+    const K2Lds<T> L = k2_lds<T>(smem, PMAX, Q);
     const int tid = threadIdx.x;
-    const int wg = blockIdx.x;
-
-    if (tid == 0) {
-        int s = 0;
-        for (int w = 0; w < kWaves1; ++w) {
-            L.off[w] = s;
-            s += a.cand_cnt[(size_t)wg * kWaves1 + w];
-        }
-        L.off[kWaves1] = s;
-    }
-    __syncthreads();
-    const int M = L.off[kWaves1];
-    if (M == 0) return;
+    const uint32_t total = *a.cand_count;
+    if (total == 0u) return;
 
     if (tid == 0) *L.c = *a.tab.consts;
-    for (int k = tid; k < Q * P; k += kBlock) { L.psi[k] = a.tab.psi[k]; L.wpsi[k] = a.tab.wpsi[k]; }
+    for (int k = tid; k < Q * PMAX; k += kBlock) {
+        const int q = k / PMAX, h = k - q * PMAX;
+        L.psi[k] = h < P ? a.tab.psi[q * P + h] : (T)0;
+        L.wpsi[k] = h < P ? a.tab.wpsi[q * P + h] : (T)0;
+    }
     for (int k = tid; k < Q; k += kBlock) {
         L.eps0[k] = a.tab.eps0[k]; L.eps0sq[k] = a.tab.eps0sq[k];
         L.cedge[k] = a.tab.cedge[k]; L.vfield[k] = a.tab.vfield[k];
     }
     for (int k = tid; k <= kEdgePts / 2; k += kBlock) L.ecos[k] = a.tab.edge_cos[k];
-    for (int k = tid; k < P; k += kBlock) L.drift[k] = (T)(a.vfdt * a.ehat[k]);
-    for (int k = tid; k < Q * 3; k += kBlock) L.run[k] = 0.0;
+    for (int k = tid; k < PMAX; k += kBlock) L.drift[k] = k < P ? (T)(a.vfdt * a.ehat[k]) : (T)0;
     if (tid < 16) L.cnt[tid] = 0u;
     __syncthreads();
     const Consts<T>& c = *L.c;
 
     const int g = tid % G;                // rank in the group = node handled
     const int grp = tid / G;
-    const int per_pass = kBlock / G;
-    const int64_t begin = (int64_t)wg * a.chunk;
+    const uint32_t per_pass = kBlock / G;
 
-    for (int p0 = 0; p0 < M; p0 += per_pass) {
-        const int cid = p0 + grp;
-        const bool has = cid < M;
-        int64_t i = begin;
-        if (has) {
-            int w = 0;
-            while (cid >= L.off[w + 1]) ++w;
-            i = begin + a.cand_idx[((size_t)wg * kWaves1 + w) * a.cap_w + (cid - L.off[w])];
-        }
+    for (;;) {
+        if (tid == 0) *L.slot = atomicAdd(a.head, per_pass);
+        __syncthreads();
+        const uint32_t p0 = *L.slot;
+        __syncthreads();
+        if (p0 >= total) break;
+        const uint32_t cid = p0 + grp;
+        if (cid >= total) continue;
+        const int64_t i = a.cand[cid];
         T cx[PMAX], cy[PMAX];
-#pragma unroll
-        for (int h = 0; h < PMAX; ++h) {
-            if (h < P) {
-                cx[h] = a.kx[(size_t)h * a.n + i] - L.drift[h];
-                cy[h] = a.ky[(size_t)h * a.n + i];
-            } else {
-                cx[h] = (T)0; cy[h] = (T)0;
-            }
-        }
-        if (has) {
-            T tc = (T)0;
-            uint32_t coll = 0;
-            const uint32_t ctr0 = (uint32_t)i;
-            for (;;) {
-                // Gamma~ = (1 + alpha) max over the nodes of sum_nu Gamma^nu
-                T smax = (T)0;
-                for (int q = g; q < Q; q += G) {
-                    const T* ps = L.psi + q * P;
-                    T kx = (T)0, ky = (T)0;
-#pragma unroll
-                    for (int h = 0; h < PMAX; ++h)
-                        if (h < P) { kx += cx[h] * ps[h]; ky += cy[h] * ps[h]; }
-                    const T e = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
-                    T r[5];
-                    phonon_rates<T>(c, e, L.eps0[q], r);
-                    T sum = (T)0;
-#pragma unroll
-                    for (int m = 0; m < 5; ++m) sum += r[m];
-                    sum += edge_rate<T>(c, L.ecos, L.cedge[q], L.eps0[q], kx, ky, e);
-                    smax = sum > smax ? sum : smax;
-                }
-                smax = group_max<T>(smax, G);
-                const T Gt = c.alpha1 * smax;
-                const Words wx = philox10(ctr0, a.step, (coll << 8) | kPurXi, a.instance, a.seed_lo,
-                                          a.seed_hi);
-                const T dtc = -dlog(uni<T>(wx.w0, wx.w1)) / Gt;   // eq. dt, node maximum
-                if (!(tc + dtc < a.dt)) break;
-                if (g == 0) atomicAdd(&L.cnt[SGPM_CNT_COLLISIONS], 1u);
-
-                const Words ws = philox10(ctr0, a.step, (coll << 8) | kPurSel, a.instance, a.seed_lo,
-                                          a.seed_hi);
-                const T su = uni<T>(ws.w0, ws.w1), eta = uni<T>(ws.w2, ws.w3);
-                const Words wa = philox10(ctr0, a.step, (coll << 8) | kPurAng, a.instance, a.seed_lo,
-                                          a.seed_hi);
-                const T u1 = uni<T>(wa.w0, wa.w1), u2 = uni<T>(wa.w2, wa.w3);
-                // AC angle: twice the polar angle of a uniform point of the unit
-                // disk centred at (1,0) (density 1 + cos), by the double angle
-                T s_phi, c_phi;
-                dsincospi((T)2 * u2, &s_phi, &c_phi);
-                const T rr = sqrt(u1);
-                const T dx = (T)1 + rr * c_phi, dy = rr * s_phi;
-                const T n2 = dx * dx + dy * dy;
-                const T cac = (dx * dx - dy * dy) / n2, sac = ((T)2 * dx * dy) / n2;
-                T sop, cop;
-                dsincospi((T)2 * u1, &sop, &cop);    // OP angle 2 pi u1
-
-                T px_new[PMAX], py_new[PMAX];
-#pragma unroll
-                for (int h = 0; h < PMAX; ++h) { px_new[h] = (T)0; py_new[h] = (T)0; }
-                uint32_t nev = 0, nrej = 0, nexh = 0;
-                for (int q = g; q < Q; q += G) {
-                    const T* ps = L.psi + q * P;
-                    T kx = (T)0, ky = (T)0;
-#pragma unroll
-                    for (int h = 0; h < PMAX; ++h)
-                        if (h < P) { kx += cx[h] * ps[h]; ky += cy[h] * ps[h]; }
-                    const T e0 = L.eps0[q];
-                    const T e = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
-                    T r[5];
-                    phonon_rates<T>(c, e, e0, r);
-                    int ell = 7;
-                    T cum = (T)0;
-#pragma unroll
-                    for (int m = 0; m < 5; ++m) {
-                        cum += r[m];
-                        if (ell == 7 && su < cum / Gt) ell = m + 1;
-                    }
-                    if (ell == 7) {
-                        cum += edge_rate<T>(c, L.ecos, L.cedge[q], e0, kx, ky, e);
-                        if (su < cum / Gt) ell = 6;
-                    }
-                    T nx = kx, ny = ky;
-                    if (ell != 7) {
-                        const T kabs = sqrt(kx * kx + ky * ky);
-                        const T cin = kabs > (T)0 ? kx / kabs : (T)1;
-                        const T sin_ = kabs > (T)0 ? ky / kabs : (T)0;
-                        T px = kx, py = ky;
-                        bool ok = true;
-                        if (ell == 6) {
-                            // absolute final angle, density exp(-kap (cos t' - cos t_in)^2)
-                            const T kap = c.edge_kap * (kx * kx + ky * ky);
-                            ok = false;
-                            for (uint32_t j = 0; j < (uint32_t)kEdgeTries; ++j) {
-                                const Words we = philox10(ctr0, a.step, (coll << 8) | (kPurEdge0 + j),
-                                                          a.instance, a.seed_lo, a.seed_hi);
-                                const T ut = uni<T>(we.w0, we.w1), v = uni<T>(we.w2, we.w3);
-                                T st, ct;
-                                dsincospi((T)2 * ut, &st, &ct);
-                                const T d = ct - cin;
-                                if (v < dexp(-kap * d * d)) {
-                                    px = kabs * ct; py = kabs * st;
-                                    ok = true;
-                                    break;
-                                }
-                            }
-                            if (!ok) ++nexh;
-                        } else {
-                            T ct, st, mag;
-                            if (ell == 1) { ct = cac; st = sac; mag = kabs; }
-                            else {
-                                const bool op = (ell == 2 || ell == 3);
-                                const T hw = op ? c.hw_o : c.hw_k;
-                                const T de = (ell == 2 || ell == 4) ? -hw : hw;
-                                if (op) { ct = cop; st = sop; } else { ct = -cac; st = -sac; }
-                                if (c.final_state == 1) {
-                                    mag = kabs + de;
-                                } else {
-                                    const T e1 = e + de;     // energy-conserving final state
-                                    mag = sqrt((e1 - e0) * (e1 + e0));
-                                }
-                            }
-                            px = mag * (ct * cin - st * sin_);
-                            py = mag * (st * cin + ct * sin_);
-                        }
-                        if (ok) {
-                            ++nev;
-                            const T f = c.pauli ? pauli_f<T>(a, L, c, q, px, py) : (T)0;
-                            if (f < eta) { nx = px; ny = py; } else { ++nrej; }
-                        }
-                    }
-                    const T* wp = L.wpsi + q * P;
-#pragma unroll
-                    for (int h = 0; h < PMAX; ++h)
-                        if (h < P) { px_new[h] += wp[h] * nx; py_new[h] += wp[h] * ny; }
-                }
-                if (nev) atomicAdd(&L.cnt[SGPM_CNT_EVENTS], nev);
-                if (nrej) atomicAdd(&L.cnt[SGPM_CNT_PAULI_REJ], nrej);
-                if (nexh) atomicAdd(&L.cnt[SGPM_CNT_EDGE_EXH], nexh);
-                // k_h = sum_q w_q Psi_h(z_q) k_q  (group sum over the nodes)
-#pragma unroll
-                for (int h = 0; h < PMAX; ++h) {
-                    if (h < P) {
-                        cx[h] = group_sum<T>(px_new[h], G);
-                        cy[h] = group_sum<T>(py_new[h], G);
-                    }
-                }
-                tc += dtc;
-                ++coll;
-                if (coll >= (uint32_t)c.c_max) {
-                    if (g == 0) atomicAdd(&L.cnt[SGPM_CNT_CMAX], 1u);
-                    break;
-                }
-            }
-#pragma unroll
-            for (int h = 0; h < PMAX; ++h)
-                if (h < P && (h % G) == g) {
-                    a.kx[(size_t)h * a.n + i] = cx[h];
-                    a.ky[(size_t)h * a.n + i] = cy[h];
-                }
-        }
-        // final node values: H^{n+1} cells and the pass's sums per (candidate, node)
-        for (int q = g; q < Q; q += G) {
-            double vx = 0.0, vy = 0.0, en = 0.0;
-            if (has) {
-                const T* ps = L.psi + q * P;
-                T kx = (T)0, ky = (T)0;
-#pragma unroll
-                for (int h = 0; h < PMAX; ++h)
-                    if (h < P) { kx += cx[h] * ps[h]; ky += cy[h] * ps[h]; }
+        load_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, i, L.drift, cx, cy);
+        T tc = (T)0;
+        uint32_t coll = 0;
+        const uint32_t ctr0 = (uint32_t)i;
+        for (;;) {
+            // Gamma~ = (1 + alpha) max over the nodes of sum_nu Gamma^nu
+            T smax = (T)0;
+            for (int q = g; q < Q; q += G) {
+                T kx, ky;
+                eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
                 const T e = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
-                const T inv = (T)1 / e;
-                const int r = cell_coord<T>(kx, c.lk, c.dk, c.inv_dk);
-                const int l = cell_coord<T>(ky, c.lk, c.dk, c.inv_dk);
-                if (r < 0 || l < 0 || r >= c.nk || l >= c.nk)
-                    atomicAdd(&L.cnt[SGPM_CNT_OUT_OF_GRID], 1u);
-                else
-                    atomicAdd(&a.h_acc[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l], 1u);
-                vx = (double)(c.v_f * kx * inv);
-                vy = (double)(c.v_f * ky * inv);
-                en = (double)e;
+                T r[5];
+                phonon_rates<T>(c, e, L.eps0[q], r);
+                T sum = (T)0;
+#pragma unroll
+                for (int m = 0; m < 5; ++m) sum += r[m];
+                sum += edge_rate<T>(c, L.ecos, L.cedge[q], L.eps0[q], kx, ky, e);
+                smax = sum > smax ? sum : smax;
             }
-            double* dst = L.pass + ((size_t)grp * Q + q) * 3;
-            dst[0] = vx; dst[1] = vy; dst[2] = en;
+            smax = group_max<T>(smax, G);
+            const T Gt = c.alpha1 * smax;
+            const Words wx = philox10(ctr0, a.step, (coll << 8) | kPurXi, a.instance, a.seed_lo,
+                                      a.seed_hi);
+            const T dtc = -dlog(uni<T>(wx.w0, wx.w1)) / Gt;   // eq. dt, node maximum
+            if (!(tc + dtc < a.dt)) break;
+            if (g == 0) atomicAdd(&L.cnt[SGPM_CNT_COLLISIONS], 1u);
+
+            const Words ws = philox10(ctr0, a.step, (coll << 8) | kPurSel, a.instance, a.seed_lo,
+                                      a.seed_hi);
+            const T su = uni<T>(ws.w0, ws.w1), eta = uni<T>(ws.w2, ws.w3);
+            const Words wa = philox10(ctr0, a.step, (coll << 8) | kPurAng, a.instance, a.seed_lo,
+                                      a.seed_hi);
+            const T u1 = uni<T>(wa.w0, wa.w1), u2 = uni<T>(wa.w2, wa.w3);
+            // AC angle: twice the polar angle of a uniform point of the unit
+            // disk centred at (1,0) (density 1 + cos), by the double angle
+            T s_phi, c_phi;
+            dsincospi((T)2 * u2, &s_phi, &c_phi);
+            const T rr = sqrt(u1);
+            const T dx = (T)1 + rr * c_phi, dy = rr * s_phi;
+            const T n2 = dx * dx + dy * dy;
+            const T cac = (dx * dx - dy * dy) / n2, sac = ((T)2 * dx * dy) / n2;
+            T sop, cop;
+            dsincospi((T)2 * u1, &sop, &cop);    // OP angle 2 pi u1
+
+            T px_new[PMAX], py_new[PMAX];
+#pragma unroll
+            for (int h = 0; h < PMAX; ++h) { px_new[h] = (T)0; py_new[h] = (T)0; }
+            uint32_t nev = 0, nrej = 0, nexh = 0;
+            for (int q = g; q < Q; q += G) {
+                T kx, ky;
+                eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
+                const T e0 = L.eps0[q];
+                const T e = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
+                T r[5];
+                phonon_rates<T>(c, e, e0, r);
+                int ell = 7;
+                T cum = (T)0;
+#pragma unroll
+                for (int m = 0; m < 5; ++m) {
+                    cum += r[m];
+                    if (ell == 7 && su < cum / Gt) ell = m + 1;
+                }
+                if (ell == 7) {
+                    cum += edge_rate<T>(c, L.ecos, L.cedge[q], e0, kx, ky, e);
+                    if (su < cum / Gt) ell = 6;
+                }
+                T nx = kx, ny = ky;
+                if (ell != 7) {
+                    const T kabs = sqrt(kx * kx + ky * ky);
+                    const T cin = kabs > (T)0 ? kx / kabs : (T)1;
+                    const T sin_ = kabs > (T)0 ? ky / kabs : (T)0;
+                    T px = kx, py = ky;
+                    bool ok = true;
+                    if (ell == 6) {
+                        // absolute final angle, density exp(-kap (cos t' - cos t_in)^2)
+                        const T kap = c.edge_kap * (kx * kx + ky * ky);
+                        ok = false;
+                        for (uint32_t j = 0; j < (uint32_t)kEdgeTries; ++j) {
+                            const Words we = philox10(ctr0, a.step, (coll << 8) | (kPurEdge0 + j),
+                                                      a.instance, a.seed_lo, a.seed_hi);
+                            const T ut = uni<T>(we.w0, we.w1), v = uni<T>(we.w2, we.w3);
+                            T st, ct;
+                            dsincospi((T)2 * ut, &st, &ct);
+                            const T d = ct - cin;
+                            if (v < dexp(-kap * d * d)) {
+                                px = kabs * ct; py = kabs * st;
+                                ok = true;
+                                break;
+                            }
+                        }
+                        if (!ok) ++nexh;
+                    } else {
+                        T ct, st, mag;
+                        if (ell == 1) { ct = cac; st = sac; mag = kabs; }
+                        else {
+                            const bool op = (ell == 2 || ell == 3);
+                            const T hw = op ? c.hw_o : c.hw_k;
+                            const T de = (ell == 2 || ell == 4) ? -hw : hw;
+                            if (op) { ct = cop; st = sop; } else { ct = -cac; st = -sac; }
+                            if (c.final_state == 1) {
+                                mag = kabs + de;
+                            } else {
+                                const T e1 = e + de;     // energy-conserving final state
+                                mag = sqrt((e1 - e0) * (e1 + e0));
+                            }
+                        }
+                        px = mag * (ct * cin - st * sin_);
+                        py = mag * (st * cin + ct * sin_);
+                    }
+                    if (ok) {
+                        ++nev;
+                        const T f = c.pauli ? pauli_f<T>(a, L, c, q, px, py) : (T)0;
+                        if (f < eta) { nx = px; ny = py; } else { ++nrej; }
+                    }
+                }
+                const T* wp = L.wpsi + q * PMAX;
+#pragma unroll
+                for (int h = 0; h < PMAX; ++h) { px_new[h] += wp[h] * nx; py_new[h] += wp[h] * ny; }
+            }
+            if (nev) atomicAdd(&L.cnt[SGPM_CNT_EVENTS], nev);
+            if (nrej) atomicAdd(&L.cnt[SGPM_CNT_PAULI_REJ], nrej);
+            if (nexh) atomicAdd(&L.cnt[SGPM_CNT_EDGE_EXH], nexh);
+            // k_h = sum_q w_q Psi_h(z_q) k_q  (group sum over the nodes)
+#pragma unroll
+            for (int h = 0; h < PMAX; ++h) {
+                cx[h] = group_sum<T>(px_new[h], G);
+                cy[h] = group_sum<T>(py_new[h], G);
+            }
+            tc += dtc;
+            ++coll;
+            if (coll >= (uint32_t)c.c_max) {
+                if (g == 0) atomicAdd(&L.cnt[SGPM_CNT_CMAX], 1u);
+                break;
+            }
         }
-        __syncthreads();
-        // running sums per node, candidates in list order
-        for (int k = tid; k < Q * 3; k += kBlock) {
-            const int q = k / 3, o = k % 3;
-            double s = L.run[k];
-            for (int gg = 0; gg < per_pass && p0 + gg < M; ++gg) s += L.pass[((size_t)gg * Q + q) * 3 + o];
-            L.run[k] = s;
-        }
-        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < PMAX; ++h)
+            if (h < P && (h % G) == g) {
+                a.kx[(size_t)h * a.n + i] = cx[h];
+                a.ky[(size_t)h * a.n + i] = cy[h];
+            }
     }
-    // add the candidates' sums to the stream workgroup's partial sums
-    for (int k = tid; k < Q * 3; k += kBlock) a.partial[(size_t)wg * Q * 3 + k] += L.run[k];
+    __syncthreads();
     if (tid < 8 && L.cnt[tid]) atomicAdd(&a.counters[tid], (unsigned long long)L.cnt[tid]);
 }
 
 // ===================================================== K3: finalize kernel
-__global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args a) {
-    const int q = blockIdx.x, tid = threadIdx.x;
-    const size_t cells = (size_t)a.nk * a.nk;
-    const uint32_t* h = a.h_acc + (size_t)q * cells;
-    uint32_t* z = a.h_clr + (size_t)q * cells;
-    uint32_t m = 0;
-    for (size_t k = tid; k < cells; k += kBlock) {
-        const uint32_t v = h[k];
-        m = v > m ? v : m;
-        z[k] = 0u;
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const uint32_t o = __shfl_xor(m, off, 64);
-        m = o > m ? o : m;
-    }
-    __shared__ uint32_t wm[kWaves];
-    if ((tid & 63) == 0) wm[tid >> 6] = m;
+// Workgroups [0, n_win_wg): kK3Words window words each (two cells per word),
+// every slab summed, plus the overflow count, into H^n.  Workgroups after
+// that: kK3Rest cells of the rest of the grid (overflow count only).  Every
+// workgroup zeroes the overflow cells it read and contributes its maximum;
+// workgroup (q + Q b) also reduces moment batch b of node q.
+__global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args a, const double* partial,
+                                                      int nwg, int nb, double* record) {
+    const int tid = threadIdx.x;
+    const int cells = a.nk * a.nk;
+    const int wcells = a.win * a.win;
+    __shared__ uint32_t part[kK3Lanes][kK3Words][2];
+    __shared__ uint32_t smax[kMaxQ];
+    for (int k = tid; k < a.Q; k += kBlock) smax[k] = 0u;
     __syncthreads();
-    if (tid == 0) {
-        uint32_t mm = 0;
-        for (int w = 0; w < kWaves; ++w) mm = wm[w] > mm ? wm[w] : mm;
-        a.hmax_out[q] = mm;
+    if ((int)blockIdx.x < a.n_win_wg) {
+        // 16 columns of four words, kK3Lanes slab lanes; 16-byte loads
+        const int col = tid % (kK3Words / 4);
+        const int lane = tid / (kK3Words / 4);
+        const int word0 = blockIdx.x * kK3Words + 4 * col;
+        uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
+        if (word0 < a.hwin_words) {
+            const uint32_t* src = a.slabs + word0;
+#pragma unroll 4
+            for (int s = lane; s < nwg; s += kK3Lanes) {
+                const uint4 v = *reinterpret_cast<const uint4*>(src + (size_t)s * a.hwin_words);
+                lo[0] += v.x & 0xFFFFu; hi[0] += v.x >> 16;
+                lo[1] += v.y & 0xFFFFu; hi[1] += v.y >> 16;
+                lo[2] += v.z & 0xFFFFu; hi[2] += v.z >> 16;
+                lo[3] += v.w & 0xFFFFu; hi[3] += v.w >> 16;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { part[lane][4 * col + j][0] = lo[j]; part[lane][4 * col + j][1] = hi[j]; }
+        __syncthreads();
+        if (tid < 2 * kK3Words) {
+            const int wl = tid >> 1, half = tid & 1;
+            const int word = blockIdx.x * kK3Words + wl;
+            uint32_t sum = 0u;
+#pragma unroll
+            for (int k = 0; k < kK3Lanes; ++k) sum += part[k][wl][half];
+            const int idx = 2 * word + half;
+            if (word < a.hwin_words && idx < a.Q * wcells) {
+                const int q = idx / wcells, rem = idx - q * wcells;
+                const int r = a.win_r0 + rem / a.win, l = a.win_l0 + rem % a.win;
+                const size_t g = (size_t)q * cells + (size_t)r * a.nk + l;
+                sum += a.extra[g];
+                a.extra[g] = 0u;
+                a.h_out[g] = sum;
+                if (sum) atomicMax(&smax[q], sum);
+            }
+        }
+    } else {
+        const int64_t c0 = (int64_t)(blockIdx.x - a.n_win_wg) * kK3Rest;
+        const int64_t total = (int64_t)a.Q * cells;
+        for (int64_t g = c0 + tid; g < c0 + kK3Rest && g < total; g += kBlock) {
+            const int q = (int)(g / cells), rem = (int)(g - (int64_t)q * cells);
+            const int r = rem / a.nk, l = rem - r * a.nk;
+            const int wr = r - a.win_r0, wl = l - a.win_l0;
+            if ((unsigned)wr < (unsigned)a.win && (unsigned)wl < (unsigned)a.win) continue;
+            const uint32_t v = a.extra[g];
+            a.extra[g] = 0u;
+            a.h_out[g] = v;
+            if (v) atomicMax(&smax[q], v);
+        }
     }
-    // moment record: batch b collects the workgroups w = b (mod NB), in order
-    for (int k = tid; k < a.nb * 3; k += kBlock) {
-        const int b = k / 3, o = k % 3;
-        double s = 0.0;
-        for (int w = b; w < a.nwg; w += a.nb) s += a.partial[((size_t)w * a.Q + q) * 3 + o];
-        a.record[((size_t)b * a.Q + q) * 3 + o] = s;
+    __syncthreads();
+    for (int k = tid; k < a.Q; k += kBlock)
+        if (smax[k]) atomicMax(&a.hmax_out[k], smax[k]);
+    if (blockIdx.x == 0) {
+        for (int k = tid; k < a.Q; k += kBlock) a.hmax_clr[k] = 0u;
+        if (tid < 2) a.reset[tid] = 0u;
+    }
+    // moment record: batch b of node q collects the stream workgroups w = b (mod NB)
+    if ((int)blockIdx.x < a.Q * nb && tid < 3) {
+        const int q = blockIdx.x % a.Q, b = blockIdx.x / a.Q;
+        double sum = 0.0;
+        for (int w = b; w < nwg; w += nb) sum += partial[((size_t)w * a.Q + q) * 3 + tid];
+        record[((size_t)b * a.Q + q) * 3 + tid] = sum;
     }
 }
 
 // ------------------------------------------------------------ launchers
 template <typename T, int PMAX, int QMAX>
 static int launch_k1_t(const K1Args<T>& a, int nwg, void* stream) {
-    const size_t lds = k1_lds_bytes(a.P, a.Q, sizeof(T) == 4, a.hwin_words);
+    const size_t lds = k1_lds_bytes(a.P, a.Q, sizeof(T) == 4, a.hwin_words, (int)a.chunk);
     hipLaunchKernelGGL((k1_stream<T, PMAX, QMAX>), dim3(nwg), dim3(kBlock1), lds,
                        (hipStream_t)stream, a);
     return (int)hipGetLastError();
@@ -737,38 +771,54 @@ template <typename T, int PMAX>
 static int launch_k1_q(const K1Args<T>& a, int nwg, void* stream) {
     if (a.Q <= 1) return launch_k1_t<T, PMAX, 1>(a, nwg, stream);
     if (a.Q <= 8) return launch_k1_t<T, PMAX, 8>(a, nwg, stream);
-    if (a.Q <= 16) return launch_k1_t<T, PMAX, 16>(a, nwg, stream);
+    if (a.Q <= 12) return launch_k1_t<T, PMAX, 12>(a, nwg, stream);
     return launch_k1_t<T, PMAX, 0>(a, nwg, stream);
 }
 
 template <typename T>
 static int launch_k1_any(const K1Args<T>& a, int nwg, void* stream) {
-    if (a.P <= 1) return launch_k1_q<T, 1>(a, nwg, stream);
-    if (a.P <= 8) return launch_k1_q<T, 8>(a, nwg, stream);
-    if (a.P <= 16) return launch_k1_q<T, 16>(a, nwg, stream);
-    return launch_k1_q<T, 32>(a, nwg, stream);
+    switch (pmax_bucket(a.P)) {
+    case 1: return launch_k1_q<T, 1>(a, nwg, stream);
+    case 3: return launch_k1_q<T, 3>(a, nwg, stream);
+    case 6: return launch_k1_q<T, 6>(a, nwg, stream);
+    case 9: return launch_k1_q<T, 9>(a, nwg, stream);
+    case 16: return launch_k1_q<T, 16>(a, nwg, stream);
+    default: return launch_k1_q<T, 32>(a, nwg, stream);
+    }
 }
 
 int launch_k1_f64(const K1Args<double>& a, int nwg, void* s) { return launch_k1_any<double>(a, nwg, s); }
 int launch_k1_f32(const K1Args<float>& a, int nwg, void* s) { return launch_k1_any<float>(a, nwg, s); }
+
+// persistent collider grid: enough workgroups to fill the device
+int k2_grid() { return 1024; }
 
 template <typename T>
 static int launch_k2_any(const K2Args<T>& a, int nwg, void* stream) {
     const size_t lds = k2_lds_bytes(a.P, a.Q, sizeof(T) == 4);
     const dim3 grid(nwg), blk(kBlock);
     const hipStream_t s = (hipStream_t)stream;
-    if (a.P <= 1) hipLaunchKernelGGL((k2_collide<T, 1>), grid, blk, lds, s, a);
-    else if (a.P <= 8) hipLaunchKernelGGL((k2_collide<T, 8>), grid, blk, lds, s, a);
-    else if (a.P <= 16) hipLaunchKernelGGL((k2_collide<T, 16>), grid, blk, lds, s, a);
-    else hipLaunchKernelGGL((k2_collide<T, 32>), grid, blk, lds, s, a);
+    switch (pmax_bucket(a.P)) {
+    case 1: hipLaunchKernelGGL((k2_collide<T, 1>), grid, blk, lds, s, a); break;
+    case 3: hipLaunchKernelGGL((k2_collide<T, 3>), grid, blk, lds, s, a); break;
+    case 6: hipLaunchKernelGGL((k2_collide<T, 6>), grid, blk, lds, s, a); break;
+    case 9: hipLaunchKernelGGL((k2_collide<T, 9>), grid, blk, lds, s, a); break;
+    case 16: hipLaunchKernelGGL((k2_collide<T, 16>), grid, blk, lds, s, a); break;
+    default: hipLaunchKernelGGL((k2_collide<T, 32>), grid, blk, lds, s, a); break;
+    }
     return (int)hipGetLastError();
 }
 
 int launch_k2_f64(const K2Args<double>& a, int nwg, void* s) { return launch_k2_any<double>(a, nwg, s); }
 int launch_k2_f32(const K2Args<float>& a, int nwg, void* s) { return launch_k2_any<float>(a, nwg, s); }
 
-int launch_k3(const K3Args& a, void* stream) {
-    hipLaunchKernelGGL(k3_finalize, dim3(a.Q), dim3(kBlock), 0, (hipStream_t)stream, a);
+int launch_k3(const K3Args& a, int nwg, int nb, const double* partial, double* record,
+              void* stream) {
+    const int64_t rest = ((int64_t)a.Q * a.nk * a.nk + kK3Rest - 1) / kK3Rest;
+    int64_t grid = (int64_t)a.n_win_wg + rest;
+    if (grid < (int64_t)a.Q * nb) grid = (int64_t)a.Q * nb;
+    hipLaunchKernelGGL(k3_finalize, dim3((unsigned)grid), dim3(kBlock), 0, (hipStream_t)stream, a,
+                       partial, nwg, nb, record);
     return (int)hipGetLastError();
 }
 
