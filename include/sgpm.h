@@ -83,6 +83,18 @@ enum {
     SGPM_N_COUNTERS = 8
 };
 
+/* Step kernels, in the order they run within a step (sgpm_kernel_times). */
+enum {
+    SGPM_KERNEL_STREAM = 0,    /* drift, node evaluation, histogram window, moments,
+                                  rate bound and candidate list (all particles)     */
+    SGPM_KERNEL_FINALIZE = 1,  /* H^n and its maxima, moment record of t^n          */
+    SGPM_KERNEL_COLLIDE = 2,   /* collision loop of the candidates (Algorithm 2)    */
+    SGPM_N_KERNELS = 3
+};
+
+/* Largest number of instances of one context. */
+#define SGPM_MAX_INSTANCES 1024
+
 /* One simulation instance.  Defaults in brackets are the paper's. */
 typedef struct {
     int32_t dim_z;          /* number of uncertain inputs: 0, 1 or 2              */
@@ -122,7 +134,11 @@ sgpm_status sgpm_workspace_bytes(const sgpm_instance_desc* descs, int32_t n_inst
  * Builds the FP64 set-up tables on the host (nodes, weights, basis, Galerkin
  * field coefficients, rate constants of the Appendix, Fermi-Dirac CDF
  * tables) and uploads them.  *out receives the context (host memory owned
- * by the library, released by sgpm_destroy). */
+ * by the library, released by sgpm_destroy).  1 <= n_inst <=
+ * SGPM_MAX_INSTANCES.  Instances of the same precision and similar size of
+ * basis and node set are stepped by shared launches (one per kernel and
+ * step for the whole group); the particles of different instances never
+ * interact. */
 sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* dev_workspace,
                         size_t ws_bytes, void* hip_stream, sgpm_ctx** out);
 
@@ -133,8 +149,26 @@ sgpm_status sgpm_init_particles(sgpm_ctx* ctx);
 
 /* Advance every instance by n_steps steps of length dt_s (Sec. 4.1: Galerkin
  * drift, then the collision step of Algorithm 2 against H^n; H^{n+1} and the
- * moments at t^{n+1} are built by the same pass).  Asynchronous. */
+ * moments at t^{n+1} are built by the same pass).  Asynchronous.  By default
+ * the steps are replayed from captured HIP graphs of a block of steps
+ * (sgpm_set_graph); results do not depend on how they are launched. */
 sgpm_status sgpm_step(sgpm_ctx* ctx, double dt_s, int64_t n_steps);
+
+/* Launch mode of sgpm_step: 0 = every kernel launched on the stream; B >= 1
+ * = blocks of B steps captured once as a HIP graph (on a private stream) and
+ * replayed on the context's stream, remainders from a graph of their own
+ * length.  B <= 256; default 16.  Graphs are rebuilt after sgpm_set_chunk. */
+sgpm_status sgpm_set_graph(sgpm_ctx* ctx, int32_t steps_per_graph);
+
+/* on != 0: the following sgpm_step calls launch every kernel on the stream
+ * with a HIP event after each, for sgpm_kernel_times (slightly slower). */
+sgpm_status sgpm_set_profiling(sgpm_ctx* ctx, int32_t on);
+
+/* Per-kernel device time of the last profiled sgpm_step call: avg_ms[k] =
+ * mean time between the events around launch k of kind SGPM_KERNEL_*,
+ * launches[k] = their number (may be NULL).  Arrays of SGPM_N_KERNELS.
+ * Waits for the last event.  Zeros if no profiled call was made. */
+sgpm_status sgpm_kernel_times(sgpm_ctx* ctx, double* avg_ms, int64_t* launches);
 
 /* Global step counter (the random streams are keyed by it). */
 sgpm_status sgpm_step_count(const sgpm_ctx* ctx, int64_t* steps);
@@ -202,8 +236,9 @@ sgpm_status sgpm_tables(const sgpm_ctx* ctx, int32_t inst, double* z, double* w,
  * init/set_state (the current time is re-recorded). */
 sgpm_status sgpm_set_chunk(sgpm_ctx* ctx, int32_t inst, int32_t chunk);
 
-/* Average device time (ms) of the step kernel over the last sgpm_step call,
- * measured with HIP events on the context's stream; 0 if none. */
+/* Device time (ms) of the last sgpm_step call divided by its step count,
+ * measured with HIP events on the context's stream around all of its work
+ * (the steps and the closing pass over the final state); 0 if none. */
 sgpm_status sgpm_last_step_ms(sgpm_ctx* ctx, double* ms_per_step);
 
 void sgpm_destroy(sgpm_ctx* ctx);

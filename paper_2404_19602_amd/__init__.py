@@ -13,8 +13,8 @@ import os
 
 import numpy as np
 
-from ._lib import (AGG_NAMES, COUNTER_NAMES, Desc, SgpmError, check, desc_from_cfg, lib,
-                   LIB_PATH)
+from ._lib import (AGG_NAMES, COUNTER_NAMES, KERNEL_NAMES, Desc, SgpmError, check, desc_from_cfg,
+                   lib, LIB_PATH)
 
 __all__ = ["Simulation", "philox_device", "SgpmError", "AGG_NAMES", "COUNTER_NAMES", "LIB_PATH"]
 
@@ -96,6 +96,22 @@ class Simulation:
 
     def set_chunk(self, chunk: int, inst: int = 0):
         check(lib().sgpm_set_chunk(self._ctx, inst, chunk), self._ctx, "set_chunk")
+
+    def set_graph(self, steps_per_graph: int):
+        """0: launch every kernel; B >= 1: replay captured graphs of B steps."""
+        check(lib().sgpm_set_graph(self._ctx, steps_per_graph), self._ctx, "set_graph")
+
+    def set_profiling(self, on: bool):
+        check(lib().sgpm_set_profiling(self._ctx, 1 if on else 0), self._ctx, "set_profiling")
+
+    def kernel_times(self) -> dict:
+        """Mean device time (ms) and launch count of each step kernel over the
+        last profiled step call."""
+        ms = np.zeros(len(KERNEL_NAMES))
+        n = np.zeros(len(KERNEL_NAMES), dtype=np.int64)
+        check(lib().sgpm_kernel_times(self._ctx, ms.ctypes.data_as(C.c_void_p),
+                                      n.ctypes.data_as(C.c_void_p)), self._ctx, "kernel_times")
+        return {name: (float(ms[k]), int(n[k])) for k, name in enumerate(KERNEL_NAMES)}
 
     def moments(self, first: int = 0, count: int | None = None, inst: int = 0) -> dict:
         P, Q = self.sizes[inst]

@@ -8,6 +8,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsgpm.so"
 
 COUNTER_NAMES = ("collisions", "events", "pauli_rejected", "edge_exhausted", "cmax_hits",
                  "out_of_grid", "candidates", "reserved")
+KERNEL_NAMES = ("stream", "finalize", "collide")
 AGG_NAMES = ("E_vx", "Var_vx", "E_jx", "Var_jx", "E_energy", "Var_energy", "SE_E_vx",
              "SE_Var_vx", "SE_E_jx", "SE_Var_jx", "SE_E_energy", "SE_Var_energy")
 
@@ -63,6 +64,9 @@ def lib():
             "sgpm_tables": (i32, [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
             "sgpm_set_chunk": (i32, [vp, i32, i32]),
             "sgpm_last_step_ms": (i32, [vp, C.POINTER(dbl)]),
+            "sgpm_set_graph": (i32, [vp, i32]),
+            "sgpm_set_profiling": (i32, [vp, i32]),
+            "sgpm_kernel_times": (i32, [vp, vp, vp]),
             "sgpm_destroy": (None, [vp]),
             "sgpm_last_error": (C.c_char_p, [vp]),
             "sgpm_status_string": (C.c_char_p, [i32]),

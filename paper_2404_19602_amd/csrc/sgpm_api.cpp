@@ -2,8 +2,16 @@
 // workspace, set-up tables, launches of the gfx950 kernels and the host-side
 // finalisation of the moment record (expectations and variances over z by
 // the nodal quadrature, Sec. 4.2; Monte Carlo errors by batch means).
+//
+// Orchestration.  Instances of the same shape (precision, padded mode count,
+// node bucket) form a group; one launch of each step kernel serves the whole
+// group, reading per-instance descriptors from device memory.  Everything
+// that changes from step to step (the step counter, the record index, dt)
+// also lives in device memory, so the launches of one step never change and
+// a block of steps is captured once as a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -19,6 +27,8 @@ namespace {
 
 constexpr double kECharge = 1.602176634e-19;
 constexpr int kMaxBins = 4096;
+constexpr int kDefaultGraphSteps = 16;
+constexpr int kMaxGraphSteps = 256;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -32,16 +42,18 @@ struct Instance {
     int nwg = 1, nb = 1;
     int win = 0, win_r0 = 0, win_l0 = 0, hwin_words = 0;
     int64_t hstride = 0;       // words per histogram buffer (padded)
+    int64_t hmstride = 0;      // words per maximum buffer
     int64_t step = 0;          // global step counter (random streams)
     int64_t rec_base = 0;      // step counter of record index 0
     bool initialised = false;
+    int grp = 0, pos = 0;      // shape group and slot in the descriptor arrays
     // device pointers
     void* kx = nullptr;
     void* ky = nullptr;
     uint32_t* H = nullptr;     // [3][hstride] H^n for the Pauli lookups
     uint32_t* extra = nullptr; // [hstride] overflow counts of H^{n+1}
     uint32_t* slabs = nullptr; // [nwg_max][hwin_words] window slabs
-    uint32_t* Hmax = nullptr;  // [3][64]
+    uint32_t* Hmax = nullptr;  // [3][hmstride]
     double* partial = nullptr; // [nwg_max][Q][3]
     double* record = nullptr;  // [max_steps+1][NB][Q][3]
     unsigned long long* counters = nullptr;
@@ -62,6 +74,16 @@ struct Instance {
     uint32_t* qc = nullptr;    // [2][2] candidate count and work head, by step parity
 };
 
+// Instances of one shape, stepped by one launch of each kernel.
+struct Group {
+    bool fp32 = false;
+    int pmax = 1, qmax = 1;
+    std::vector<int> members;  // instance indices, in slot order
+    int pos0 = 0;              // first slot
+    unsigned k1_grid = 0, k3_grid = 0;
+    size_t k1_lds = 0, k2_lds = 0;
+};
+
 // Bytes of every device region of one instance, in carving order.
 struct Layout {
     size_t total = 0;
@@ -74,6 +96,28 @@ struct Layout {
         return o;
     }
 };
+
+// Context region at the start of the workspace: step states, descriptor
+// arrays and workgroup tables of n instances.
+struct CtxLayout {
+    size_t dyn, k1d, k1f, k2d, k2f, k3, wg, done, total;
+};
+
+CtxLayout ctx_layout(int n) {
+    CtxLayout L;
+    size_t o = 0;
+    auto put = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    L.dyn = put((size_t)n * sizeof(Dyn));
+    L.k1d = put((size_t)n * sizeof(K1Args<double>));
+    L.k1f = put((size_t)n * sizeof(K1Args<float>));
+    L.k2d = put((size_t)n * sizeof(K2Args<double>));
+    L.k2f = put((size_t)n * sizeof(K2Args<float>));
+    L.k3 = put((size_t)n * sizeof(K3Args));
+    L.wg = put((size_t)10 * n * sizeof(uint32_t));   // 3 group tables + 2 single tables, 2n each
+    L.done = put((size_t)n * 64);
+    L.total = o;
+    return L;
+}
 
 int64_t min_chunk(int64_t n) {
     // at most kMaxStreamWG stream workgroups
@@ -151,16 +195,42 @@ Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
     return L;
 }
 
+// HIP events around every kernel of a profiled step call.
+struct Prof {
+    std::vector<hipEvent_t> ev;   // pool, grown on demand
+    std::vector<int> kind;        // kernel kind between event k and k + 1
+    size_t used = 0;              // events recorded in the last profiled call
+};
+
 }  // namespace
 
 struct sgpm_ctx {
     std::vector<Instance> inst;
+    std::vector<Group> groups;
     hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;     // private stream the graphs are captured on
     std::string err;
     bool poisoned = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool timed = false;
     int64_t timed_steps = 0;
+    // device context region
+    Dyn* dyn = nullptr;
+    K1Args<double>* k1d = nullptr; K1Args<float>* k1f = nullptr;
+    K2Args<double>* k2d = nullptr; K2Args<float>* k2f = nullptr;
+    K3Args* k3 = nullptr;
+    uint32_t* wg = nullptr;        // [5][2n] workgroup tables
+    uint32_t* done = nullptr;      // [n][16] collider completion counters by group
+    // host mirrors of the descriptor arrays
+    std::vector<K1Args<double>> h_k1d; std::vector<K1Args<float>> h_k1f;
+    std::vector<K2Args<double>> h_k2d; std::vector<K2Args<float>> h_k2f;
+    std::vector<K3Args> h_k3;
+    std::vector<uint32_t> h_wg;
+    // graphs of a block of steps, by block length
+    int graph_steps = kDefaultGraphSteps;
+    std::vector<std::pair<int, hipGraphExec_t>> graphs;
+    bool profiling = false;
+    Prof prof;
 };
 
 namespace {
@@ -244,13 +314,8 @@ Consts<T> make_consts(const sgpm_instance_desc& d, const HostTables& t) {
     return c;
 }
 
-uint32_t* hbuf(const Instance& I, int64_t k) { return I.H + (size_t)(k % 3) * I.hstride; }
-uint32_t* hmbuf(const Instance& I, int64_t k) {
-    return I.Hmax + (size_t)(k % 3) * 64 * ((I.Q + 63) / 64);
-}
-
 template <typename T>
-K1Args<T> make_k1(const Instance& I, double dt, bool moving, int64_t step) {
+K1Args<T> make_k1(const sgpm_ctx* cx, const Instance& I) {
     K1Args<T> a;
     std::memset(&a, 0, sizeof(a));
     a.kx = static_cast<T*>(I.kx);
@@ -258,26 +323,23 @@ K1Args<T> make_k1(const Instance& I, double dt, bool moving, int64_t step) {
     a.n = I.n; a.P = I.P; a.Q = I.Q;
     a.tab = dev_tab<T>(I);
     a.ehat = I.d_ehat;
-    a.vfdt = I.t.v_f * dt;
-    a.dt = (T)dt;
+    a.dyn = cx->dyn + I.pos;
     a.seed_lo = (uint32_t)(I.d.seed & 0xFFFFFFFFu);
     a.seed_hi = (uint32_t)(I.d.seed >> 32);
     a.instance = I.d.instance_id;
-    a.step = (uint32_t)step;
     a.extra = I.extra;
     a.slabs = I.slabs;
     a.win = I.win; a.win_r0 = I.win_r0; a.win_l0 = I.win_l0; a.hwin_words = I.hwin_words;
     a.partial = I.partial;
     a.cand = I.cand;
-    a.cand_count = I.qc + 2 * (step & 1);
+    a.qc = I.qc;
     a.counters = I.counters;
     a.chunk = I.chunk;
-    a.do_collide = moving ? 1 : 0;
     return a;
 }
 
 template <typename T>
-K2Args<T> make_k2(const Instance& I, double dt, int64_t step) {
+K2Args<T> make_k2(const sgpm_ctx* cx, const Instance& I) {
     K2Args<T> a;
     std::memset(&a, 0, sizeof(a));
     a.kx = static_cast<T*>(I.kx);
@@ -288,57 +350,193 @@ K2Args<T> make_k2(const Instance& I, double dt, int64_t step) {
     a.G = G;
     a.tab = dev_tab<T>(I);
     a.ehat = I.d_ehat;
-    a.vfdt = I.t.v_f * dt;
-    a.dt = (T)dt;
+    a.dyn = cx->dyn + I.pos;
     a.seed_lo = (uint32_t)(I.d.seed & 0xFFFFFFFFu);
     a.seed_hi = (uint32_t)(I.d.seed >> 32);
     a.instance = I.d.instance_id;
-    a.step = (uint32_t)step;
-    a.h_read = hbuf(I, step);
-    a.hmax_read = hmbuf(I, step);
+    a.H = I.H; a.Hmax = I.Hmax;
+    a.hstride = I.hstride; a.hmstride = I.hmstride;
     a.cand = I.cand;
-    a.cand_count = I.qc + 2 * (step & 1);
-    a.head = I.qc + 2 * (step & 1) + 1;
+    a.qc = I.qc;
     a.counters = I.counters;
     return a;
 }
 
-K3Args make_k3(const Instance& I, int64_t step) {
+K3Args make_k3(const sgpm_ctx* cx, const Instance& I) {
     K3Args a;
+    std::memset(&a, 0, sizeof(a));
     a.Q = I.Q; a.nk = I.nk;
     a.slabs = I.slabs;
     a.hwin_words = I.hwin_words; a.win = I.win; a.win_r0 = I.win_r0; a.win_l0 = I.win_l0;
     a.extra = I.extra;
-    a.h_out = hbuf(I, step);
-    a.hmax_out = hmbuf(I, step);
-    a.hmax_clr = hmbuf(I, step + 1);
-    a.reset = I.qc + 2 * ((step + 1) & 1);
+    a.H = I.H; a.Hmax = I.Hmax;
+    a.hstride = I.hstride; a.hmstride = I.hmstride;
+    a.qc = I.qc;
     a.n_win_wg = (I.hwin_words + kK3Words - 1) / kK3Words;
+    a.nwg = I.nwg; a.nb = I.nb;
+    a.partial = I.partial;
+    a.record = I.record;
+    a.dyn = cx->dyn + I.pos;
     return a;
 }
 
-// bins and moments of the current state (time index step - rec_base)
-sgpm_status run_state_pass(sgpm_ctx* c, Instance& I, double dt, bool moving) {
-    int e;
-    if (I.fp32) e = launch_k1_f32(make_k1<float>(I, dt, moving, I.step), I.nwg, c->stream);
-    else e = launch_k1_f64(make_k1<double>(I, dt, moving, I.step), I.nwg, c->stream);
-    if (!e)
-        e = launch_k3(make_k3(I, I.step), I.nwg, I.nb, I.partial,
-                      I.record + (size_t)(I.step - I.rec_base) * I.nb * I.Q * 3, c->stream);
-    if (e != 0) return dev_fail(c, (hipError_t)e, "state pass launch");
+int k3_grid(const Instance& I) {
+    return k3_grid_of(I.Q, I.nk, (I.hwin_words + kK3Words - 1) / kK3Words, I.nb);
+}
+
+// workgroup tables: group tables of K1, K3, K2 and single-instance tables of K1, K3
+enum { kTabK1 = 0, kTabK3 = 1, kTabK2 = 2, kTabK1One = 3, kTabK3One = 4 };
+uint32_t* wg_table(sgpm_ctx* c, int tab, int off) {
+    return c->wg + (size_t)tab * 2 * c->inst.size() + off;
+}
+
+void drop_graphs(sgpm_ctx* c) {
+    for (auto& g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    c->graphs.clear();
+}
+
+// Descriptors, workgroup tables and grids of every group, uploaded and waited
+// for.  Any captured graph is dropped: grids may have changed.
+sgpm_status upload_args(sgpm_ctx* c) {
+    const int n = (int)c->inst.size();
+    std::vector<uint32_t>& W = c->h_wg;
+    W.assign((size_t)10 * n, 0u);
+    auto tab = [&](int t, int off) { return &W[(size_t)t * 2 * n + off]; };
+    for (size_t g = 0; g < c->groups.size(); ++g) {
+        Group& G = c->groups[g];
+        const int off = G.pos0 + (int)g;
+        uint32_t *t1 = tab(kTabK1, off), *t3 = tab(kTabK3, off), *t2 = tab(kTabK2, off);
+        t1[0] = t3[0] = t2[0] = 0u;
+        double ntot = 0.0;
+        for (int k : G.members) ntot += (double)c->inst[k].n;
+        double cum = 0.0;
+        G.k1_lds = 0; G.k2_lds = 0;
+        for (size_t m = 0; m < G.members.size(); ++m) {
+            Instance& I = c->inst[G.members[m]];
+            t1[m + 1] = t1[m] + (uint32_t)I.nwg;
+            t3[m + 1] = t3[m] + (uint32_t)k3_grid(I);
+            cum += (double)I.n;
+            t2[m + 1] = (uint32_t)std::llround(kK2Grid * cum / ntot);
+            if (m + 1 == G.members.size()) t2[m + 1] = kK2Grid;
+            G.k1_lds = std::max(G.k1_lds, k1_lds_bytes(I.P, I.Q, I.fp32, I.hwin_words, (int)I.chunk));
+            G.k2_lds = std::max(G.k2_lds, k2_lds_bytes(I.P, I.Q, I.fp32));
+            uint32_t* s1 = tab(kTabK1One, 2 * I.pos);
+            uint32_t* s3 = tab(kTabK3One, 2 * I.pos);
+            s1[0] = 0u; s1[1] = (uint32_t)I.nwg;
+            s3[0] = 0u; s3[1] = (uint32_t)k3_grid(I);
+            if (I.fp32) {
+                c->h_k1f[I.pos] = make_k1<float>(c, I);
+                c->h_k2f[I.pos] = make_k2<float>(c, I);
+            } else {
+                c->h_k1d[I.pos] = make_k1<double>(c, I);
+                c->h_k2d[I.pos] = make_k2<double>(c, I);
+            }
+            c->h_k3[I.pos] = make_k3(c, I);
+        }
+        G.k1_grid = t1[G.members.size()];
+        G.k3_grid = t3[G.members.size()];
+    }
+    drop_graphs(c);
+    const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+    HIPCHK(c, hipMemcpyAsync(c->k1d, c->h_k1d.data(), n * sizeof(K1Args<double>), h2d, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->k1f, c->h_k1f.data(), n * sizeof(K1Args<float>), h2d, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->k2d, c->h_k2d.data(), n * sizeof(K2Args<double>), h2d, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->k2f, c->h_k2f.data(), n * sizeof(K2Args<float>), h2d, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->k3, c->h_k3.data(), n * sizeof(K3Args), h2d, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->wg, W.data(), W.size() * 4, h2d, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return SGPM_OK;
 }
 
-// One time step of instance I: the state pass of t^n with the drift and the
-// candidate list, then the collisions of the candidates against H^n.
-sgpm_status launch_step(sgpm_ctx* c, Instance& I, double dt) {
-    sgpm_status s = run_state_pass(c, I, dt, true);
-    if (s) return s;
-    int e;
-    if (I.fp32) e = launch_k2_f32(make_k2<float>(I, dt, I.step), k2_grid(), c->stream);
-    else e = launch_k2_f64(make_k2<double>(I, dt, I.step), k2_grid(), c->stream);
-    if (e != 0) return dev_fail(c, (hipError_t)e, "collider launch");
-    I.step += 1;
+const void* k1_args(sgpm_ctx* c, bool fp32, int pos) {
+    return fp32 ? (const void*)(c->k1f + pos) : (const void*)(c->k1d + pos);
+}
+const void* k2_args(sgpm_ctx* c, bool fp32, int pos) {
+    return fp32 ? (const void*)(c->k2f + pos) : (const void*)(c->k2d + pos);
+}
+
+// event after a kernel of a profiled call
+sgpm_status prof_mark(sgpm_ctx* c, hipStream_t s, int kind) {
+    Prof& P = c->prof;
+    if (P.used >= P.ev.size()) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        P.ev.push_back(e);
+    }
+    HIPCHK(c, hipEventRecord(P.ev[P.used], s));
+    if (kind >= 0) P.kind.push_back(kind);
+    P.used += 1;
+    return SGPM_OK;
+}
+
+// One time step of every group: the state pass of t^n with the drift and the
+// candidate lists, the finalize of H^n and of the moments of t^n, then the
+// collisions of the candidates against H^n.
+sgpm_status enqueue_step(sgpm_ctx* c, hipStream_t s, bool prof) {
+    for (size_t g = 0; g < c->groups.size(); ++g) {
+        const Group& G = c->groups[g];
+        const int m = (int)G.members.size(), off = G.pos0 + (int)g;
+        int e = launch_k1(G.fp32, G.pmax, G.qmax, k1_args(c, G.fp32, G.pos0),
+                          wg_table(c, kTabK1, off), m, 1, G.k1_grid, G.k1_lds, s);
+        if (e) return dev_fail(c, (hipError_t)e, "stream kernel launch");
+        if (prof) { sgpm_status r = prof_mark(c, s, SGPM_KERNEL_STREAM); if (r) return r; }
+        e = launch_k3(c->k3 + G.pos0, wg_table(c, kTabK3, off), m, G.k3_grid, s);
+        if (e) return dev_fail(c, (hipError_t)e, "finalize kernel launch");
+        if (prof) { sgpm_status r = prof_mark(c, s, SGPM_KERNEL_FINALIZE); if (r) return r; }
+        e = launch_k2(G.fp32, G.pmax, k2_args(c, G.fp32, G.pos0), wg_table(c, kTabK2, off), m,
+                      c->done + 16 * g, kK2Grid, G.k2_lds, s);
+        if (e) return dev_fail(c, (hipError_t)e, "collider launch");
+        if (prof) { sgpm_status r = prof_mark(c, s, SGPM_KERNEL_COLLIDE); if (r) return r; }
+    }
+    return SGPM_OK;
+}
+
+// bins and moments of the current state of every group (no drift, no collisions)
+sgpm_status enqueue_state_pass(sgpm_ctx* c, hipStream_t s) {
+    for (size_t g = 0; g < c->groups.size(); ++g) {
+        const Group& G = c->groups[g];
+        const int m = (int)G.members.size(), off = G.pos0 + (int)g;
+        int e = launch_k1(G.fp32, G.pmax, G.qmax, k1_args(c, G.fp32, G.pos0),
+                          wg_table(c, kTabK1, off), m, 0, G.k1_grid, G.k1_lds, s);
+        if (!e) e = launch_k3(c->k3 + G.pos0, wg_table(c, kTabK3, off), m, G.k3_grid, s);
+        if (e) return dev_fail(c, (hipError_t)e, "state pass launch");
+    }
+    return SGPM_OK;
+}
+
+// the same for one instance
+sgpm_status state_pass_one(sgpm_ctx* c, const Instance& I) {
+    const Group& G = c->groups[I.grp];
+    int e = launch_k1(I.fp32, G.pmax, G.qmax, k1_args(c, I.fp32, I.pos),
+                      wg_table(c, kTabK1One, 2 * I.pos), 1, 0, (unsigned)I.nwg,
+                      k1_lds_bytes(I.P, I.Q, I.fp32, I.hwin_words, (int)I.chunk), c->stream);
+    if (!e)
+        e = launch_k3(c->k3 + I.pos, wg_table(c, kTabK3One, 2 * I.pos), 1, (unsigned)k3_grid(I),
+                      c->stream);
+    if (e) return dev_fail(c, (hipError_t)e, "state pass launch");
+    return SGPM_OK;
+}
+
+// a graph of `steps` steps, captured on the private stream
+sgpm_status graph_for(sgpm_ctx* c, int steps, hipGraphExec_t* out) {
+    for (auto& g : c->graphs)
+        if (g.first == steps) { *out = g.second; return SGPM_OK; }
+    HIPCHK(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+    sgpm_status s = SGPM_OK;
+    for (int k = 0; k < steps && !s; ++k) s = enqueue_step(c, c->cap, false);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap, &graph);
+    if (s) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    if (e != hipSuccess) return dev_fail(c, e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) return dev_fail(c, e2, "hipGraphInstantiate");
+    c->graphs.emplace_back(steps, exec);
+    *out = exec;
     return SGPM_OK;
 }
 
@@ -350,14 +548,16 @@ void set_chunk(Instance& I, int64_t chunk) {
 
 // histogram, its maximum and record index 0 for the current state
 sgpm_status rebuild(sgpm_ctx* c, Instance& I) {
-    const size_t hm = (size_t)64 * ((I.Q + 63) / 64) * 4;
     HIPCHK(c, hipMemsetAsync(I.H, 0, (size_t)3 * I.hstride * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(I.extra, 0, (size_t)I.hstride * 4, c->stream));
-    HIPCHK(c, hipMemsetAsync(I.Hmax, 0, 3 * hm, c->stream));
+    HIPCHK(c, hipMemsetAsync(I.Hmax, 0, (size_t)3 * I.hmstride * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(I.qc, 0, 64, c->stream));
     HIPCHK(c, hipMemsetAsync(I.counters, 0, SGPM_N_COUNTERS * 8, c->stream));
     I.rec_base = I.step;
-    return run_state_pass(c, I, 0.0, false);
+    int e = launch_set_dyn(c->dyn + I.pos, 1, 1, (uint32_t)I.step, (uint32_t)I.rec_base, 0, 0.0,
+                           c->stream);
+    if (e) return dev_fail(c, (hipError_t)e, "step state launch");
+    return state_pass_one(c, I);
 }
 
 }  // namespace
@@ -391,8 +591,8 @@ const char* sgpm_status_string(sgpm_status s) {
 }
 
 sgpm_status sgpm_workspace_bytes(const sgpm_instance_desc* descs, int32_t n_inst, size_t* bytes) {
-    if (!descs || n_inst < 1 || !bytes) return SGPM_EINVAL;
-    size_t total = 0;
+    if (!descs || n_inst < 1 || !bytes || n_inst > SGPM_MAX_INSTANCES) return SGPM_EINVAL;
+    size_t total = ctx_layout(n_inst).total;
     for (int k = 0; k < n_inst; ++k) {
         HostTables t;
         const char* why = build_tables(descs[k], t);
@@ -407,17 +607,21 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
                         void* stream, sgpm_ctx** out) {
     if (!out) return SGPM_EINVAL;
     *out = nullptr;
-    if (!descs || n_inst < 1) return SGPM_EINVAL;
+    if (!descs || n_inst < 1 || n_inst > SGPM_MAX_INSTANCES) return SGPM_EINVAL;
     sgpm_ctx* c = new (std::nothrow) sgpm_ctx();
     if (!c) return SGPM_ENOMEM;
     c->stream = (hipStream_t)stream;
     try {
         c->inst.resize(n_inst);
+        c->h_k1d.resize(n_inst); c->h_k1f.resize(n_inst);
+        c->h_k2d.resize(n_inst); c->h_k2f.resize(n_inst);
+        c->h_k3.resize(n_inst);
     } catch (...) {
         delete c;
         return SGPM_ENOMEM;
     }
-    size_t need = 0;
+    const CtxLayout CL = ctx_layout(n_inst);
+    size_t need = CL.total;
     for (int k = 0; k < n_inst; ++k) {
         Instance& I = c->inst[k];
         I.d = descs[k];
@@ -435,7 +639,39 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         delete c;
         return SGPM_EWORKSPACE;
     }
+    // shape groups, slots in group order
+    for (int k = 0; k < n_inst; ++k) {
+        Instance& I = c->inst[k];
+        const bool f32 = I.d.precision == SGPM_FP32;
+        const int pm = pmax_bucket(I.t.P), qm = qmax_bucket(I.t.Q);
+        size_t g = 0;
+        while (g < c->groups.size() &&
+               !(c->groups[g].fp32 == f32 && c->groups[g].pmax == pm && c->groups[g].qmax == qm))
+            ++g;
+        if (g == c->groups.size()) {
+            Group G;
+            G.fp32 = f32; G.pmax = pm; G.qmax = qm;
+            c->groups.push_back(G);
+        }
+        c->groups[g].members.push_back(k);
+        I.grp = (int)g;
+    }
+    {
+        int pos = 0;
+        for (Group& G : c->groups) {
+            G.pos0 = pos;
+            for (int k : G.members) c->inst[k].pos = pos++;
+        }
+    }
     unsigned char* base = static_cast<unsigned char*>(ws);
+    c->dyn = (Dyn*)(base + CL.dyn);
+    c->k1d = (K1Args<double>*)(base + CL.k1d); c->k1f = (K1Args<float>*)(base + CL.k1f);
+    c->k2d = (K2Args<double>*)(base + CL.k2d); c->k2f = (K2Args<float>*)(base + CL.k2f);
+    c->k3 = (K3Args*)(base + CL.k3);
+    c->wg = (uint32_t*)(base + CL.wg);
+    c->done = (uint32_t*)(base + CL.done);
+    base += CL.total;
+    std::vector<Dyn> dyn0(n_inst);
     for (int k = 0; k < n_inst; ++k) {
         Instance& I = c->inst[k];
         const HostTables& t = I.t;
@@ -444,6 +680,7 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         I.P = t.P; I.Q = t.Q; I.nk = I.d.nk; I.n = I.d.n_particles;
         I.fp32 = I.d.precision == SGPM_FP32;
         I.hstride = ((int64_t)I.Q * I.nk * I.nk + 63) / 64 * 64;
+        I.hmstride = 64 * ((I.Q + 63) / 64);
         I.kx = at(0); I.ky = at(1);
         I.H = (uint32_t*)at(2); I.Hmax = (uint32_t*)at(3);
         I.partial = (double*)at(4); I.record = (double*)at(5);
@@ -467,6 +704,8 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         set_chunk(I, 0);
         window_for(I.P, I.Q, I.nk, I.fp32, (int)I.chunk, &I.win, &I.win_r0, &I.win_l0,
                    &I.hwin_words);
+        std::memset(&dyn0[I.pos], 0, sizeof(Dyn));
+        dyn0[I.pos].v_f = t.v_f;
 
         // upload the tables (FP64 masters and FP32 copies)
         const int Q = I.Q, P = I.P;
@@ -518,6 +757,7 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         if (e == hipSuccess) e = up(I.f_consts, &cf, sizeof(cf));
         if (e == hipSuccess) e = up(I.d_ehat, t.ehat.data(), P * 8);
         if (e == hipSuccess) e = hipMemsetAsync(I.counters, 0, SGPM_N_COUNTERS * 8, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(I.qc, 0, 64, c->stream);
         // host vectors above are released at scope end: wait for the copies
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) {
@@ -526,8 +766,16 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
             return SGPM_EDEVICE;
         }
     }
-    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
-        delete c;
+    hipError_t e = hipMemcpyAsync(c->dyn, dyn0.data(), n_inst * sizeof(Dyn), hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(c->done, 0, (size_t)n_inst * 64, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipEventCreate(&c->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&c->ev1);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (e != hipSuccess || upload_args(c) != SGPM_OK) {
+        fprintf(stderr, "sgpm_create: %s\n", e != hipSuccess ? hipGetErrorString(e) : c->err.c_str());
+        sgpm_destroy(c);
         return SGPM_EDEVICE;
     }
     *out = c;
@@ -536,6 +784,9 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
 
 void sgpm_destroy(sgpm_ctx* c) {
     if (!c) return;
+    drop_graphs(c);
+    for (hipEvent_t e : c->prof.ev) (void)hipEventDestroy(e);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;
@@ -573,7 +824,45 @@ sgpm_status sgpm_set_chunk(sgpm_ctx* c, int32_t inst, int32_t chunk) {
     if (I.initialised && I.step != I.rec_base)
         return fail(c, SGPM_ESTATE, "the launch shape can only change right after init/set_state");
     set_chunk(I, chunk);
+    s = upload_args(c);
+    if (s) return s;
     if (I.initialised) return rebuild(c, I);
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_set_graph(sgpm_ctx* c, int32_t steps_per_graph) {
+    if (!c) return SGPM_EINVAL;
+    if (steps_per_graph < 0 || steps_per_graph > kMaxGraphSteps)
+        return fail(c, SGPM_EINVAL, "steps per graph must be in [0, 256]");
+    if (steps_per_graph != c->graph_steps) drop_graphs(c);
+    c->graph_steps = steps_per_graph;
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_set_profiling(sgpm_ctx* c, int32_t on) {
+    if (!c) return SGPM_EINVAL;
+    c->profiling = on != 0;
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_kernel_times(sgpm_ctx* c, double* avg_ms, int64_t* launches) {
+    if (!c || !avg_ms) return SGPM_EINVAL;
+    double tot[SGPM_N_KERNELS] = {0.0, 0.0, 0.0};
+    int64_t cnt[SGPM_N_KERNELS] = {0, 0, 0};
+    const Prof& P = c->prof;
+    if (P.used > 1) {
+        HIPCHK(c, hipEventSynchronize(P.ev[P.used - 1]));
+        for (size_t k = 0; k + 1 < P.used && k < P.kind.size(); ++k) {
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, P.ev[k], P.ev[k + 1]));
+            tot[P.kind[k]] += ms;
+            cnt[P.kind[k]] += 1;
+        }
+    }
+    for (int k = 0; k < SGPM_N_KERNELS; ++k) {
+        avg_ms[k] = cnt[k] ? tot[k] / (double)cnt[k] : 0.0;
+        if (launches) launches[k] = cnt[k];
+    }
     return SGPM_OK;
 }
 
@@ -615,18 +904,40 @@ sgpm_status sgpm_step(sgpm_ctx* c, double dt, int64_t n_steps) {
             return fail(c, SGPM_EINVAL, "step counter would reach the initialisation stream");
     }
     if (n_steps == 0) return SGPM_OK;
+    const int n_inst = (int)c->inst.size();
+    int e = launch_set_dyn(c->dyn, n_inst, 0, 0u, 0u, 1, dt, c->stream);
+    if (e) return dev_fail(c, (hipError_t)e, "step state launch");
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    for (int64_t k = 0; k < n_steps; ++k) {
-        for (Instance& I : c->inst) {
-            sgpm_status s = launch_step(c, I, dt);
+    if (c->profiling) {
+        c->prof.used = 0;
+        c->prof.kind.clear();
+        sgpm_status s = prof_mark(c, c->stream, -1);
+        for (int64_t k = 0; k < n_steps && !s; ++k) s = enqueue_step(c, c->stream, true);
+        if (s) return s;
+    } else if (c->graph_steps > 0) {
+        const int B = c->graph_steps;
+        hipGraphExec_t gB = nullptr, gR = nullptr;
+        if (n_steps >= B) {
+            sgpm_status s = graph_for(c, B, &gB);
+            if (s) return s;
+        }
+        const int rem = (int)(n_steps % B);
+        if (rem) {
+            sgpm_status s = graph_for(c, rem, &gR);
+            if (s) return s;
+        }
+        for (int64_t k = 0; k < n_steps / B; ++k) HIPCHK(c, hipGraphLaunch(gB, c->stream));
+        if (rem) HIPCHK(c, hipGraphLaunch(gR, c->stream));
+    } else {
+        for (int64_t k = 0; k < n_steps; ++k) {
+            sgpm_status s = enqueue_step(c, c->stream, false);
             if (s) return s;
         }
     }
+    for (Instance& I : c->inst) I.step += n_steps;
     // bins and moments of the final state
-    for (Instance& I : c->inst) {
-        sgpm_status s = run_state_pass(c, I, dt, false);
-        if (s) return s;
-    }
+    sgpm_status s = enqueue_state_pass(c, c->stream);
+    if (s) return s;
     HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     c->timed = true;
     c->timed_steps = n_steps;

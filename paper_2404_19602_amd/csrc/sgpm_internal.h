@@ -83,13 +83,29 @@ struct DevTab {
 
 constexpr int kWaves1 = 4;            // waves per workgroup of the stream kernel
 constexpr int kBlock1 = 64 * kWaves1;
-constexpr int kMaxStreamWG = 4096;    // cap on stream workgroups (sizes the slabs)
+constexpr int kMaxStreamWG = 4096;    // cap on stream workgroups of one instance (sizes the slabs)
 constexpr int kMaxChunk = 8192;       // cap on particles per stream workgroup (LDS list)
+constexpr int kK2Grid = 1024;         // persistent collider workgroups of one launch
+
+// Per-instance values that change from step to step, resident in device
+// memory.  The kernels of a step read them instead of taking them as launch
+// arguments, so the launches of every step are identical and a captured graph
+// can replay them; the collider's last workgroup advances the step.
+struct Dyn {
+    uint32_t step;       // global step counter n: random streams, buffer parity
+    uint32_t rec_base;   // value of step at record index 0
+    uint32_t pad0, pad1;
+    double dt;           // time step, s
+    double vfdt;         // v_F dt, m: the drift of mode h is vfdt * ehat[h]
+    double v_f;          // m/s
+    double pad2;
+};
 
 // Stream kernel: every particle of a chunk, lane per particle.  From the
 // state at t^n it bins H^n and sums the moments at t^n; then it applies the
 // Galerkin drift and decides with a rigorous rate bound whether the particle
-// may collide in this step; candidates go to a global work list.
+// may collide in this step; candidates go to a global work list.  One launch
+// covers the instances of a group; the descriptors live in device memory.
 template <typename T>
 struct K1Args {
     T* kx;
@@ -98,38 +114,36 @@ struct K1Args {
     int P, Q;
     DevTab<T> tab;
     const double* ehat;     // [P] Galerkin field coefficients (V/m)
-    double vfdt;            // v_F dt: drift of mode h is vfdt * ehat[h]
-    T dt;
-    uint32_t seed_lo, seed_hi, instance, step;
+    const Dyn* dyn;
+    uint32_t seed_lo, seed_hi, instance, pad;
     uint32_t* extra;        // overflow grid of H^n (outside the LDS window)
     uint32_t* slabs;        // [nwg][hwin_words] window slabs of H^n
     int win, win_r0, win_l0, hwin_words;
     double* partial;        // [nwg][Q][3] moment sums at t^n
     int* cand;              // global list of collision candidates
-    uint32_t* cand_count;   // its length (zero on entry)
+    uint32_t* qc;           // [2][2] candidate count and work head, by step parity
     unsigned long long* counters;
     int64_t chunk;
-    int do_collide;         // 0: bins and moments only (no drift, no candidates)
 };
 
 // Collider kernel: a group of G lanes per candidate, one node per lane;
-// candidates pulled from the global list by a work counter.
+// candidates pulled from each instance's list by its work counter.
 template <typename T>
 struct K2Args {
     T* kx;
     T* ky;
     int64_t n;
-    int P, Q, G;            // G: lanes per candidate (power of two)
+    int P, Q, G, pad;       // G: lanes per candidate (power of two)
     DevTab<T> tab;
     const double* ehat;
-    double vfdt;
-    T dt;
-    uint32_t seed_lo, seed_hi, instance, step;
-    const uint32_t* h_read;     // H^n
-    const uint32_t* hmax_read;  // its per-node maximum
+    Dyn* dyn;               // step advanced here once every workgroup is done
+    uint32_t seed_lo, seed_hi, instance, pad2;
+    const uint32_t* H;      // [3][hstride] histograms, H^n at n mod 3
+    const uint32_t* Hmax;   // [3][hmstride] their per-node maxima
+    int64_t hstride;
+    int64_t hmstride;
     const int* cand;
-    const uint32_t* cand_count;
-    uint32_t* head;             // work counter (zero on entry)
+    uint32_t* qc;
     unsigned long long* counters;
 };
 
@@ -144,11 +158,16 @@ struct K3Args {
     const uint32_t* slabs;  // [nwg][hwin_words]
     int hwin_words, win, win_r0, win_l0;
     uint32_t* extra;        // [Q][nk][nk] overflow counts (zeroed here)
-    uint32_t* h_out;        // H^n
-    uint32_t* hmax_out;     // its per-node maximum (zero on entry)
-    uint32_t* hmax_clr;     // stale maximum slot zeroed for the next step
-    uint32_t* reset;        // [2] counters of the next step zeroed
+    uint32_t* H;            // [3][hstride]
+    uint32_t* Hmax;         // [3][hmstride]
+    int64_t hstride, hmstride;
+    uint32_t* qc;           // [2][2] counters by step parity
     int n_win_wg;           // workgroups of the window part
+    int nwg, nb;            // stream workgroups and moment batches
+    int pad;
+    const double* partial;  // [nwg][Q][3]
+    double* record;         // [max_steps + 1][nb][Q][3]
+    const Dyn* dyn;
 };
 
 struct InitArgs {
@@ -178,20 +197,24 @@ struct EnergyHistArgs {
     unsigned long long* bins;  // [Q][nbins]
 };
 
-// Kernel launchers (sgpm_kernels.hip).  Return hipError_t as int.
-int launch_k1_f64(const K1Args<double>& a, int nwg, void* stream);
-int launch_k1_f32(const K1Args<float>& a, int nwg, void* stream);
-int launch_k2_f64(const K2Args<double>& a, int nwg, void* stream);
-int launch_k2_f32(const K2Args<float>& a, int nwg, void* stream);
-int k2_grid();
-int launch_k3(const K3Args& a, int nwg, int nb, const double* partial, double* record,
-              void* stream);
+// Kernel launchers (sgpm_kernels.hip).  Return hipError_t as int.  The
+// batched launchers take device arrays of descriptors of n_inst instances of
+// one shape group and wg0[n_inst + 1], the first workgroup of each instance.
+int launch_k1(int fp32, int pmax, int qmax, const void* args, const uint32_t* wg0, int n_inst,
+              int moving, unsigned grid, size_t lds, void* stream);
+int launch_k2(int fp32, int pmax, const void* args, const uint32_t* wg0, int n_inst,
+              uint32_t* done, unsigned grid, size_t lds, void* stream);
+int launch_k3(const K3Args* args, const uint32_t* wg0, int n_inst, unsigned grid, void* stream);
+int launch_set_dyn(Dyn* d, int n, int set_step, uint32_t step, uint32_t rec_base, int set_dt,
+                   double dt, void* stream);
 int pmax_bucket(int P);
+int qmax_bucket(int Q);
 int launch_init(const InitArgs& a, void* stream);
 int launch_energy_hist(const EnergyHistArgs& a, void* stream);
 int launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n,
                   void* stream);
 size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words, int chunk);
 size_t k2_lds_bytes(int P, int Q, int fp32);
+int k3_grid_of(int Q, int nk, int n_win_wg, int nb);
 
 }  // namespace sgpm

@@ -193,6 +193,26 @@ __device__ __forceinline__ void load_coeffs(const T* __restrict__ kxa, const T* 
     }
 }
 
+// Descriptor j of a batched launch, read through the constant address space:
+// the array is not written while a kernel runs, and pointers loaded from
+// constant memory are known to be global, so their accesses compile to global
+// (not flat) instructions.
+template <typename D>
+__device__ __forceinline__ D load_desc(const D* all, int j) {
+    typedef const __attribute__((address_space(4))) D CD;
+    return __builtin_bit_cast(D, ((CD*)all)[j]);
+}
+
+// Instance of a workgroup of a batched launch: the last j with wg0[j] <= b.
+__device__ __forceinline__ int find_slot(const uint32_t* __restrict__ wg0, int n_inst, uint32_t b) {
+    int lo = 0, hi = n_inst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b >= wg0[mid]) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ======================================================= K1: stream kernel
 size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words, int chunk) {
     const size_t s = fp32 ? 4 : 8;
@@ -266,17 +286,26 @@ __device__ __forceinline__ void k1_bin(const K1Args<T>& a, const K1Lds<T>& L, co
 // G~ <= gb and -log(xi) >= 1 - xi the test needs the logarithm only when
 // xi > 1 - gb dt.
 template <typename T>
-__device__ __forceinline__ bool k1_candidate(const K1Args<T>& a, const Consts<T>& c, int64_t i, T ub) {
-    const T t = rate_bound<T>(c, ub) * a.dt;
-    const Words wx = philox10((uint32_t)i, a.step, kPurXi, a.instance, a.seed_lo, a.seed_hi);
+__device__ __forceinline__ bool k1_candidate(const K1Args<T>& a, const Consts<T>& c, int64_t i, T ub,
+                                             uint32_t step, T dt) {
+    const T t = rate_bound<T>(c, ub) * dt;
+    const Words wx = philox10((uint32_t)i, step, kPurXi, a.instance, a.seed_lo, a.seed_hi);
     const T xi = uni<T>(wx.w0, wx.w1);
     if (xi <= (T)1 - t * c.b_margin) return false;
     return !(-dlog(xi) >= t);
 }
 
 template <typename T, int PMAX, int QMAX>
-__global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T> a) {
+__global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict__ all,
+                                                     const uint32_t* __restrict__ wg0, int n_inst,
+                                                     int moving) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int slot = find_slot(wg0, n_inst, blockIdx.x);
+    const K1Args<T> a = load_desc(all, slot);
+    const uint32_t wg = blockIdx.x - wg0[slot];
+    const uint32_t step = a.dyn->step;
+    const double vfdt = a.dyn->vfdt;
+    const T dt = (T)a.dyn->dt;
     const int P = a.P, Q = a.Q;
     const K1Lds<T> L = k1_lds<T>(smem, PMAX, Q, a.hwin_words, (int)a.chunk);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -289,7 +318,7 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T> a) {
     }
     for (int k = tid; k < PMAX; k += kBlock1) {
         L.psimax[k] = k < P ? a.tab.psimax[k] : (T)0;
-        L.drift[k] = (a.do_collide && k < P) ? (T)(a.vfdt * a.ehat[k]) : (T)0;
+        L.drift[k] = (moving && k < P) ? (T)(vfdt * a.ehat[k]) : (T)0;
     }
     for (int k = tid; k < kWaves1 * Q * 3; k += kBlock1) L.red[k] = 0.0;
     if (tid < 16) L.cnt[tid] = 0u;
@@ -304,7 +333,7 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T> a) {
     __syncthreads();
     const Consts<T>& c = *L.c;
 
-    const int64_t begin = (int64_t)blockIdx.x * a.chunk;
+    const int64_t begin = (int64_t)wg * a.chunk;
     const int64_t end = begin + a.chunk < a.n ? begin + a.chunk : a.n;
 
     double acc[QMAX > 0 ? QMAX : 1][3];
@@ -342,7 +371,7 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T> a) {
             }
             // the nodal energies after the drift, bounded with a relative
             // margin for the rounding of the shifted evaluation
-            if (act && a.do_collide) cand = k1_candidate<T>(a, c, i, sqrt(e2max) * c.b_margin);
+            if (act && moving) cand = k1_candidate<T>(a, c, i, sqrt(e2max) * c.b_margin, step, dt);
         } else {
             for (int q = 0; q < Q; ++q) {
                 double vx = 0.0, vy = 0.0, en = 0.0;
@@ -362,7 +391,7 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T> a) {
                     m[0] += vx; m[1] += vy; m[2] += en;
                 }
             }
-            if (act && a.do_collide) {
+            if (act && moving) {
                 // |k(z_q)| <= sum_h |k_h| max_q |Psi_h(z_q)| per component, after the drift
                 T bx = (T)0, by = (T)0;
 #pragma unroll
@@ -370,10 +399,10 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T> a) {
                     bx += fabs(cx[h] - L.drift[h]) * L.psimax[h];
                     by += fabs(cy[h]) * L.psimax[h];
                 }
-                cand = k1_candidate<T>(a, c, i, sqrt(bx * bx + by * by + c.eps0max_sq));
+                cand = k1_candidate<T>(a, c, i, sqrt(bx * bx + by * by + c.eps0max_sq), step, dt);
             }
         }
-        if (act && a.do_collide && !cand) {
+        if (act && moving && !cand) {
             // the particle does not collide: its step is the drift alone
 #pragma unroll
             for (int h = 0; h < PMAX; ++h)
@@ -412,7 +441,7 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T> a) {
         __shared__ uint32_t gbase;
         const uint32_t nc = L.cnt[SGPM_CNT_CANDIDATES];
         if (nc) {
-            if (tid == 0) gbase = atomicAdd(a.cand_count, nc);
+            if (tid == 0) gbase = atomicAdd(a.qc + 2 * (step & 1), nc);
             __syncthreads();
             for (uint32_t k = tid; k < nc; k += kBlock1) a.cand[gbase + k] = L.cbuf[k];
         }
@@ -420,7 +449,7 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T> a) {
 
     // the LDS window as this workgroup's dense slab (plain 16-byte stores)
     {
-        uint32_t* slab = a.slabs + (size_t)blockIdx.x * a.hwin_words;
+        uint32_t* slab = a.slabs + (size_t)wg * a.hwin_words;
         const int nv = a.hwin_words >> 2;
         for (int w = tid; w < nv; w += kBlock1)
             reinterpret_cast<uint4*>(slab)[w] = reinterpret_cast<const uint4*>(L.hwin)[w];
@@ -429,7 +458,7 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T> a) {
     for (int k = tid; k < Q * 3; k += kBlock1) {
         double v = 0.0;
         for (int wv = 0; wv < kWaves1; ++wv) v += L.red[wv * Q * 3 + k];
-        a.partial[(size_t)blockIdx.x * Q * 3 + k] = v;
+        a.partial[(size_t)wg * Q * 3 + k] = v;
     }
     if (tid < 8 && L.cnt[tid]) atomicAdd(&a.counters[tid], (unsigned long long)L.cnt[tid]);
 }
@@ -479,26 +508,32 @@ __device__ __forceinline__ K2Lds<T> k2_lds(unsigned char* smem, int PM, int Q) {
 // Pauli occupation f = H^n / max H^n of node q at the candidate's cell on the
 // grid moved with this step's drift (lookup at k' + v_F E(z_q) dt x^)
 template <typename T>
-__device__ __forceinline__ T pauli_f(const K2Args<T>& a, const K2Lds<T>& L, const Consts<T>& c,
-                                     int q, T px, T py) {
-    const uint32_t mx = a.hmax_read[q];
+__device__ __forceinline__ T pauli_f(const uint32_t* __restrict__ h_read,
+                                     const uint32_t* __restrict__ hmax_read, const K2Lds<T>& L,
+                                     const Consts<T>& c, int q, T px, T py, T dt) {
+    const uint32_t mx = hmax_read[q];
     if (mx == 0u) return (T)0;
-    const T shift = L.vfield[q] * a.dt;
+    const T shift = L.vfield[q] * dt;
     const int r = cell_coord<T>(px + shift, c.lk, c.inv_dk);
     const int l = cell_coord<T>(py, c.lk, c.inv_dk);
     if (r < 0 || l < 0 || r >= c.nk || l >= c.nk) return (T)0;
-    const uint32_t h = a.h_read[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l];
+    const uint32_t h = h_read[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l];
     return (T)h / (T)mx;
 }
 
+// The candidates of one instance, pulled by the whole workgroup until its list
+// is exhausted; total: the list's length (nonzero, uniform).
 template <typename T, int PMAX>
-__global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T> a) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+__device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* smem, uint32_t step,
+                                            uint32_t total) {
     const int P = a.P, Q = a.Q, G = a.G;
     const K2Lds<T> L = k2_lds<T>(smem, PMAX, Q);
     const int tid = threadIdx.x;
-    const uint32_t total = *a.cand_count;
-    if (total == 0u) return;
+    const T dt = (T)a.dyn->dt;
+    const double vfdt = a.dyn->vfdt;
+    const uint32_t* h_read = a.H + (size_t)(step % 3u) * a.hstride;
+    const uint32_t* hmax_read = a.Hmax + (size_t)(step % 3u) * a.hmstride;
+    uint32_t* head = a.qc + 2 * (step & 1u) + 1;
 
     if (tid == 0) *L.c = *a.tab.consts;
     for (int k = tid; k < Q * PMAX; k += kBlock) {
@@ -511,7 +546,7 @@ __global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T> a) {
         L.cedge[k] = a.tab.cedge[k]; L.vfield[k] = a.tab.vfield[k];
     }
     for (int k = tid; k <= kEdgePts / 2; k += kBlock) L.ecos[k] = a.tab.edge_cos[k];
-    for (int k = tid; k < PMAX; k += kBlock) L.drift[k] = k < P ? (T)(a.vfdt * a.ehat[k]) : (T)0;
+    for (int k = tid; k < PMAX; k += kBlock) L.drift[k] = k < P ? (T)(vfdt * a.ehat[k]) : (T)0;
     if (tid < 16) L.cnt[tid] = 0u;
     __syncthreads();
     const Consts<T>& c = *L.c;
@@ -521,7 +556,7 @@ __global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T> a) {
     const uint32_t per_pass = kBlock / G;
 
     for (;;) {
-        if (tid == 0) *L.slot = atomicAdd(a.head, per_pass);
+        if (tid == 0) *L.slot = atomicAdd(head, per_pass);
         __syncthreads();
         const uint32_t p0 = *L.slot;
         __syncthreads();
@@ -551,16 +586,16 @@ __global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T> a) {
             }
             smax = group_max<T>(smax, G);
             const T Gt = c.alpha1 * smax;
-            const Words wx = philox10(ctr0, a.step, (coll << 8) | kPurXi, a.instance, a.seed_lo,
+            const Words wx = philox10(ctr0, step, (coll << 8) | kPurXi, a.instance, a.seed_lo,
                                       a.seed_hi);
             const T dtc = -dlog(uni<T>(wx.w0, wx.w1)) / Gt;   // eq. dt, node maximum
-            if (!(tc + dtc < a.dt)) break;
+            if (!(tc + dtc < dt)) break;
             if (g == 0) atomicAdd(&L.cnt[SGPM_CNT_COLLISIONS], 1u);
 
-            const Words ws = philox10(ctr0, a.step, (coll << 8) | kPurSel, a.instance, a.seed_lo,
+            const Words ws = philox10(ctr0, step, (coll << 8) | kPurSel, a.instance, a.seed_lo,
                                       a.seed_hi);
             const T su = uni<T>(ws.w0, ws.w1), eta = uni<T>(ws.w2, ws.w3);
-            const Words wa = philox10(ctr0, a.step, (coll << 8) | kPurAng, a.instance, a.seed_lo,
+            const Words wa = philox10(ctr0, step, (coll << 8) | kPurAng, a.instance, a.seed_lo,
                                       a.seed_hi);
             const T u1 = uni<T>(wa.w0, wa.w1), u2 = uni<T>(wa.w2, wa.w3);
             // AC angle: twice the polar angle of a uniform point of the unit
@@ -608,7 +643,7 @@ __global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T> a) {
                         const T kap = c.edge_kap * (kx * kx + ky * ky);
                         ok = false;
                         for (uint32_t j = 0; j < (uint32_t)kEdgeTries; ++j) {
-                            const Words we = philox10(ctr0, a.step, (coll << 8) | (kPurEdge0 + j),
+                            const Words we = philox10(ctr0, step, (coll << 8) | (kPurEdge0 + j),
                                                       a.instance, a.seed_lo, a.seed_hi);
                             const T ut = uni<T>(we.w0, we.w1), v = uni<T>(we.w2, we.w3);
                             T st, ct;
@@ -641,7 +676,8 @@ __global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T> a) {
                     }
                     if (ok) {
                         ++nev;
-                        const T f = c.pauli ? pauli_f<T>(a, L, c, q, px, py) : (T)0;
+                        const T f = c.pauli ? pauli_f<T>(h_read, hmax_read, L, c, q, px, py, dt)
+                                            : (T)0;
                         if (f < eta) { nx = px; ny = py; } else { ++nrej; }
                     }
                 }
@@ -672,8 +708,46 @@ __global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T> a) {
                 a.ky[(size_t)h * a.n + i] = cy[h];
             }
     }
-    __syncthreads();
+    // every lane is past the last claim: the counters are complete
     if (tid < 8 && L.cnt[tid]) atomicAdd(&a.counters[tid], (unsigned long long)L.cnt[tid]);
+    __syncthreads();
+}
+
+// Persistent collider grid of a group: workgroup b starts with the instance
+// whose share of the grid holds b and then visits the others in turn, so the
+// large lists are shared out first.  The last workgroup to finish advances the
+// step of every instance of the group.
+template <typename T, int PMAX>
+__global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T>* __restrict__ all,
+                                                     const uint32_t* __restrict__ wg0, int n_inst,
+                                                     uint32_t* done) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __shared__ uint32_t s_total;
+    const int tid = threadIdx.x;
+    const int first = find_slot(wg0, n_inst, blockIdx.x);
+    for (int t = 0; t < n_inst; ++t) {
+        const int j = first + t < n_inst ? first + t : first + t - n_inst;
+        const K2Args<T> a = load_desc(all, j);
+        const uint32_t step = a.dyn->step;
+        if (tid == 0) {
+            const uint32_t* qc = a.qc + 2 * (step & 1u);
+            const uint32_t total = __hip_atomic_load(qc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t head = __hip_atomic_load(qc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_total = head < total ? total : 0u;
+        }
+        __syncthreads();
+        const uint32_t total = s_total;
+        __syncthreads();
+        if (total) k2_instance<T, PMAX>(a, smem, step, total);
+    }
+    if (tid == 0) {
+        __threadfence();
+        if (atomicAdd(done, 1u) == gridDim.x - 1) {
+            for (int j = 0; j < n_inst; ++j) all[j].dyn->step += 1u;
+            __threadfence();
+            atomicExch(done, 0u);
+        }
+    }
 }
 
 // ===================================================== K3: finalize kernel
@@ -682,8 +756,17 @@ __global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T> a) {
 // that: kK3Rest cells of the rest of the grid (overflow count only).  Every
 // workgroup zeroes the overflow cells it read and contributes its maximum;
 // workgroup (q + Q b) also reduces moment batch b of node q.
-__global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args a, const double* partial,
-                                                      int nwg, int nb, double* record) {
+__global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__ all,
+                                                      const uint32_t* __restrict__ wg0, int n_inst) {
+    const int slot = find_slot(wg0, n_inst, blockIdx.x);
+    const K3Args a = load_desc(all, slot);
+    const int wg = (int)(blockIdx.x - wg0[slot]);
+    const uint32_t step = a.dyn->step;
+    const int nwg = a.nwg, nb = a.nb;
+    const double* partial = a.partial;
+    double* record = a.record + (size_t)(step - a.dyn->rec_base) * nb * a.Q * 3;
+    uint32_t* h_out = a.H + (size_t)(step % 3u) * a.hstride;
+    uint32_t* hmax_out = a.Hmax + (size_t)(step % 3u) * a.hmstride;
     const int tid = threadIdx.x;
     const int cells = a.nk * a.nk;
     const int wcells = a.win * a.win;
@@ -691,11 +774,11 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args a, const doub
     __shared__ uint32_t smax[kMaxQ];
     for (int k = tid; k < a.Q; k += kBlock) smax[k] = 0u;
     __syncthreads();
-    if ((int)blockIdx.x < a.n_win_wg) {
+    if (wg < a.n_win_wg) {
         // 16 columns of four words, kK3Lanes slab lanes; 16-byte loads
         const int col = tid % (kK3Words / 4);
         const int lane = tid / (kK3Words / 4);
-        const int word0 = blockIdx.x * kK3Words + 4 * col;
+        const int word0 = wg * kK3Words + 4 * col;
         uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
         if (word0 < a.hwin_words) {
             const uint32_t* src = a.slabs + word0;
@@ -713,7 +796,7 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args a, const doub
         __syncthreads();
         if (tid < 2 * kK3Words) {
             const int wl = tid >> 1, half = tid & 1;
-            const int word = blockIdx.x * kK3Words + wl;
+            const int word = wg * kK3Words + wl;
             uint32_t sum = 0u;
 #pragma unroll
             for (int k = 0; k < kK3Lanes; ++k) sum += part[k][wl][half];
@@ -724,12 +807,12 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args a, const doub
                 const size_t g = (size_t)q * cells + (size_t)r * a.nk + l;
                 sum += a.extra[g];
                 a.extra[g] = 0u;
-                a.h_out[g] = sum;
+                h_out[g] = sum;
                 if (sum) atomicMax(&smax[q], sum);
             }
         }
     } else {
-        const int64_t c0 = (int64_t)(blockIdx.x - a.n_win_wg) * kK3Rest;
+        const int64_t c0 = (int64_t)(wg - a.n_win_wg) * kK3Rest;
         const int64_t total = (int64_t)a.Q * cells;
         for (int64_t g = c0 + tid; g < c0 + kK3Rest && g < total; g += kBlock) {
             const int q = (int)(g / cells), rem = (int)(g - (int64_t)q * cells);
@@ -738,20 +821,22 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args a, const doub
             if ((unsigned)wr < (unsigned)a.win && (unsigned)wl < (unsigned)a.win) continue;
             const uint32_t v = a.extra[g];
             a.extra[g] = 0u;
-            a.h_out[g] = v;
+            h_out[g] = v;
             if (v) atomicMax(&smax[q], v);
         }
     }
     __syncthreads();
     for (int k = tid; k < a.Q; k += kBlock)
-        if (smax[k]) atomicMax(&a.hmax_out[k], smax[k]);
-    if (blockIdx.x == 0) {
-        for (int k = tid; k < a.Q; k += kBlock) a.hmax_clr[k] = 0u;
-        if (tid < 2) a.reset[tid] = 0u;
+        if (smax[k]) atomicMax(&hmax_out[k], smax[k]);
+    if (wg == 0) {
+        // stale maximum slot of step n + 1 and the counters of that step
+        uint32_t* hmax_clr = a.Hmax + (size_t)((step + 1u) % 3u) * a.hmstride;
+        for (int k = tid; k < a.Q; k += kBlock) hmax_clr[k] = 0u;
+        if (tid < 2) a.qc[2 * ((step + 1u) & 1u) + tid] = 0u;
     }
     // moment record: batch b of node q collects the stream workgroups w = b (mod NB)
-    if ((int)blockIdx.x < a.Q * nb && tid < 3) {
-        const int q = blockIdx.x % a.Q, b = blockIdx.x / a.Q;
+    if (wg < a.Q * nb && tid < 3) {
+        const int q = wg % a.Q, b = wg / a.Q;
         double sum = 0.0;
         for (int w = b; w < nwg; w += nb) sum += partial[((size_t)w * a.Q + q) * 3 + tid];
         record[((size_t)b * a.Q + q) * 3 + tid] = sum;
@@ -759,66 +844,108 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args a, const doub
 }
 
 // ------------------------------------------------------------ launchers
+int qmax_bucket(int Q) {
+    if (Q <= 1) return 1;
+    if (Q <= 8) return 8;
+    if (Q <= 12) return 12;
+    return 0;
+}
+
 template <typename T, int PMAX, int QMAX>
-static int launch_k1_t(const K1Args<T>& a, int nwg, void* stream) {
-    const size_t lds = k1_lds_bytes(a.P, a.Q, sizeof(T) == 4, a.hwin_words, (int)a.chunk);
-    hipLaunchKernelGGL((k1_stream<T, PMAX, QMAX>), dim3(nwg), dim3(kBlock1), lds,
-                       (hipStream_t)stream, a);
+static int launch_k1_t(const void* args, const uint32_t* wg0, int n_inst, int moving, unsigned grid,
+                       size_t lds, void* stream) {
+    hipLaunchKernelGGL((k1_stream<T, PMAX, QMAX>), dim3(grid), dim3(kBlock1), lds,
+                       (hipStream_t)stream, static_cast<const K1Args<T>*>(args), wg0, n_inst,
+                       moving);
     return (int)hipGetLastError();
 }
 
 template <typename T, int PMAX>
-static int launch_k1_q(const K1Args<T>& a, int nwg, void* stream) {
-    if (a.Q <= 1) return launch_k1_t<T, PMAX, 1>(a, nwg, stream);
-    if (a.Q <= 8) return launch_k1_t<T, PMAX, 8>(a, nwg, stream);
-    if (a.Q <= 12) return launch_k1_t<T, PMAX, 12>(a, nwg, stream);
-    return launch_k1_t<T, PMAX, 0>(a, nwg, stream);
-}
-
-template <typename T>
-static int launch_k1_any(const K1Args<T>& a, int nwg, void* stream) {
-    switch (pmax_bucket(a.P)) {
-    case 1: return launch_k1_q<T, 1>(a, nwg, stream);
-    case 3: return launch_k1_q<T, 3>(a, nwg, stream);
-    case 6: return launch_k1_q<T, 6>(a, nwg, stream);
-    case 9: return launch_k1_q<T, 9>(a, nwg, stream);
-    case 16: return launch_k1_q<T, 16>(a, nwg, stream);
-    default: return launch_k1_q<T, 32>(a, nwg, stream);
+static int launch_k1_q(int qmax, const void* args, const uint32_t* wg0, int n_inst, int moving,
+                       unsigned grid, size_t lds, void* stream) {
+    switch (qmax) {
+    case 1: return launch_k1_t<T, PMAX, 1>(args, wg0, n_inst, moving, grid, lds, stream);
+    case 8: return launch_k1_t<T, PMAX, 8>(args, wg0, n_inst, moving, grid, lds, stream);
+    case 12: return launch_k1_t<T, PMAX, 12>(args, wg0, n_inst, moving, grid, lds, stream);
+    default: return launch_k1_t<T, PMAX, 0>(args, wg0, n_inst, moving, grid, lds, stream);
     }
 }
 
-int launch_k1_f64(const K1Args<double>& a, int nwg, void* s) { return launch_k1_any<double>(a, nwg, s); }
-int launch_k1_f32(const K1Args<float>& a, int nwg, void* s) { return launch_k1_any<float>(a, nwg, s); }
+template <typename T>
+static int launch_k1_any(int pmax, int qmax, const void* args, const uint32_t* wg0, int n_inst,
+                         int moving, unsigned grid, size_t lds, void* stream) {
+    switch (pmax) {
+    case 1: return launch_k1_q<T, 1>(qmax, args, wg0, n_inst, moving, grid, lds, stream);
+    case 3: return launch_k1_q<T, 3>(qmax, args, wg0, n_inst, moving, grid, lds, stream);
+    case 6: return launch_k1_q<T, 6>(qmax, args, wg0, n_inst, moving, grid, lds, stream);
+    case 9: return launch_k1_q<T, 9>(qmax, args, wg0, n_inst, moving, grid, lds, stream);
+    case 16: return launch_k1_q<T, 16>(qmax, args, wg0, n_inst, moving, grid, lds, stream);
+    default: return launch_k1_q<T, 32>(qmax, args, wg0, n_inst, moving, grid, lds, stream);
+    }
+}
 
-// persistent collider grid: enough workgroups to fill the device
-int k2_grid() { return 1024; }
+int launch_k1(int fp32, int pmax, int qmax, const void* args, const uint32_t* wg0, int n_inst,
+              int moving, unsigned grid, size_t lds, void* stream) {
+    if (fp32) return launch_k1_any<float>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream);
+    return launch_k1_any<double>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream);
+}
 
 template <typename T>
-static int launch_k2_any(const K2Args<T>& a, int nwg, void* stream) {
-    const size_t lds = k2_lds_bytes(a.P, a.Q, sizeof(T) == 4);
-    const dim3 grid(nwg), blk(kBlock);
+static int launch_k2_any(int pmax, const void* args, const uint32_t* wg0, int n_inst,
+                         uint32_t* done, unsigned grid, size_t lds, void* stream) {
+    const K2Args<T>* a = static_cast<const K2Args<T>*>(args);
+    const dim3 g(grid), blk(kBlock);
     const hipStream_t s = (hipStream_t)stream;
-    switch (pmax_bucket(a.P)) {
-    case 1: hipLaunchKernelGGL((k2_collide<T, 1>), grid, blk, lds, s, a); break;
-    case 3: hipLaunchKernelGGL((k2_collide<T, 3>), grid, blk, lds, s, a); break;
-    case 6: hipLaunchKernelGGL((k2_collide<T, 6>), grid, blk, lds, s, a); break;
-    case 9: hipLaunchKernelGGL((k2_collide<T, 9>), grid, blk, lds, s, a); break;
-    case 16: hipLaunchKernelGGL((k2_collide<T, 16>), grid, blk, lds, s, a); break;
-    default: hipLaunchKernelGGL((k2_collide<T, 32>), grid, blk, lds, s, a); break;
+    switch (pmax) {
+    case 1: hipLaunchKernelGGL((k2_collide<T, 1>), g, blk, lds, s, a, wg0, n_inst, done); break;
+    case 3: hipLaunchKernelGGL((k2_collide<T, 3>), g, blk, lds, s, a, wg0, n_inst, done); break;
+    case 6: hipLaunchKernelGGL((k2_collide<T, 6>), g, blk, lds, s, a, wg0, n_inst, done); break;
+    case 9: hipLaunchKernelGGL((k2_collide<T, 9>), g, blk, lds, s, a, wg0, n_inst, done); break;
+    case 16: hipLaunchKernelGGL((k2_collide<T, 16>), g, blk, lds, s, a, wg0, n_inst, done); break;
+    default: hipLaunchKernelGGL((k2_collide<T, 32>), g, blk, lds, s, a, wg0, n_inst, done); break;
     }
     return (int)hipGetLastError();
 }
 
-int launch_k2_f64(const K2Args<double>& a, int nwg, void* s) { return launch_k2_any<double>(a, nwg, s); }
-int launch_k2_f32(const K2Args<float>& a, int nwg, void* s) { return launch_k2_any<float>(a, nwg, s); }
+int launch_k2(int fp32, int pmax, const void* args, const uint32_t* wg0, int n_inst,
+              uint32_t* done, unsigned grid, size_t lds, void* stream) {
+    if (fp32) return launch_k2_any<float>(pmax, args, wg0, n_inst, done, grid, lds, stream);
+    return launch_k2_any<double>(pmax, args, wg0, n_inst, done, grid, lds, stream);
+}
 
-int launch_k3(const K3Args& a, int nwg, int nb, const double* partial, double* record,
-              void* stream) {
-    const int64_t rest = ((int64_t)a.Q * a.nk * a.nk + kK3Rest - 1) / kK3Rest;
-    int64_t grid = (int64_t)a.n_win_wg + rest;
-    if (grid < (int64_t)a.Q * nb) grid = (int64_t)a.Q * nb;
-    hipLaunchKernelGGL(k3_finalize, dim3((unsigned)grid), dim3(kBlock), 0, (hipStream_t)stream, a,
-                       partial, nwg, nb, record);
+// finalize workgroups of one instance: the window part, the rest of the
+// grid, and at least one per (node, batch) of the moment record
+int k3_grid_of(int Q, int nk, int n_win_wg, int nb) {
+    const int64_t rest = ((int64_t)Q * nk * nk + kK3Rest - 1) / kK3Rest;
+    int64_t grid = (int64_t)n_win_wg + rest;
+    if (grid < (int64_t)Q * nb) grid = (int64_t)Q * nb;
+    return (int)grid;
+}
+
+int launch_k3(const K3Args* args, const uint32_t* wg0, int n_inst, unsigned grid, void* stream) {
+    hipLaunchKernelGGL(k3_finalize, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, args, wg0,
+                       n_inst);
+    return (int)hipGetLastError();
+}
+
+// Step state of n instances: the step counters (set_step) and the time step
+// (set_dt), written by one small kernel so the writes are ordered on the stream.
+__global__ void set_dyn_kernel(Dyn* d, int n, int set_step, uint32_t step, uint32_t rec_base,
+                               int set_dt, double dt) {
+    const int k = (int)threadIdx.x;
+    if (k >= n) return;
+    if (set_step) { d[k].step = step; d[k].rec_base = rec_base; }
+    if (set_dt) { d[k].dt = dt; d[k].vfdt = d[k].v_f * dt; }
+}
+
+int launch_set_dyn(Dyn* d, int n, int set_step, uint32_t step, uint32_t rec_base, int set_dt,
+                   double dt, void* stream) {
+    if (n <= 0) return 0;
+    for (int k0 = 0; k0 < n; k0 += 1024) {
+        const int m = n - k0 < 1024 ? n - k0 : 1024;
+        hipLaunchKernelGGL(set_dyn_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, d + k0, m,
+                           set_step, step, rec_base, set_dt, dt);
+    }
     return (int)hipGetLastError();
 }
 

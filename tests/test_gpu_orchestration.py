@@ -1,0 +1,156 @@
+"""GPU checks of the launch orchestration: graph replay, batched launches of
+many instances, per-kernel profiling.
+
+None of these may change a single bit of the results: the kernels of a
+graph are the ones launched eagerly, and an instance stepped inside a batch
+runs the same arithmetic on the same random streams as when it is stepped
+alone.  So every comparison here is exact (np.array_equal), FP64 and FP32.
+The batched instances are also checked against the CPU oracle directly.
+"""
+import numpy as np
+import pytest
+
+from workloads import batched_sweep
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sg():
+    import paper_2404_19602_amd as sg
+    return sg
+
+
+def cfg_of(**kw):
+    base = dict(dim_z=1, degree=5, nodes_1d=8, n_particles=20_001, gap_mode=0, gap_dim=0,
+                gap0=0.2, gap_rel=0.1, field_dim=-1, field0=2e6, field_rel=0.0, fermi_eV=0.4,
+                temp_K=300.0, alpha=0.1, nk=240, lk_eV=5.0, pauli=1, final_state=0,
+                rate_scale=(1.0,) * 6, seed=777, instance=0, c_max=32, dt=2e-15,
+                precision="fp64", steps=400)
+    base.update(kw)
+    return base
+
+
+def snapshot(sim, inst=0):
+    kx, ky = sim.get_state(inst)
+    H, M = sim.histogram(inst)
+    return dict(kx=kx, ky=ky, H=H, M=M, cnt=sim.counters(inst),
+                rec=sim.moments(inst=inst)["per_node_vx"], agg=sim.moments(inst=inst)["E_jx"])
+
+
+def assert_same(a, b, what=""):
+    for k in a:
+        if isinstance(a[k], dict):
+            assert a[k] == b[k], (what, k)
+        else:
+            assert np.array_equal(a[k], b[k]), (what, k)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replay_matches_eager(sg, prec):
+    """Graphs of 4 steps replayed many times, with host reads between the
+    calls, against the same calls launched eagerly; every call compared."""
+    cfg = cfg_of(precision=prec)
+    print(f"\n[gpu case] graph replay {prec}", flush=True)
+    eager = sg.Simulation(cfg)
+    eager.set_graph(0)
+    graph = sg.Simulation(cfg)
+    graph.set_graph(4)
+    for s in (eager, graph):
+        s.init_particles()
+    for n in (13, 20, 1, 17, 4):
+        eager.step(n)
+        graph.step(n)
+        assert_same(snapshot(eager), snapshot(graph), f"after {n}")
+    assert eager.step_count == graph.step_count == 55
+
+
+def test_graph_survives_rechunk(sg):
+    """A new launch shape drops the captured graphs; replays after it match."""
+    cfg = cfg_of(n_particles=30_000)
+    a = sg.Simulation(cfg)
+    b = sg.Simulation(cfg)
+    a.set_graph(0)
+    b.set_graph(3)
+    for s in (a, b):
+        s.init_particles()
+        s.set_chunk(512)
+        s.step(7)
+    assert_same(snapshot(a), snapshot(b))
+
+
+def mixed_instances():
+    """Six instances in four shape groups, two groups with several members of
+    different P and Q (P = 6, Q = 8 with P = 5, Q = 7)."""
+    return [
+        cfg_of(n_particles=30_000, instance=0),
+        cfg_of(n_particles=12_345, field0=5e6, instance=1, seed=99),
+        cfg_of(dim_z=0, degree=0, nodes_1d=1, gap_dim=-1, gap_rel=0.0, n_particles=5_000,
+               instance=2),
+        cfg_of(n_particles=20_000, precision="fp32", instance=3),
+        cfg_of(degree=2, nodes_1d=5, n_particles=7_000, gap0=0.4, instance=4),
+        cfg_of(degree=4, nodes_1d=7, n_particles=9_000, field0=1e5, instance=5),
+    ]
+
+
+def test_batched_matches_single_instances(sg):
+    cfgs = mixed_instances()
+    print("\n[gpu case] batched 6 instances", flush=True)
+    batch = sg.Simulation(cfgs)
+    batch.init_particles()
+    batch.set_profiling(True)
+    batch.step(25)
+    t = batch.kernel_times()
+    n_groups = t["stream"][1] // 25
+    assert n_groups == 4, t
+    assert t["finalize"][1] == t["collide"][1] == 25 * n_groups
+    assert all(ms > 0 for ms, _ in t.values())
+    batch.set_profiling(False)
+    batch.step(15)
+    for j, cfg in enumerate(cfgs):
+        alone = sg.Simulation(cfg)
+        alone.init_particles()
+        alone.step(25)
+        alone.step(15)
+        assert_same(snapshot(batch, j), snapshot(alone), f"instance {j}")
+
+
+def test_batched_instance_matches_oracle(sg):
+    """An instance with P = 5, Q = 7 run inside a group whose kernels are
+    padded for P <= 6, Q <= 8, against the oracle."""
+    import oracle
+    from test_gpu_parity import TOL, rel_err
+    cfgs = mixed_instances()
+    batch = sg.Simulation(cfgs)
+    batch.init_particles()
+    batch.step(30)
+    j = 5
+    gx, gy = batch.get_state(j)
+    ref = oracle.OracleSim(cfgs[j])
+    ref.init()
+    ref.run(cfgs[j]["dt"], 30)
+    ox, oy = ref.get_state()
+    err = rel_err(gx, gy, ox, oy)
+    flips = int((err > TOL).sum())
+    assert flips <= 2, (flips, err.max())
+    if flips == 0:
+        H, M = batch.histogram(j)
+        Ho, Mo = ref.histogram()
+        assert np.array_equal(H, Ho) and np.array_equal(M, Mo)
+
+
+def test_sweep_of_64_instances(sg):
+    """The 64-instance sweep (three shape groups), scaled to 2e3-2e4
+    particles, in graphs of 8 steps; sampled instances against runs alone."""
+    cfgs = batched_sweep(n_min=2e3, n_max=2e4, steps=100)
+    print(f"\n[gpu case] sweep of {len(cfgs)} instances, N={sum(c['n_particles'] for c in cfgs)}",
+          flush=True)
+    batch = sg.Simulation(cfgs)
+    batch.set_graph(8)
+    batch.init_particles()
+    batch.step(20)
+    for j in (0, 17, 40, 63):
+        alone = sg.Simulation(cfgs[j])
+        alone.init_particles()
+        alone.step(20)
+        assert_same(snapshot(batch, j), snapshot(alone), f"instance {j}")

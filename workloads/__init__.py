@@ -46,3 +46,29 @@ def workload(name: str, **overrides) -> dict:
     cfg = copy.deepcopy(WORKLOADS[name])
     cfg.update(overrides)
     return cfg
+
+
+def batched_sweep(n_inst: int = 64, n_min: float = 1e5, n_max: float = 2e6,
+                  seed: int = BASE_SEED + 4, precision: str = "fp32", steps: int = 2500) -> list:
+    """The batched parameter sweep: n_inst independent instances with the field
+    uniform over 1-50 kV/cm, the mean band gap uniform over 0.1-0.5 eV with a
+    +-10 % uniform uncertainty, Legendre order M drawn from {2, 4, 6} with
+    Q = M + 3 Gauss nodes, and particle counts log-uniform in [n_min, n_max].
+    The draws come from numpy's PCG64 seeded with ``seed``; every instance
+    shares the Philox key and has its own instance word, so the random
+    streams of the method are independent."""
+    import math
+
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(n_inst):
+        field = float(rng.uniform(1.0e5, 5.0e6))
+        gap0 = float(rng.uniform(0.1, 0.5))
+        M = int(rng.choice([2, 4, 6]))
+        N = int(round(10.0 ** rng.uniform(math.log10(n_min), math.log10(n_max))))
+        out.append(dict(_COMMON, dim_z=1, degree=M, nodes_1d=M + 3, n_particles=N, gap0=gap0,
+                        gap_rel=0.1, gap_dim=0, field0=field, field_rel=0.0, field_dim=-1,
+                        steps=steps, precision=precision, seed=seed, instance=j))
+    return out
