@@ -1,22 +1,29 @@
 """Benchmark of the sG-PM hot path on one MI355X.
 
-Workload: sg_gap_m5_q8_n1e6 -- 1e6 particles, uncertain band gap
+Headline workload: sg_gap_m5_q8_n1e6 -- 1e6 particles, uncertain band gap
 Delta(z) = 0.2 eV (1 + 0.1 z), Legendre order M = 5 (6 modes), 8 Gauss nodes,
 E = 20 kV/cm, dt = 2 fs, FP64 particle state (the plain form), the paper's
-rates and Pauli acceptance on a 240 x 240 grid.  A step is one pass of the
-whole hot path (drift, node evaluation, collisions, histogram, moments) over
-all particles.  The same steps are also run with FP32 particle state and the
-two are compared against the Monte Carlo standard error.
+rates and the Pauli acceptance on a 240 x 240 grid.  A step is one pass of
+the whole hot path (drift, node evaluation, histogram, moments, collision
+decision, nodal collisions, projection) over every particle, launched the
+library's default way (captured HIP graphs of 16 steps).
 
-Prints one JSON line.  Throughput is particle-node updates per second with the
-state resident in HBM; the roofline of the step kernel uses its algorithmic
-bytes per launch and its average duration from HIP events on the stream it
-runs on.  The CPU baseline is the plain FP64 oracle on a bounded sample of the
-same workload, on the host cores.
+The same K steps are then run once more with a HIP event after every kernel
+launch (on the library's stream) to time each kernel; the roofline is that
+of the kernel with the largest mean time, from its algorithmic bytes per
+launch.  The same workload with FP32 particle state is run beside it and
+compared against the Monte Carlo standard error, and the 64-instance batched
+FP32 sweep is timed in one shared launch per kernel and step.  The CPU
+baseline is the plain FP64 oracle on a bounded sample of the headline
+workload, on the host cores.
+
+Prints one JSON line.  Throughput is particle-node updates per second with
+the state resident in HBM.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,43 +34,105 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "sg_gap_m5_q8_n1e6"
+KERNEL_SYMBOLS = {"stream": "sgpm::k1_stream", "finalize": "sgpm::k3_finalize",
+                  "collide": "sgpm::k2_collide"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_sg_gap_m5_q8_n1e6.json")
 
 
-def algorithmic_bytes(cfg: dict, P: int, Q: int, n_drift_modes: int, candidates_per_step: float):
-    """Bytes one step must move in HBM: read every coefficient; write back the
-    drifted modes of the particles that do not collide and every mode of the
-    ones that may; clear the stale histogram of Q nk^2 uint32 cells."""
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sgpm_kernels.hip", "sgpm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2404_19602_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def kernel_bytes(cfg: dict, P: int, Q: int, n_drift: int, cand: float) -> dict:
+    """Algorithmic HBM bytes of one launch of each step kernel.
+
+    stream: read every coefficient (2 P s per particle) and write back the
+      drifted modes of the particles that cannot collide (n_drift s each);
+    finalize: write H^n (Q nk^2 uint32) and clear the overflow counts of the
+      next one (the same size);
+    collide: read and write all 2 P coefficients of every candidate."""
     s = 4 if cfg.get("precision") == "fp32" else 8
     N = cfg["n_particles"]
-    read = 2 * P * s * N
-    write = (N - candidates_per_step) * n_drift_modes * s + candidates_per_step * 2 * P * s
-    clear = Q * cfg["nk"] ** 2 * 4
-    return read + write + clear
+    grid = Q * cfg.get("nk", 240) ** 2 * 4
+    return {"stream": 2 * P * s * N + (N - cand) * n_drift * s,
+            "finalize": 2 * grid,
+            "collide": cand * 4 * P * s}
 
 
-def run_gpu(cfg: dict, steps: int, warmup: int):
+def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True):
+    """Warm-up, K timed steps in the default launch mode, then K profiled
+    steps.  cfgs: one workload or a list (batched instances)."""
     import numpy as np
     import torch
     import paper_2404_19602_amd as sg
 
-    sim = sg.Simulation(cfg, max_steps=warmup + steps)
+    many = isinstance(cfgs, list)
+    sim = sg.Simulation(cfgs, max_steps=warmup + 2 * steps)
     sim.init_particles()
+    dt = (cfgs[0] if many else cfgs)["dt"]
     if warmup:
-        sim.step(warmup, cfg["dt"])
-    c0 = sim.counters()
+        sim.step(warmup, dt)
+    c0 = [sim.counters(j) for j in range(sim.n_inst)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sim.step(steps, cfg["dt"])
+    sim.step(steps, dt)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    dev_ms = sim.last_step_ms()        # HIP events on the library's stream
-    c1 = sim.counters()
-    mom = sim.moments()
-    t = sim.tables()
-    n_drift = int(np.count_nonzero(t["ehat"]))
-    cand = (c1["candidates"] - c0["candidates"]) / steps
-    return dict(sim=sim, wall=wall, dev_ms=dev_ms, moments=mom, P=sim.P, Q=sim.Q,
-                n_drift=n_drift, cand=cand, counters=c1)
+    dev_ms = sim.last_step_ms()
+    c1 = [sim.counters(j) for j in range(sim.n_inst)]
+    out = dict(sim=sim, wall=wall, dev_ms=dev_ms,
+               cand=[(b["candidates"] - a["candidates"]) / steps for a, b in zip(c0, c1)])
+    if not many:
+        out["moments"] = sim.moments(0, warmup + steps + 1)
+        t = sim.tables()
+        out["n_drift"] = int(np.count_nonzero(t["ehat"]))
+    if profile:
+        sim.set_profiling(True)
+        sim.step(steps, dt)
+        out["kernels"] = sim.kernel_times()
+        sim.set_profiling(False)
+    return out
+
+
+def roofline_of(cfg, r, P, Q) -> tuple:
+    """Per-kernel achieved GB/s and the roofline object of the dominant kernel."""
+    b = kernel_bytes(cfg, P, Q, r["n_drift"], r["cand"][0])
+    per = {}
+    for k, (ms, n) in r["kernels"].items():
+        per[k] = {"avg_ms": ms, "launches": n, "bytes_per_launch": b[k],
+                  "GBps": b[k] / (ms * 1e-3) / 1e9 if ms > 0 else None}
+    dom = max(per, key=lambda k: per[k]["avg_ms"])
+    ach = per[dom]["GBps"]
+    roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": KERNEL_SYMBOLS[dom],
+            "kernel_ms": per[dom]["avg_ms"], "bytes_per_launch": per[dom]["bytes_per_launch"],
+            "timing": "HIP events around each launch on the library's stream, "
+                      "profiled pass of the same number of steps"}
+    traffic = measured_traffic(dom)
+    if traffic is not None:
+        roof["traffic"] = traffic
+    return roof, per
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of a kernel from the committed PMC summary, if the
+    kernel source is the one the counters were taken on."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
 def cpu_baseline(cfg: dict):
@@ -96,28 +165,42 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison run")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance sweep")
+    ap.add_argument("--batched-steps", type=int, default=100)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run five plain 256 MiB device copies (calibrates the HBM "
+                         "byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the sharded "
-              "design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); how the "
+              "path would shard over several GPUs is described in DESIGN.md", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
-    from workloads import workload
+    from workloads import batched_sweep, workload
+
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 5 copies of 268435456 bytes")
+        del src, dst
 
     cfg = workload(WORKLOAD)
-    print(f"[bench] {WORKLOAD}: FP64, {args.warmup} warm-up + {args.steps} timed steps",
-          file=sys.stderr, flush=True)
+    log(f"{WORKLOAD}: FP64, {args.warmup} warm-up + {args.steps} timed + {args.steps} profiled steps")
     r64 = run_gpu(dict(cfg, precision="fp64"), args.steps, args.warmup)
-    P, Q, N = r64["P"], r64["Q"], cfg["n_particles"]
+    P, Q, N = r64["sim"].P, r64["sim"].Q, cfg["n_particles"]
     pn = N * Q * args.steps
-    value = pn / r64["wall"]
-    bytes64 = algorithmic_bytes(cfg, P, Q, r64["n_drift"], r64["cand"])
-    achieved = bytes64 / (r64["dev_ms"] * 1e-3) / 1e9
+    roof, per = roofline_of(dict(cfg, precision="fp64"), r64, P, Q)
+    log(f"FP64 {r64['wall'] * 1e3 / args.steps:.4f} ms/step; kernels " +
+        ", ".join(f"{k} {v['avg_ms'] * 1e3:.1f} us" for k, v in per.items()))
 
     out = {
         "metric": "particle-node updates/s + HBM GB/s; FP32-batched vs FP64 plain at matched err",
-        "value": value,
+        "value": pn / r64["wall"],
         "unit": "particle-node updates/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -130,36 +213,52 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n_particles": N, "gpc_modes": P, "nodes": Q,
                    "grid": cfg["nk"], "dt_fs": cfg["dt"] * 1e15, "field_V_per_m": cfg["field0"],
-                   "gap_eV": cfg["gap0"], "gap_rel": cfg["gap_rel"], "state": "fp64"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "sgpm::step_kernel<double,8>",
-                     "kernel_ms": r64["dev_ms"], "bytes_per_launch": bytes64},
-        "hbm_GBps": achieved,
-        "candidates_per_step": r64["cand"],
+                   "gap_eV": cfg["gap0"], "gap_rel": cfg["gap_rel"], "state": "fp64",
+                   "launch": "hip graphs of 16 steps"},
+        "roofline": roof,
+        "kernels": per,
+        "device_ms_per_step": r64["dev_ms"],
+        "candidates_per_step": r64["cand"][0],
     }
+    del r64["sim"]
 
     if not args.no_fp32:
-        print("[bench] FP32 run of the same steps", file=sys.stderr, flush=True)
+        log("FP32 run of the same steps")
         r32 = run_gpu(dict(cfg, precision="fp32"), args.steps, args.warmup)
         m64, m32 = r64["moments"], r32["moments"]
         dev = {}
         for obs in ("E_vx", "Var_vx", "E_jx", "Var_jx", "E_energy"):
             se = np.maximum(m64["SE_" + obs][1:], 1e-300)
             dev[obs] = float(np.max(np.abs(m64[obs][1:] - m32[obs][1:]) / se))
-        bytes32 = algorithmic_bytes(dict(cfg, precision="fp32"), P, Q, r32["n_drift"], r32["cand"])
+        _, per32 = roofline_of(dict(cfg, precision="fp32"), r32, P, Q)
         out["fp32"] = {
             "value": pn / r32["wall"], "ms_per_step": r32["wall"] * 1e3 / args.steps,
-            "kernel_ms": r32["dev_ms"],
-            "hbm_GBps": bytes32 / (r32["dev_ms"] * 1e-3) / 1e9,
+            "kernels": per32,
             "speedup_vs_fp64": r64["wall"] / r32["wall"],
             "max_abs_dev_over_mc_se": dev,
             "matched_error": all(v < 3.0 for v in dev.values()),
         }
         del r32
 
+    if not args.no_batched:
+        cfgs = batched_sweep()
+        nb = args.batched_steps
+        log(f"batched sweep: {len(cfgs)} instances, FP32, {sum(c['n_particles'] for c in cfgs)} "
+            f"particles, 10 warm-up + {nb} timed steps")
+        rb = run_gpu(cfgs, nb, 10)
+        pn_b = sum(c["n_particles"] * (c["degree"] + 3) for c in cfgs) * nb
+        out["batched"] = {
+            "workload": "batched_sweep_64 (E 1-50 kV/cm, gap 0.1-0.5 eV +-10 %, M in {2,4,6}, "
+                        "Q = M + 3, N log-uniform 1e5-2e6)",
+            "instances": len(cfgs), "n_particles": sum(c["n_particles"] for c in cfgs),
+            "value": pn_b / rb["wall"], "unit": "particle-node updates/s",
+            "ms_per_step": rb["wall"] * 1e3 / nb, "steps": nb, "dtype": "f32",
+            "kernels": {k: {"avg_ms": ms, "launches": n} for k, (ms, n) in rb["kernels"].items()},
+        }
+        del rb
+
     if not args.no_cpu:
-        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        log("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out), flush=True)
 

@@ -229,8 +229,9 @@ sgpm_status sgpm_tables(const sgpm_ctx* ctx, int32_t inst, double* z, double* w,
                         double* density_m2);
 
 /* Launch shape: particles per workgroup chunk (a multiple of 256, at most
- * 8192, and large enough for at most 4096 workgroups) of the step kernels
- * of instance inst; 0 restores the automatic
+ * 8192, at least a quarter of the automatic choice of about N/512, and large
+ * enough for at most 4096 workgroups) of the step kernels of instance inst;
+ * 0 restores the automatic
  * choice.  Particle trajectories, histograms and counters do not depend on
  * it; the FP64 moment sums only through their order.  Allowed right after
  * init/set_state (the current time is re-recorded). */

@@ -30,6 +30,7 @@
  * absent and its tables only give relative errors against a solver it does
  * not describe): "parity unpinned" for those absolute curves.
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -359,12 +360,18 @@ orc_sim *orc_create(const orc_params *p)
     }
 
     /* Galerkin field coefficients  E_h = int E(z) Psi_h(z) p(z) dz  (Sec. 4.1,
-     * electric forcing), by the same quadrature. */
+     * electric forcing), by the same quadrature.  E is linear in z and Psi_h
+     * a polynomial of degree <= M, so the Gauss rule is exact for the
+     * integrand: a sum that lies within its own rounding bound
+     * (4 Q eps sum_q |w_q E_q Psi_h(z_q)|) is the integral's exact zero. */
     s->Ehat = (double *)calloc((size_t)P, sizeof(double));
     for (int h = 0; h < P; ++h) {
-        double acc = 0.0;
-        for (int q = 0; q < Q; ++q) acc += s->w[q] * s->field[q] * s->psi[q * P + h];
-        s->Ehat[h] = acc;
+        double acc = 0.0, mag = 0.0;
+        for (int q = 0; q < Q; ++q) {
+            acc += s->w[q] * s->field[q] * s->psi[q * P + h];
+            mag += fabs(s->w[q] * s->field[q] * s->psi[q * P + h]);
+        }
+        s->Ehat[h] = fabs(acc) <= 4.0 * Q * DBL_EPSILON * mag ? 0.0 : acc;
     }
 
     /* Scattering-rate prefactors, Appendix closed forms, energies in eV.

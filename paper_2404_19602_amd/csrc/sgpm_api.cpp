@@ -119,8 +119,8 @@ CtxLayout ctx_layout(int n) {
     return L;
 }
 
-int64_t min_chunk(int64_t n) {
-    // at most kMaxStreamWG stream workgroups
+// smallest chunk with at most kMaxStreamWG stream workgroups
+int64_t wg_cap_chunk(int64_t n) {
     int64_t c = (n + kMaxStreamWG - 1) / kMaxStreamWG;
     c = (c + kBlock1 - 1) / kBlock1 * kBlock1;
     return c < kBlock1 ? kBlock1 : c;
@@ -130,9 +130,17 @@ int64_t auto_chunk(int64_t n) {
     // about two stream workgroups per compute unit, whole sub-tiles
     int64_t c = (n + 511) / 512;
     c = (c + kBlock1 - 1) / kBlock1 * kBlock1;
-    if (c < min_chunk(n)) c = min_chunk(n);
+    if (c < wg_cap_chunk(n)) c = wg_cap_chunk(n);
     if (c > kMaxChunk) c = kMaxChunk;
     return c;
+}
+
+// smallest chunk a launch shape may use: a quarter of the automatic one
+// (bounds the slab region, one window slab per stream workgroup)
+int64_t min_chunk(int64_t n) {
+    int64_t c = auto_chunk(n) / 4 / kBlock1 * kBlock1;
+    if (c < wg_cap_chunk(n)) c = wg_cap_chunk(n);
+    return c < kBlock1 ? kBlock1 : c;
 }
 
 // LDS histogram window of the stream kernel: the largest even square of
@@ -188,8 +196,8 @@ Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
         int w, r0, l0, words;
         window_for(t.P, t.Q, d.nk, d.precision == SGPM_FP32, (int)auto_chunk(d.n_particles), &w,
                    &r0, &l0, &words);
-        size_t nwg_slab = ((size_t)d.n_particles + kBlock1 - 1) / kBlock1;
-        if (nwg_slab > (size_t)kMaxStreamWG) nwg_slab = kMaxStreamWG;
+        const int64_t mc = min_chunk(d.n_particles);
+        const size_t nwg_slab = (size_t)((d.n_particles + mc - 1) / mc);
         L.add(nwg_slab * (size_t)words * 4);          // 35 slabs
     }
     return L;
@@ -820,7 +828,9 @@ sgpm_status sgpm_set_chunk(sgpm_ctx* c, int32_t inst, int32_t chunk) {
         return fail(c, SGPM_EINVAL, "chunk must be a multiple of 256 up to 8192 (0 = automatic)");
     Instance& I = c->inst[inst];
     if (chunk > 0 && chunk < min_chunk(I.n))
-        return fail(c, SGPM_EINVAL, "chunk too small: at most 4096 stream workgroups");
+        return fail(c, SGPM_EINVAL,
+                    "chunk too small: at least a quarter of the automatic chunk and at most "
+                    "4096 stream workgroups");
     if (I.initialised && I.step != I.rec_base)
         return fail(c, SGPM_ESTATE, "the launch shape can only change right after init/set_state");
     set_chunk(I, chunk);

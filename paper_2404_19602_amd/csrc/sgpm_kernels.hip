@@ -740,11 +740,13 @@ __global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T>* __restrict
         __syncthreads();
         if (total) k2_instance<T, PMAX>(a, smem, step, total);
     }
+    // No fence: a workgroup has used its reads of the step before it counts
+    // itself done, and the kernel boundary publishes the new step to the
+    // next launch (a device-scope fence here would write back the L2 of the
+    // XCD once per workgroup).
     if (tid == 0) {
-        __threadfence();
         if (atomicAdd(done, 1u) == gridDim.x - 1) {
             for (int j = 0; j < n_inst; ++j) all[j].dyn->step += 1u;
-            __threadfence();
             atomicExch(done, 0u);
         }
     }

@@ -2,6 +2,7 @@
 // weights, the orthonormal Legendre basis, the Galerkin field coefficients
 // (Sec. 4.1), the scattering-rate constants of the Appendix, the electron
 // density and the Fermi-Dirac CDF tables of the initial datum.
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 
@@ -192,11 +193,18 @@ const char* build_tables(const sgpm_instance_desc& d, HostTables& t) {
         }
         t.field[q] = d.field0 * (1.0 + d.field_rel * zf);
     }
+    // Galerkin field coefficients (Sec. 4.1) by the Gauss rule, exact for the
+    // polynomial integrand E(z) Psi_h(z): sums within their rounding bound are
+    // the exact zeros of the modes E(z) does not reach, and the drift leaves
+    // those modes untouched.
     t.ehat.assign(P, 0.0);
     for (int h = 0; h < P; ++h) {
-        double s = 0.0;
-        for (int q = 0; q < Q; ++q) s += t.wpsi[q * P + h] * t.field[q];
-        t.ehat[h] = s;
+        double s = 0.0, mag = 0.0;
+        for (int q = 0; q < Q; ++q) {
+            s += t.wpsi[q * P + h] * t.field[q];
+            mag += std::fabs(t.wpsi[q * P + h] * t.field[q]);
+        }
+        t.ehat[h] = std::fabs(s) <= 4.0 * Q * DBL_EPSILON * mag ? 0.0 : s;
     }
 
     // Appendix closed forms; rate = c * energy[eV] * (occupation factors)

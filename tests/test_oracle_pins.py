@@ -134,6 +134,19 @@ def test_field_coefficients_closed_form(orc):
     ref[0] = E0
     ref[2] = E0 * r / math.sqrt(3)          # mode (0,1) is linear in z_2
     assert np.allclose(t["ehat"], ref, atol=1e-9 * E0, rtol=0)
+    # the modes the field does not reach are exact zeros (the drift leaves them alone)
+    assert np.count_nonzero(t["ehat"]) == 2 and t["ehat"][1] == 0.0
+
+
+@pytest.mark.parametrize("kw", [dict(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1),
+                                dict(dim_z=1, degree=8, nodes_1d=12, gap_dim=0, gap_rel=0.2),
+                                dict(dim_z=2, degree=4, nodes_1d=8, gap_dim=0, gap_rel=0.15)])
+def test_deterministic_field_drives_only_the_mean_mode(orc, kw):
+    # E independent of z: E_h = E0 for h = 0 and exactly 0 otherwise
+    E0 = 2e6
+    t = orc.OracleSim(small(field0=E0, n_particles=4, **kw)).tables()
+    assert abs(t["ehat"][0] - E0) <= 1e-12 * E0
+    assert np.all(t["ehat"][1:] == 0.0)
 
 
 def test_gap_and_width(orc):
