@@ -71,7 +71,7 @@ struct Instance {
     Consts<double>* d_consts = nullptr; Consts<float>* f_consts = nullptr;
     double* d_ehat = nullptr;
     int* cand = nullptr;       // [N] global candidate list
-    uint32_t* qc = nullptr;    // [2][2] candidate count and work head, by step parity
+    uint32_t* qc = nullptr;    // [2][2] candidate count (and a spare word), by step parity
 };
 
 // Instances of one shape, stepped by one launch of each kernel.
@@ -82,6 +82,7 @@ struct Group {
     int pos0 = 0;              // first slot
     unsigned k1_grid = 0, k3_grid = 0;
     size_t k1_lds = 0, k2_lds = 0;
+    int npl = 1;               // collider nodes per lane (2 beyond 64 nodes)
 };
 
 // Bytes of every device region of one instance, in carving order.
@@ -100,7 +101,7 @@ struct Layout {
 // Context region at the start of the workspace: step states, descriptor
 // arrays and workgroup tables of n instances.
 struct CtxLayout {
-    size_t dyn, k1d, k1f, k2d, k2f, k3, wg, done, total;
+    size_t dyn, k1d, k1f, k2d, k2f, k3, wg, total;
 };
 
 CtxLayout ctx_layout(int n) {
@@ -113,8 +114,7 @@ CtxLayout ctx_layout(int n) {
     L.k2d = put((size_t)n * sizeof(K2Args<double>));
     L.k2f = put((size_t)n * sizeof(K2Args<float>));
     L.k3 = put((size_t)n * sizeof(K3Args));
-    L.wg = put((size_t)10 * n * sizeof(uint32_t));   // 3 group tables + 2 single tables, 2n each
-    L.done = put((size_t)n * 64);
+    L.wg = put((size_t)8 * n * sizeof(uint32_t));    // 2 group tables + 2 single tables, 2n each
     L.total = o;
     return L;
 }
@@ -227,8 +227,7 @@ struct sgpm_ctx {
     K1Args<double>* k1d = nullptr; K1Args<float>* k1f = nullptr;
     K2Args<double>* k2d = nullptr; K2Args<float>* k2f = nullptr;
     K3Args* k3 = nullptr;
-    uint32_t* wg = nullptr;        // [5][2n] workgroup tables
-    uint32_t* done = nullptr;      // [n][16] collider completion counters by group
+    uint32_t* wg = nullptr;        // [4][2n] workgroup tables
     // host mirrors of the descriptor arrays
     std::vector<K1Args<double>> h_k1d; std::vector<K1Args<float>> h_k1f;
     std::vector<K2Args<double>> h_k2d; std::vector<K2Args<float>> h_k2f;
@@ -392,8 +391,8 @@ int k3_grid(const Instance& I) {
     return k3_grid_of(I.Q, I.nk, (I.hwin_words + kK3Words - 1) / kK3Words, I.nb);
 }
 
-// workgroup tables: group tables of K1, K3, K2 and single-instance tables of K1, K3
-enum { kTabK1 = 0, kTabK3 = 1, kTabK2 = 2, kTabK1One = 3, kTabK3One = 4 };
+// workgroup tables: group tables of K1, K3 and single-instance tables of K1, K3
+enum { kTabK1 = 0, kTabK3 = 1, kTabK1One = 2, kTabK3One = 3 };
 uint32_t* wg_table(sgpm_ctx* c, int tab, int off) {
     return c->wg + (size_t)tab * 2 * c->inst.size() + off;
 }
@@ -408,26 +407,21 @@ void drop_graphs(sgpm_ctx* c) {
 sgpm_status upload_args(sgpm_ctx* c) {
     const int n = (int)c->inst.size();
     std::vector<uint32_t>& W = c->h_wg;
-    W.assign((size_t)10 * n, 0u);
+    W.assign((size_t)8 * n, 0u);
     auto tab = [&](int t, int off) { return &W[(size_t)t * 2 * n + off]; };
     for (size_t g = 0; g < c->groups.size(); ++g) {
         Group& G = c->groups[g];
         const int off = G.pos0 + (int)g;
-        uint32_t *t1 = tab(kTabK1, off), *t3 = tab(kTabK3, off), *t2 = tab(kTabK2, off);
-        t1[0] = t3[0] = t2[0] = 0u;
-        double ntot = 0.0;
-        for (int k : G.members) ntot += (double)c->inst[k].n;
-        double cum = 0.0;
-        G.k1_lds = 0; G.k2_lds = 0;
+        uint32_t *t1 = tab(kTabK1, off), *t3 = tab(kTabK3, off);
+        t1[0] = t3[0] = 0u;
+        G.k1_lds = 0; G.k2_lds = 0; G.npl = 1;
         for (size_t m = 0; m < G.members.size(); ++m) {
             Instance& I = c->inst[G.members[m]];
             t1[m + 1] = t1[m] + (uint32_t)I.nwg;
             t3[m + 1] = t3[m] + (uint32_t)k3_grid(I);
-            cum += (double)I.n;
-            t2[m + 1] = (uint32_t)std::llround(kK2Grid * cum / ntot);
-            if (m + 1 == G.members.size()) t2[m + 1] = kK2Grid;
             G.k1_lds = std::max(G.k1_lds, k1_lds_bytes(I.P, I.Q, I.fp32, I.hwin_words, (int)I.chunk));
             G.k2_lds = std::max(G.k2_lds, k2_lds_bytes(I.P, I.Q, I.fp32));
+            if (I.Q > 64) G.npl = 2;
             uint32_t* s1 = tab(kTabK1One, 2 * I.pos);
             uint32_t* s3 = tab(kTabK3One, 2 * I.pos);
             s1[0] = 0u; s1[1] = (uint32_t)I.nwg;
@@ -488,11 +482,10 @@ sgpm_status enqueue_step(sgpm_ctx* c, hipStream_t s, bool prof) {
                           wg_table(c, kTabK1, off), m, 1, G.k1_grid, G.k1_lds, s);
         if (e) return dev_fail(c, (hipError_t)e, "stream kernel launch");
         if (prof) { sgpm_status r = prof_mark(c, s, SGPM_KERNEL_STREAM); if (r) return r; }
-        e = launch_k3(c->k3 + G.pos0, wg_table(c, kTabK3, off), m, G.k3_grid, s);
+        e = launch_k3(c->k3 + G.pos0, wg_table(c, kTabK3, off), m, 1, G.k3_grid, s);
         if (e) return dev_fail(c, (hipError_t)e, "finalize kernel launch");
         if (prof) { sgpm_status r = prof_mark(c, s, SGPM_KERNEL_FINALIZE); if (r) return r; }
-        e = launch_k2(G.fp32, G.pmax, k2_args(c, G.fp32, G.pos0), wg_table(c, kTabK2, off), m,
-                      c->done + 16 * g, kK2Grid, G.k2_lds, s);
+        e = launch_k2(G.fp32, G.pmax, G.npl, k2_args(c, G.fp32, G.pos0), m, kK2Grid, G.k2_lds, s);
         if (e) return dev_fail(c, (hipError_t)e, "collider launch");
         if (prof) { sgpm_status r = prof_mark(c, s, SGPM_KERNEL_COLLIDE); if (r) return r; }
     }
@@ -506,7 +499,7 @@ sgpm_status enqueue_state_pass(sgpm_ctx* c, hipStream_t s) {
         const int m = (int)G.members.size(), off = G.pos0 + (int)g;
         int e = launch_k1(G.fp32, G.pmax, G.qmax, k1_args(c, G.fp32, G.pos0),
                           wg_table(c, kTabK1, off), m, 0, G.k1_grid, G.k1_lds, s);
-        if (!e) e = launch_k3(c->k3 + G.pos0, wg_table(c, kTabK3, off), m, G.k3_grid, s);
+        if (!e) e = launch_k3(c->k3 + G.pos0, wg_table(c, kTabK3, off), m, 0, G.k3_grid, s);
         if (e) return dev_fail(c, (hipError_t)e, "state pass launch");
     }
     return SGPM_OK;
@@ -519,8 +512,8 @@ sgpm_status state_pass_one(sgpm_ctx* c, const Instance& I) {
                       wg_table(c, kTabK1One, 2 * I.pos), 1, 0, (unsigned)I.nwg,
                       k1_lds_bytes(I.P, I.Q, I.fp32, I.hwin_words, (int)I.chunk), c->stream);
     if (!e)
-        e = launch_k3(c->k3 + I.pos, wg_table(c, kTabK3One, 2 * I.pos), 1, (unsigned)k3_grid(I),
-                      c->stream);
+        e = launch_k3(c->k3 + I.pos, wg_table(c, kTabK3One, 2 * I.pos), 1, 0,
+                      (unsigned)k3_grid(I), c->stream);
     if (e) return dev_fail(c, (hipError_t)e, "state pass launch");
     return SGPM_OK;
 }
@@ -677,7 +670,6 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
     c->k2d = (K2Args<double>*)(base + CL.k2d); c->k2f = (K2Args<float>*)(base + CL.k2f);
     c->k3 = (K3Args*)(base + CL.k3);
     c->wg = (uint32_t*)(base + CL.wg);
-    c->done = (uint32_t*)(base + CL.done);
     base += CL.total;
     std::vector<Dyn> dyn0(n_inst);
     for (int k = 0; k < n_inst; ++k) {
@@ -776,7 +768,6 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
     }
     hipError_t e = hipMemcpyAsync(c->dyn, dyn0.data(), n_inst * sizeof(Dyn), hipMemcpyHostToDevice,
                                   c->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(c->done, 0, (size_t)n_inst * 64, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = hipEventCreate(&c->ev0);
     if (e == hipSuccess) e = hipEventCreate(&c->ev1);

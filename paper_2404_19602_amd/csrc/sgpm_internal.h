@@ -90,11 +90,20 @@ constexpr int kK2Grid = 1024;         // persistent collider workgroups of one l
 // Per-instance values that change from step to step, resident in device
 // memory.  The kernels of a step read them instead of taking them as launch
 // arguments, so the launches of every step are identical and a captured graph
-// can replay them; the collider's last workgroup advances the step.
+// can replay them.
+//
+// The global step counter n (random streams, buffer parity) is kept in three
+// copies, one per step kernel, each advanced by the kernel that runs after its
+// reader: the finalize kernel of step n advances the stream kernel's copy, the
+// collider the finalize kernel's, the next stream kernel the collider's.  So a
+// copy never changes while its reader runs, and no kernel has to find out
+// when all of its workgroups are done.  Before the stream kernel of step n:
+// step_k1 = step_k3 = n, step_k2 = n - 1.  Bins-only passes advance nothing.
 struct Dyn {
-    uint32_t step;       // global step counter n: random streams, buffer parity
-    uint32_t rec_base;   // value of step at record index 0
-    uint32_t pad0, pad1;
+    uint32_t step_k1;    // n as read by the stream kernel
+    uint32_t step_k3;    // n as read by the finalize kernel
+    uint32_t step_k2;    // n as read by the collider
+    uint32_t rec_base;   // value of n at record index 0
     double dt;           // time step, s
     double vfdt;         // v_F dt, m: the drift of mode h is vfdt * ehat[h]
     double v_f;          // m/s
@@ -114,14 +123,14 @@ struct K1Args {
     int P, Q;
     DevTab<T> tab;
     const double* ehat;     // [P] Galerkin field coefficients (V/m)
-    const Dyn* dyn;
+    Dyn* dyn;
     uint32_t seed_lo, seed_hi, instance, pad;
     uint32_t* extra;        // overflow grid of H^n (outside the LDS window)
     uint32_t* slabs;        // [nwg][hwin_words] window slabs of H^n
     int win, win_r0, win_l0, hwin_words;
     double* partial;        // [nwg][Q][3] moment sums at t^n
     int* cand;              // global list of collision candidates
-    uint32_t* qc;           // [2][2] candidate count and work head, by step parity
+    uint32_t* qc;           // [2][2] candidate count (and a spare word), by step parity
     unsigned long long* counters;
     int64_t chunk;
 };
@@ -136,7 +145,7 @@ struct K2Args {
     int P, Q, G, pad;       // G: lanes per candidate (power of two)
     DevTab<T> tab;
     const double* ehat;
-    Dyn* dyn;               // step advanced here once every workgroup is done
+    Dyn* dyn;
     uint32_t seed_lo, seed_hi, instance, pad2;
     const uint32_t* H;      // [3][hstride] histograms, H^n at n mod 3
     const uint32_t* Hmax;   // [3][hmstride] their per-node maxima
@@ -167,7 +176,7 @@ struct K3Args {
     int pad;
     const double* partial;  // [nwg][Q][3]
     double* record;         // [max_steps + 1][nb][Q][3]
-    const Dyn* dyn;
+    Dyn* dyn;
 };
 
 struct InitArgs {
@@ -202,9 +211,10 @@ struct EnergyHistArgs {
 // one shape group and wg0[n_inst + 1], the first workgroup of each instance.
 int launch_k1(int fp32, int pmax, int qmax, const void* args, const uint32_t* wg0, int n_inst,
               int moving, unsigned grid, size_t lds, void* stream);
-int launch_k2(int fp32, int pmax, const void* args, const uint32_t* wg0, int n_inst,
-              uint32_t* done, unsigned grid, size_t lds, void* stream);
-int launch_k3(const K3Args* args, const uint32_t* wg0, int n_inst, unsigned grid, void* stream);
+int launch_k2(int fp32, int pmax, int npl, const void* args, int n_inst, unsigned grid,
+              size_t lds, void* stream);
+int launch_k3(const K3Args* args, const uint32_t* wg0, int n_inst, int moving, unsigned grid,
+              void* stream);
 int launch_set_dyn(Dyn* d, int n, int set_step, uint32_t step, uint32_t rec_base, int set_dt,
                    double dt, void* stream);
 int pmax_bucket(int P);

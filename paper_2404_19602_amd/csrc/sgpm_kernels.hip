@@ -103,14 +103,6 @@ __device__ __forceinline__ T group_max(T v, int G) {
     return v;
 }
 
-// sum over the lanes of the group, the same value (the group's first lane's
-// result) delivered to every lane
-template <typename T>
-__device__ __forceinline__ T group_sum(T v, int G) {
-    for (int m = G >> 1; m >= 1; m >>= 1) v += __shfl_xor(v, m, G);
-    return __shfl(v, 0, G);
-}
-
 // ------------------------------------------------------- rate evaluations
 // the five closed-form phonon rates (Appendix) at energy e of a node with
 // band minimum e0, order AC, OP-, OP+, K-, K+
@@ -303,8 +295,10 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
     const int slot = find_slot(wg0, n_inst, blockIdx.x);
     const K1Args<T> a = load_desc(all, slot);
     const uint32_t wg = blockIdx.x - wg0[slot];
-    const uint32_t step = a.dyn->step;
+    const uint32_t step = a.dyn->step_k1;
     const double vfdt = a.dyn->vfdt;
+    // the collider of the previous step is done with its copy of n
+    if (moving && wg == 0 && threadIdx.x == 0) a.dyn->step_k2 = step;
     const T dt = (T)a.dyn->dt;
     const int P = a.P, Q = a.Q;
     const K1Lds<T> L = k1_lds<T>(smem, PMAX, Q, a.hwin_words, (int)a.chunk);
@@ -464,14 +458,24 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
 }
 
 // ===================================================== K2: collider kernel
+// lanes per candidate of the collider: one node per lane, at most a wave
+__host__ __device__ __forceinline__ int k2_group_width(int Q) {
+    int G = 1;
+    while (G < Q && G < 64) G <<= 1;
+    return G;
+}
+
 size_t k2_lds_bytes(int P, int Q, int fp32) {
     const size_t s = fp32 ? 4 : 8;
     const int PM = pmax_bucket(P);
+    const int groups = kBlock / k2_group_width(Q);
     size_t off = sizeof(Consts<double>);
     off = (off + 15) & ~(size_t)15;
     off += s * (2 * (size_t)Q * PM + 4 * (size_t)Q + 32 + PM);   // psi wpsi eps0 eps0sq cedge vfield ecos drift
     off = (off + 15) & ~(size_t)15;
-    off += 16 * 4 + 16;                  // counters, work slot
+    off += s * (size_t)groups * (2 * (size_t)Q + 2 * PM);         // per-group projection scratch
+    off = (off + 15) & ~(size_t)15;
+    off += 16 * 4;                       // counters
     return off;
 }
 
@@ -479,12 +483,12 @@ template <typename T>
 struct K2Lds {
     Consts<T>* c;
     T* psi; T* wpsi; T* eps0; T* eps0sq; T* cedge; T* vfield; T* ecos; T* drift;
+    T* scratch;          // [groups][2Q + 2PM]: new node values, then new modes
     uint32_t* cnt;
-    uint32_t* slot;
 };
 
 template <typename T>
-__device__ __forceinline__ K2Lds<T> k2_lds(unsigned char* smem, int PM, int Q) {
+__device__ __forceinline__ K2Lds<T> k2_lds(unsigned char* smem, int PM, int Q, int groups) {
     K2Lds<T> L;
     size_t off = 0;
     L.c = reinterpret_cast<Consts<T>*>(smem);
@@ -500,8 +504,10 @@ __device__ __forceinline__ K2Lds<T> k2_lds(unsigned char* smem, int PM, int Q) {
     L.drift = L.ecos + 32;
     off += sizeof(T) * (2 * (size_t)Q * PM + 4 * (size_t)Q + 32 + PM);
     off = (off + 15) & ~(size_t)15;
+    L.scratch = reinterpret_cast<T*>(smem + off);
+    off += sizeof(T) * (size_t)groups * (2 * (size_t)Q + 2 * PM);
+    off = (off + 15) & ~(size_t)15;
     L.cnt = reinterpret_cast<uint32_t*>(smem + off);
-    L.slot = L.cnt + 16;
     return L;
 }
 
@@ -521,19 +527,29 @@ __device__ __forceinline__ T pauli_f(const uint32_t* __restrict__ h_read,
     return (T)h / (T)mx;
 }
 
-// The candidates of one instance, pulled by the whole workgroup until its list
-// is exhausted; total: the list's length (nonzero, uniform).
-template <typename T, int PMAX>
+// Cross-lane exchange through LDS inside one wave: a wave's LDS operations
+// are performed in order, so only the compiler must keep them in order.
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// The candidates of one instance: workgroup b of the grid takes the passes
+// b, b + grid, ... of kBlock / G candidates each (the list is complete when
+// the kernel starts, so a static share needs no work counter); total: the
+// list's length, nonzero and uniform, with at least one pass for b.  A group of G
+// lanes serves one candidate, lane g holding nodes g and g + G (NPL = 2 only
+// when Q > 64).  Per collision every node's rates are evaluated once: their
+// running sums give both Gamma~ (eq. gamma_tot) and the mechanism selection.
+template <typename T, int PMAX, int NPL>
 __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* smem, uint32_t step,
                                             uint32_t total) {
     const int P = a.P, Q = a.Q, G = a.G;
-    const K2Lds<T> L = k2_lds<T>(smem, PMAX, Q);
+    const K2Lds<T> L = k2_lds<T>(smem, PMAX, Q, kBlock / G);
     const int tid = threadIdx.x;
     const T dt = (T)a.dyn->dt;
     const double vfdt = a.dyn->vfdt;
     const uint32_t* h_read = a.H + (size_t)(step % 3u) * a.hstride;
     const uint32_t* hmax_read = a.Hmax + (size_t)(step % 3u) * a.hmstride;
-    uint32_t* head = a.qc + 2 * (step & 1u) + 1;
 
     if (tid == 0) *L.c = *a.tab.consts;
     for (int k = tid; k < Q * PMAX; k += kBlock) {
@@ -554,13 +570,10 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
     const int g = tid % G;                // rank in the group = node handled
     const int grp = tid / G;
     const uint32_t per_pass = kBlock / G;
+    T* nodes = L.scratch + (size_t)grp * (2 * Q + 2 * PMAX);   // [2][Q] new node values
+    T* modes = nodes + 2 * Q;                                   // [2][PMAX] new coefficients
 
-    for (;;) {
-        if (tid == 0) *L.slot = atomicAdd(head, per_pass);
-        __syncthreads();
-        const uint32_t p0 = *L.slot;
-        __syncthreads();
-        if (p0 >= total) break;
+    for (uint32_t p0 = blockIdx.x * per_pass; p0 < total; p0 += gridDim.x * per_pass) {
         const uint32_t cid = p0 + grp;
         if (cid >= total) continue;
         const int64_t i = a.cand[cid];
@@ -570,19 +583,25 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
         uint32_t coll = 0;
         const uint32_t ctr0 = (uint32_t)i;
         for (;;) {
-            // Gamma~ = (1 + alpha) max over the nodes of sum_nu Gamma^nu
+            // node values and running rate sums AC, OP-, OP+, K-, K+, edge;
+            // Gamma~ = (1 + alpha) max over the nodes of the total
+            T nkx[NPL], nky[NPL], ne[NPL], cum[NPL][6];
             T smax = (T)0;
-            for (int q = g; q < Q; q += G) {
-                T kx, ky;
-                eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
-                const T e = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
-                T r[5];
-                phonon_rates<T>(c, e, L.eps0[q], r);
-                T sum = (T)0;
 #pragma unroll
-                for (int m = 0; m < 5; ++m) sum += r[m];
-                sum += edge_rate<T>(c, L.ecos, L.cedge[q], L.eps0[q], kx, ky, e);
-                smax = sum > smax ? sum : smax;
+            for (int j = 0; j < NPL; ++j) {
+                const int q = g + j * G;
+                if (q < Q) {
+                    eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, nkx[j], nky[j]);
+                    ne[j] = sqrt(nkx[j] * nkx[j] + nky[j] * nky[j] + L.eps0sq[q]);
+                    T r[5];
+                    phonon_rates<T>(c, ne[j], L.eps0[q], r);
+                    T run = (T)0;
+#pragma unroll
+                    for (int m = 0; m < 5; ++m) { run += r[m]; cum[j][m] = run; }
+                    run += edge_rate<T>(c, L.ecos, L.cedge[q], L.eps0[q], nkx[j], nky[j], ne[j]);
+                    cum[j][5] = run;
+                    smax = run > smax ? run : smax;
+                }
             }
             smax = group_max<T>(smax, G);
             const T Gt = c.alpha1 * smax;
@@ -609,28 +628,18 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
             T sop, cop;
             dsincospi((T)2 * u1, &sop, &cop);    // OP angle 2 pi u1
 
-            T px_new[PMAX], py_new[PMAX];
-#pragma unroll
-            for (int h = 0; h < PMAX; ++h) { px_new[h] = (T)0; py_new[h] = (T)0; }
             uint32_t nev = 0, nrej = 0, nexh = 0;
-            for (int q = g; q < Q; q += G) {
-                T kx, ky;
-                eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
-                const T e0 = L.eps0[q];
-                const T e = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
-                T r[5];
-                phonon_rates<T>(c, e, e0, r);
-                int ell = 7;
-                T cum = (T)0;
 #pragma unroll
-                for (int m = 0; m < 5; ++m) {
-                    cum += r[m];
-                    if (ell == 7 && su < cum / Gt) ell = m + 1;
-                }
-                if (ell == 7) {
-                    cum += edge_rate<T>(c, L.ecos, L.cedge[q], e0, kx, ky, e);
-                    if (su < cum / Gt) ell = 6;
-                }
+            for (int j = 0; j < NPL; ++j) {
+                const int q = g + j * G;
+                if (q >= Q) continue;
+                const T kx = nkx[j], ky = nky[j], e = ne[j];
+                const T e0 = L.eps0[q];
+                // mechanism l: the first with s < G^l_q / Gamma~, else self (7)
+                int ell = 7;
+#pragma unroll
+                for (int m = 5; m >= 0; --m)
+                    if (su < cum[j][m] / Gt) ell = m + 1;
                 T nx = kx, ny = ky;
                 if (ell != 7) {
                     const T kabs = sqrt(kx * kx + ky * ky);
@@ -642,8 +651,8 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
                         // absolute final angle, density exp(-kap (cos t' - cos t_in)^2)
                         const T kap = c.edge_kap * (kx * kx + ky * ky);
                         ok = false;
-                        for (uint32_t j = 0; j < (uint32_t)kEdgeTries; ++j) {
-                            const Words we = philox10(ctr0, step, (coll << 8) | (kPurEdge0 + j),
+                        for (uint32_t jt = 0; jt < (uint32_t)kEdgeTries; ++jt) {
+                            const Words we = philox10(ctr0, step, (coll << 8) | (kPurEdge0 + jt),
                                                       a.instance, a.seed_lo, a.seed_hi);
                             const T ut = uni<T>(we.w0, we.w1), v = uni<T>(we.w2, we.w3);
                             T st, ct;
@@ -681,19 +690,32 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
                         if (f < eta) { nx = px; ny = py; } else { ++nrej; }
                     }
                 }
-                const T* wp = L.wpsi + q * PMAX;
-#pragma unroll
-                for (int h = 0; h < PMAX; ++h) { px_new[h] += wp[h] * nx; py_new[h] += wp[h] * ny; }
+                nodes[q] = nx;
+                nodes[Q + q] = ny;
             }
             if (nev) atomicAdd(&L.cnt[SGPM_CNT_EVENTS], nev);
             if (nrej) atomicAdd(&L.cnt[SGPM_CNT_PAULI_REJ], nrej);
             if (nexh) atomicAdd(&L.cnt[SGPM_CNT_EDGE_EXH], nexh);
-            // k_h = sum_q w_q Psi_h(z_q) k_q  (group sum over the nodes)
+            // k_h = sum_q w_q Psi_h(z_q) k_q, summed over q in order by lane h,
+            // then read back by every lane of the group
+            wave_lds_fence();
+            for (int h = g; h < P; h += G) {
+                T sx = (T)0, sy = (T)0;
+                for (int q = 0; q < Q; ++q) {
+                    const T w = L.wpsi[q * PMAX + h];
+                    sx += w * nodes[q];
+                    sy += w * nodes[Q + q];
+                }
+                modes[h] = sx;
+                modes[PMAX + h] = sy;
+            }
+            wave_lds_fence();
 #pragma unroll
             for (int h = 0; h < PMAX; ++h) {
-                cx[h] = group_sum<T>(px_new[h], G);
-                cy[h] = group_sum<T>(py_new[h], G);
+                cx[h] = h < P ? modes[h] : (T)0;
+                cy[h] = h < P ? modes[PMAX + h] : (T)0;
             }
+            wave_lds_fence();
             tc += dtc;
             ++coll;
             if (coll >= (uint32_t)c.c_max) {
@@ -708,47 +730,26 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
                 a.ky[(size_t)h * a.n + i] = cy[h];
             }
     }
-    // every lane is past the last claim: the counters are complete
+    // every lane is past its last candidate: the counters are complete
+    __syncthreads();
     if (tid < 8 && L.cnt[tid]) atomicAdd(&a.counters[tid], (unsigned long long)L.cnt[tid]);
     __syncthreads();
 }
 
-// Persistent collider grid of a group: workgroup b starts with the instance
-// whose share of the grid holds b and then visits the others in turn, so the
-// large lists are shared out first.  The last workgroup to finish advances the
-// step of every instance of the group.
-template <typename T, int PMAX>
-__global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T>* __restrict__ all,
-                                                     const uint32_t* __restrict__ wg0, int n_inst,
-                                                     uint32_t* done) {
+// Collider grid of a group: every workgroup visits every instance with work
+// for it and takes its static share of that instance's candidates.  Thread 0
+// of workgroup 0 advances the finalize kernel's copy of the step (that kernel
+// is done).
+template <typename T, int PMAX, int NPL>
+__global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T>* __restrict__ all, int n_inst) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __shared__ uint32_t s_total;
-    const int tid = threadIdx.x;
-    const int first = find_slot(wg0, n_inst, blockIdx.x);
-    for (int t = 0; t < n_inst; ++t) {
-        const int j = first + t < n_inst ? first + t : first + t - n_inst;
+    for (int j = 0; j < n_inst; ++j) {
         const K2Args<T> a = load_desc(all, j);
-        const uint32_t step = a.dyn->step;
-        if (tid == 0) {
-            const uint32_t* qc = a.qc + 2 * (step & 1u);
-            const uint32_t total = __hip_atomic_load(qc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t head = __hip_atomic_load(qc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_total = head < total ? total : 0u;
-        }
-        __syncthreads();
-        const uint32_t total = s_total;
-        __syncthreads();
-        if (total) k2_instance<T, PMAX>(a, smem, step, total);
-    }
-    // No fence: a workgroup has used its reads of the step before it counts
-    // itself done, and the kernel boundary publishes the new step to the
-    // next launch (a device-scope fence here would write back the L2 of the
-    // XCD once per workgroup).
-    if (tid == 0) {
-        if (atomicAdd(done, 1u) == gridDim.x - 1) {
-            for (int j = 0; j < n_inst; ++j) all[j].dyn->step += 1u;
-            atomicExch(done, 0u);
-        }
+        const uint32_t step = a.dyn->step_k2;
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.dyn->step_k3 = step + 1u;
+        const uint32_t total = a.qc[2 * (step & 1u)];
+        if (blockIdx.x * (uint32_t)(kBlock / a.G) < total)
+            k2_instance<T, PMAX, NPL>(a, smem, step, total);
     }
 }
 
@@ -759,11 +760,14 @@ __global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T>* __restrict
 // workgroup zeroes the overflow cells it read and contributes its maximum;
 // workgroup (q + Q b) also reduces moment batch b of node q.
 __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__ all,
-                                                      const uint32_t* __restrict__ wg0, int n_inst) {
+                                                      const uint32_t* __restrict__ wg0, int n_inst,
+                                                      int moving) {
     const int slot = find_slot(wg0, n_inst, blockIdx.x);
     const K3Args a = load_desc(all, slot);
     const int wg = (int)(blockIdx.x - wg0[slot]);
-    const uint32_t step = a.dyn->step;
+    const uint32_t step = a.dyn->step_k3;
+    // the stream kernel of this step is done with its copy of n
+    if (moving && wg == 0 && threadIdx.x == 0) a.dyn->step_k1 = step + 1u;
     const int nwg = a.nwg, nb = a.nb;
     const double* partial = a.partial;
     double* record = a.record + (size_t)(step - a.dyn->rec_base) * nb * a.Q * 3;
@@ -892,27 +896,33 @@ int launch_k1(int fp32, int pmax, int qmax, const void* args, const uint32_t* wg
     return launch_k1_any<double>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream);
 }
 
-template <typename T>
-static int launch_k2_any(int pmax, const void* args, const uint32_t* wg0, int n_inst,
-                         uint32_t* done, unsigned grid, size_t lds, void* stream) {
-    const K2Args<T>* a = static_cast<const K2Args<T>*>(args);
+template <typename T, int NPL>
+static int launch_k2_n(int pmax, const K2Args<T>* a, int n_inst, unsigned grid, size_t lds,
+                       hipStream_t s) {
     const dim3 g(grid), blk(kBlock);
-    const hipStream_t s = (hipStream_t)stream;
     switch (pmax) {
-    case 1: hipLaunchKernelGGL((k2_collide<T, 1>), g, blk, lds, s, a, wg0, n_inst, done); break;
-    case 3: hipLaunchKernelGGL((k2_collide<T, 3>), g, blk, lds, s, a, wg0, n_inst, done); break;
-    case 6: hipLaunchKernelGGL((k2_collide<T, 6>), g, blk, lds, s, a, wg0, n_inst, done); break;
-    case 9: hipLaunchKernelGGL((k2_collide<T, 9>), g, blk, lds, s, a, wg0, n_inst, done); break;
-    case 16: hipLaunchKernelGGL((k2_collide<T, 16>), g, blk, lds, s, a, wg0, n_inst, done); break;
-    default: hipLaunchKernelGGL((k2_collide<T, 32>), g, blk, lds, s, a, wg0, n_inst, done); break;
+    case 1: hipLaunchKernelGGL((k2_collide<T, 1, NPL>), g, blk, lds, s, a, n_inst); break;
+    case 3: hipLaunchKernelGGL((k2_collide<T, 3, NPL>), g, blk, lds, s, a, n_inst); break;
+    case 6: hipLaunchKernelGGL((k2_collide<T, 6, NPL>), g, blk, lds, s, a, n_inst); break;
+    case 9: hipLaunchKernelGGL((k2_collide<T, 9, NPL>), g, blk, lds, s, a, n_inst); break;
+    case 16: hipLaunchKernelGGL((k2_collide<T, 16, NPL>), g, blk, lds, s, a, n_inst); break;
+    default: hipLaunchKernelGGL((k2_collide<T, 32, NPL>), g, blk, lds, s, a, n_inst); break;
     }
     return (int)hipGetLastError();
 }
 
-int launch_k2(int fp32, int pmax, const void* args, const uint32_t* wg0, int n_inst,
-              uint32_t* done, unsigned grid, size_t lds, void* stream) {
-    if (fp32) return launch_k2_any<float>(pmax, args, wg0, n_inst, done, grid, lds, stream);
-    return launch_k2_any<double>(pmax, args, wg0, n_inst, done, grid, lds, stream);
+// npl: nodes per lane, 2 when some instance of the group has more than 64 nodes
+int launch_k2(int fp32, int pmax, int npl, const void* args, int n_inst, unsigned grid,
+              size_t lds, void* stream) {
+    const hipStream_t s = (hipStream_t)stream;
+    if (fp32) {
+        const K2Args<float>* a = static_cast<const K2Args<float>*>(args);
+        return npl > 1 ? launch_k2_n<float, 2>(pmax, a, n_inst, grid, lds, s)
+                       : launch_k2_n<float, 1>(pmax, a, n_inst, grid, lds, s);
+    }
+    const K2Args<double>* a = static_cast<const K2Args<double>*>(args);
+    return npl > 1 ? launch_k2_n<double, 2>(pmax, a, n_inst, grid, lds, s)
+                   : launch_k2_n<double, 1>(pmax, a, n_inst, grid, lds, s);
 }
 
 // finalize workgroups of one instance: the window part, the rest of the
@@ -924,9 +934,10 @@ int k3_grid_of(int Q, int nk, int n_win_wg, int nb) {
     return (int)grid;
 }
 
-int launch_k3(const K3Args* args, const uint32_t* wg0, int n_inst, unsigned grid, void* stream) {
+int launch_k3(const K3Args* args, const uint32_t* wg0, int n_inst, int moving, unsigned grid,
+              void* stream) {
     hipLaunchKernelGGL(k3_finalize, dim3(grid), dim3(kBlock), 0, (hipStream_t)stream, args, wg0,
-                       n_inst);
+                       n_inst, moving);
     return (int)hipGetLastError();
 }
 
@@ -936,7 +947,10 @@ __global__ void set_dyn_kernel(Dyn* d, int n, int set_step, uint32_t step, uint3
                                int set_dt, double dt) {
     const int k = (int)threadIdx.x;
     if (k >= n) return;
-    if (set_step) { d[k].step = step; d[k].rec_base = rec_base; }
+    if (set_step) {
+        d[k].step_k1 = step; d[k].step_k3 = step; d[k].step_k2 = step - 1u;
+        d[k].rec_base = rec_base;
+    }
     if (set_dt) { d[k].dt = dt; d[k].vfdt = d[k].v_f * dt; }
 }
 
