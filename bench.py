@@ -67,9 +67,10 @@ def kernel_bytes(cfg: dict, P: int, Q: int, n_drift: int, cand: float) -> dict:
             "collide": cand * 4 * P * s}
 
 
-def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True):
-    """Warm-up, K timed steps in the default launch mode, then K profiled
-    steps.  cfgs: one workload or a list (batched instances)."""
+def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True, tune: bool = True):
+    """Autotuned launch shape (from the initial datum, put back afterwards),
+    warm-up, K timed steps in the default launch mode, then K profiled steps.
+    cfgs: one workload or a list (batched instances)."""
     import numpy as np
     import torch
     import paper_2404_19602_amd as sg
@@ -78,6 +79,8 @@ def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True):
     sim = sg.Simulation(cfgs, max_steps=warmup + 2 * steps)
     sim.init_particles()
     dt = (cfgs[0] if many else cfgs)["dt"]
+    tuned_ms = sim.autotune(trial_steps=10, dt=dt) if tune else None
+    shape = sim.launch_shape(0)
     if warmup:
         sim.step(warmup, dt)
     c0 = [sim.counters(j) for j in range(sim.n_inst)]
@@ -88,7 +91,7 @@ def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True):
     wall = time.perf_counter() - t0
     dev_ms = sim.last_step_ms()
     c1 = [sim.counters(j) for j in range(sim.n_inst)]
-    out = dict(sim=sim, wall=wall, dev_ms=dev_ms,
+    out = dict(sim=sim, wall=wall, dev_ms=dev_ms, shape=shape, tuned_ms=tuned_ms,
                cand=[(b["candidates"] - a["candidates"]) / steps for a, b in zip(c0, c1)])
     if not many:
         out["moments"] = sim.moments(0, warmup + steps + 1)
@@ -214,7 +217,8 @@ def main():
         "config": {"workload": WORKLOAD, "n_particles": N, "gpc_modes": P, "nodes": Q,
                    "grid": cfg["nk"], "dt_fs": cfg["dt"] * 1e15, "field_V_per_m": cfg["field0"],
                    "gap_eV": cfg["gap0"], "gap_rel": cfg["gap_rel"], "state": "fp64",
-                   "launch": "hip graphs of 16 steps"},
+                   "launch": "hip graphs of 16 steps", "chunk": r64["shape"]["chunk"],
+                   "collider_workgroups": r64["shape"]["collider_workgroups"]},
         "roofline": roof,
         "kernels": per,
         "device_ms_per_step": r64["dev_ms"],
@@ -253,6 +257,8 @@ def main():
             "instances": len(cfgs), "n_particles": sum(c["n_particles"] for c in cfgs),
             "value": pn_b / rb["wall"], "unit": "particle-node updates/s",
             "ms_per_step": rb["wall"] * 1e3 / nb, "steps": nb, "dtype": "f32",
+            "launch_shape_inst0": rb["shape"],
+            "candidates_per_step": sum(rb["cand"]),
             "kernels": {k: {"avg_ms": ms, "launches": n} for k, (ms, n) in rb["kernels"].items()},
         }
         del rb

@@ -237,6 +237,26 @@ sgpm_status sgpm_tables(const sgpm_ctx* ctx, int32_t inst, double* z, double* w,
  * init/set_state (the current time is re-recorded). */
 sgpm_status sgpm_set_chunk(sgpm_ctx* ctx, int32_t inst, int32_t chunk);
 
+/* Autotuner of the launch shape.  From the current state of every instance
+ * it runs trial_steps steps of length dt_s (launched kernel by kernel, timed
+ * with HIP events on the context's stream) for each candidate shape: every
+ * instance's chunk scaled by 1/4, 1/2, 1, 2 or 4 from the automatic one
+ * (within the limits of sgpm_set_chunk), times 512, 1024 or 2048 collider
+ * workgroups.  Between trials and at the end it puts back the particle
+ * state, the step counter and the counters; the histogram is rebuilt and the
+ * moment record restarts at the current time, as after sgpm_set_state.
+ * Keeps the fastest shape (results do not depend on it; see sgpm_set_chunk)
+ * and returns its device time per step in *best_ms_per_step (may be NULL).
+ * Needs trial_steps <= max_steps of every instance (1 <= trial_steps <=
+ * 1000).  Synchronises the stream; host copies of the state are made. */
+sgpm_status sgpm_autotune(sgpm_ctx* ctx, double dt_s, int32_t trial_steps,
+                          double* best_ms_per_step);
+
+/* Current launch shape: chunk and stream workgroups of instance inst, and
+ * the collider's workgroups per launch (any pointer may be NULL). */
+sgpm_status sgpm_launch_shape(const sgpm_ctx* ctx, int32_t inst, int32_t* chunk,
+                              int32_t* stream_workgroups, int32_t* collider_workgroups);
+
 /* Device time (ms) of the last sgpm_step call divided by its step count,
  * measured with HIP events on the context's stream around all of its work
  * (the steps and the closing pass over the final state); 0 if none. */

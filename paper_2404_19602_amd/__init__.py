@@ -104,6 +104,21 @@ class Simulation:
     def set_profiling(self, on: bool):
         check(lib().sgpm_set_profiling(self._ctx, 1 if on else 0), self._ctx, "set_profiling")
 
+    def autotune(self, trial_steps: int = 20, dt: float | None = None) -> float:
+        """Pick the fastest launch shape (chunk scale and collider workgroups)
+        from timed trials; the state is put back.  Returns ms per step."""
+        dt = self.cfgs[0].get("dt", 2e-15) if dt is None else dt
+        ms = C.c_double(0)
+        check(lib().sgpm_autotune(self._ctx, C.c_double(dt), trial_steps, C.byref(ms)), self._ctx,
+              "autotune")
+        return ms.value
+
+    def launch_shape(self, inst: int = 0) -> dict:
+        ch = C.c_int32(); nw = C.c_int32(); g2 = C.c_int32()
+        check(lib().sgpm_launch_shape(self._ctx, inst, C.byref(ch), C.byref(nw), C.byref(g2)),
+              self._ctx, "launch_shape")
+        return {"chunk": ch.value, "stream_workgroups": nw.value, "collider_workgroups": g2.value}
+
     def kernel_times(self) -> dict:
         """Mean device time (ms) and launch count of each step kernel over the
         last profiled step call."""

@@ -67,6 +67,8 @@ def lib():
             "sgpm_set_graph": (i32, [vp, i32]),
             "sgpm_set_profiling": (i32, [vp, i32]),
             "sgpm_kernel_times": (i32, [vp, vp, vp]),
+            "sgpm_autotune": (i32, [vp, dbl, i32, C.POINTER(dbl)]),
+            "sgpm_launch_shape": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
             "sgpm_destroy": (None, [vp]),
             "sgpm_last_error": (C.c_char_p, [vp]),
             "sgpm_status_string": (C.c_char_p, [i32]),

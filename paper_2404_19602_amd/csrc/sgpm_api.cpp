@@ -193,10 +193,10 @@ Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
     L.add(64);                                         // 33 (spare)
     L.add(hstride * 4);                                // 34 overflow grid
     {
+        // the smallest chunk has both the most workgroups and the largest window
         int w, r0, l0, words;
-        window_for(t.P, t.Q, d.nk, d.precision == SGPM_FP32, (int)auto_chunk(d.n_particles), &w,
-                   &r0, &l0, &words);
         const int64_t mc = min_chunk(d.n_particles);
+        window_for(t.P, t.Q, d.nk, d.precision == SGPM_FP32, (int)mc, &w, &r0, &l0, &words);
         const size_t nwg_slab = (size_t)((d.n_particles + mc - 1) / mc);
         L.add(nwg_slab * (size_t)words * 4);          // 35 slabs
     }
@@ -235,6 +235,7 @@ struct sgpm_ctx {
     std::vector<uint32_t> h_wg;
     // graphs of a block of steps, by block length
     int graph_steps = kDefaultGraphSteps;
+    int k2_grid = kK2Grid;         // collider workgroups per launch
     std::vector<std::pair<int, hipGraphExec_t>> graphs;
     bool profiling = false;
     Prof prof;
@@ -485,7 +486,8 @@ sgpm_status enqueue_step(sgpm_ctx* c, hipStream_t s, bool prof) {
         e = launch_k3(c->k3 + G.pos0, wg_table(c, kTabK3, off), m, 1, G.k3_grid, s);
         if (e) return dev_fail(c, (hipError_t)e, "finalize kernel launch");
         if (prof) { sgpm_status r = prof_mark(c, s, SGPM_KERNEL_FINALIZE); if (r) return r; }
-        e = launch_k2(G.fp32, G.pmax, G.npl, k2_args(c, G.fp32, G.pos0), m, kK2Grid, G.k2_lds, s);
+        e = launch_k2(G.fp32, G.pmax, G.npl, k2_args(c, G.fp32, G.pos0), m, (unsigned)c->k2_grid,
+                      G.k2_lds, s);
         if (e) return dev_fail(c, (hipError_t)e, "collider launch");
         if (prof) { sgpm_status r = prof_mark(c, s, SGPM_KERNEL_COLLIDE); if (r) return r; }
     }
@@ -541,10 +543,13 @@ sgpm_status graph_for(sgpm_ctx* c, int steps, hipGraphExec_t* out) {
     return SGPM_OK;
 }
 
+// launch shape of the stream kernel: chunk, workgroups, batches and the LDS
+// window that fits beside the chunk's candidate list
 void set_chunk(Instance& I, int64_t chunk) {
     I.chunk = chunk > 0 ? chunk : auto_chunk(I.n);
     I.nwg = (int)((I.n + I.chunk - 1) / I.chunk);
     I.nb = I.nwg < kNumBatches ? I.nwg : kNumBatches;
+    window_for(I.P, I.Q, I.nk, I.fp32, (int)I.chunk, &I.win, &I.win_r0, &I.win_l0, &I.hwin_words);
 }
 
 // histogram, its maximum and record index 0 for the current state
@@ -559,6 +564,46 @@ sgpm_status rebuild(sgpm_ctx* c, Instance& I) {
                            c->stream);
     if (e) return dev_fail(c, (hipError_t)e, "step state launch");
     return state_pass_one(c, I);
+}
+
+// Raw copy of an instance's state, step and counters (autotuner trials).
+struct Saved {
+    std::vector<unsigned char> state;
+    int64_t step = 0;
+    unsigned long long counters[SGPM_N_COUNTERS];
+};
+
+sgpm_status save_instance(sgpm_ctx* c, Instance& I, Saved& S) {
+    const size_t b = (size_t)I.P * I.n * (I.fp32 ? 4 : 8);
+    try { S.state.resize(2 * b); } catch (...) { return fail(c, SGPM_ENOMEM, "host copy of the state"); }
+    HIPCHK(c, hipMemcpyAsync(S.state.data(), I.kx, b, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(S.state.data() + b, I.ky, b, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(S.counters, I.counters, sizeof(S.counters), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    S.step = I.step;
+    return SGPM_OK;
+}
+
+// the saved state back in place, its histogram and time rebuilt (the record
+// restarts there, as after sgpm_set_state), the counters as they were
+sgpm_status restore_instance(sgpm_ctx* c, Instance& I, const Saved& S) {
+    const size_t b = S.state.size() / 2;
+    HIPCHK(c, hipMemcpyAsync(I.kx, S.state.data(), b, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(I.ky, S.state.data() + b, b, hipMemcpyHostToDevice, c->stream));
+    I.step = S.step;
+    sgpm_status st = rebuild(c, I);
+    if (st) return st;
+    HIPCHK(c, hipMemcpyAsync(I.counters, S.counters, sizeof(S.counters), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SGPM_OK;
+}
+
+int64_t scaled_chunk(const Instance& I, double f) {
+    int64_t ch = (int64_t)std::llround(auto_chunk(I.n) * f / kBlock1) * kBlock1;
+    ch = std::max<int64_t>(ch, min_chunk(I.n));
+    return std::min<int64_t>(ch, kMaxChunk);
 }
 
 }  // namespace
@@ -702,8 +747,6 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         I.slabs = (uint32_t*)at(35);
         base += L.total;
         set_chunk(I, 0);
-        window_for(I.P, I.Q, I.nk, I.fp32, (int)I.chunk, &I.win, &I.win_r0, &I.win_l0,
-                   &I.hwin_words);
         std::memset(&dyn0[I.pos], 0, sizeof(Dyn));
         dyn0[I.pos].v_f = t.v_f;
 
@@ -864,6 +907,74 @@ sgpm_status sgpm_kernel_times(sgpm_ctx* c, double* avg_ms, int64_t* launches) {
         avg_ms[k] = cnt[k] ? tot[k] / (double)cnt[k] : 0.0;
         if (launches) launches[k] = cnt[k];
     }
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_autotune(sgpm_ctx* c, double dt, int32_t trial_steps, double* best_ms) {
+    if (!c) return SGPM_EINVAL;
+    if (c->poisoned) return fail(c, SGPM_ESTATE, "context poisoned");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(c, SGPM_EINVAL, "dt must be positive and finite");
+    if (trial_steps < 1 || trial_steps > 1000) return fail(c, SGPM_EINVAL, "trial_steps in [1, 1000]");
+    for (Instance& I : c->inst) {
+        if (!I.initialised) return fail(c, SGPM_ESTATE, "call sgpm_init_particles or sgpm_set_state first");
+        if (trial_steps > I.d.max_steps)
+            return fail(c, SGPM_EINVAL, "trial_steps exceeds the moment record capacity (max_steps)");
+        if (I.step + trial_steps >= (int64_t)0xFFFFFFFFll)
+            return fail(c, SGPM_EINVAL, "step counter would reach the initialisation stream");
+    }
+    std::vector<Saved> saved(c->inst.size());
+    for (size_t k = 0; k < c->inst.size(); ++k) {
+        sgpm_status s = save_instance(c, c->inst[k], saved[k]);
+        if (s) return s;
+    }
+    const bool prof = c->profiling;
+    c->profiling = false;
+    const int graph_steps = c->graph_steps;
+    c->graph_steps = 0;
+    static const double kFactors[] = {0.25, 0.5, 1.0, 2.0, 4.0};
+    static const int kGrids[] = {512, 1024, 2048};
+    double best = 1e300, best_f = 1.0;
+    int best_g = c->k2_grid;
+    std::vector<std::vector<int64_t>> tried;
+    sgpm_status st = SGPM_OK;
+    for (double f : kFactors) {
+        std::vector<int64_t> shape;
+        for (Instance& I : c->inst) shape.push_back(scaled_chunk(I, f));
+        if (std::find(tried.begin(), tried.end(), shape) != tried.end()) continue;
+        tried.push_back(shape);
+        for (int g : kGrids) {
+            for (size_t k = 0; k < c->inst.size(); ++k) set_chunk(c->inst[k], shape[k]);
+            c->k2_grid = g;
+            st = upload_args(c);
+            for (size_t k = 0; k < c->inst.size() && !st; ++k)
+                st = restore_instance(c, c->inst[k], saved[k]);
+            if (!st) st = sgpm_step(c, dt, trial_steps);
+            double ms = 0.0;
+            if (!st) st = sgpm_last_step_ms(c, &ms);
+            if (st) break;
+            if (ms < best) { best = ms; best_f = f; best_g = g; }
+        }
+        if (st) break;
+    }
+    c->profiling = prof;
+    c->graph_steps = graph_steps;
+    if (st) return st;
+    for (Instance& I : c->inst) set_chunk(I, scaled_chunk(I, best_f));
+    c->k2_grid = best_g;
+    st = upload_args(c);
+    for (size_t k = 0; k < c->inst.size() && !st; ++k) st = restore_instance(c, c->inst[k], saved[k]);
+    if (st) return st;
+    if (best_ms) *best_ms = best;
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_launch_shape(const sgpm_ctx* c, int32_t inst, int32_t* chunk,
+                              int32_t* stream_workgroups, int32_t* collider_workgroups) {
+    if (!c || inst < 0 || inst >= (int32_t)c->inst.size()) return SGPM_EINVAL;
+    const Instance& I = c->inst[inst];
+    if (chunk) *chunk = (int32_t)I.chunk;
+    if (stream_workgroups) *stream_workgroups = I.nwg;
+    if (collider_workgroups) *collider_workgroups = c->k2_grid;
     return SGPM_OK;
 }
 

@@ -533,16 +533,16 @@ __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-// The candidates of one instance: workgroup b of the grid takes the passes
-// b, b + grid, ... of kBlock / G candidates each (the list is complete when
-// the kernel starts, so a static share needs no work counter); total: the
-// list's length, nonzero and uniform, with at least one pass for b.  A group of G
+// The candidates of one instance in passes of kBlock / G candidates: this
+// workgroup takes the passes first, first + stride, ... below the instance's
+// pass count (the list is complete when the kernel starts, so a static share
+// needs no work counter); total: the list's length.  A group of G
 // lanes serves one candidate, lane g holding nodes g and g + G (NPL = 2 only
 // when Q > 64).  Per collision every node's rates are evaluated once: their
 // running sums give both Gamma~ (eq. gamma_tot) and the mechanism selection.
 template <typename T, int PMAX, int NPL>
 __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* smem, uint32_t step,
-                                            uint32_t total) {
+                                            uint32_t total, uint32_t first, uint32_t stride) {
     const int P = a.P, Q = a.Q, G = a.G;
     const K2Lds<T> L = k2_lds<T>(smem, PMAX, Q, kBlock / G);
     const int tid = threadIdx.x;
@@ -573,7 +573,7 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
     T* nodes = L.scratch + (size_t)grp * (2 * Q + 2 * PMAX);   // [2][Q] new node values
     T* modes = nodes + 2 * Q;                                   // [2][PMAX] new coefficients
 
-    for (uint32_t p0 = blockIdx.x * per_pass; p0 < total; p0 += gridDim.x * per_pass) {
+    for (uint32_t p0 = first * per_pass; p0 < total; p0 += stride * per_pass) {
         const uint32_t cid = p0 + grp;
         if (cid >= total) continue;
         const int64_t i = a.cand[cid];
@@ -736,20 +736,30 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
     __syncthreads();
 }
 
-// Collider grid of a group: every workgroup visits every instance with work
-// for it and takes its static share of that instance's candidates.  Thread 0
-// of workgroup 0 advances the finalize kernel's copy of the step (that kernel
-// is done).
+// Collider grid of a group.  The passes of all instances, concatenated in
+// instance order, are dealt out round-robin: workgroup b takes global passes
+// b, b + grid, ..., so a group of many small lists spreads like one long
+// list.  Thread 0 of workgroup 0 advances the finalize kernel's copy of the
+// step of every instance (that kernel is done).
 template <typename T, int PMAX, int NPL>
 __global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T>* __restrict__ all, int n_inst) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const uint32_t grid = gridDim.x;
+    uint32_t base = 0;            // global index of instance j's first pass
+    uint32_t next = blockIdx.x;   // this workgroup's next global pass
     for (int j = 0; j < n_inst; ++j) {
         const K2Args<T> a = load_desc(all, j);
         const uint32_t step = a.dyn->step_k2;
         if (blockIdx.x == 0 && threadIdx.x == 0) a.dyn->step_k3 = step + 1u;
         const uint32_t total = a.qc[2 * (step & 1u)];
-        if (blockIdx.x * (uint32_t)(kBlock / a.G) < total)
-            k2_instance<T, PMAX, NPL>(a, smem, step, total);
+        const uint32_t per_pass = (uint32_t)(kBlock / a.G);
+        const uint32_t passes = (total + per_pass - 1) / per_pass;
+        if (next < base + passes) {
+            const uint32_t first = next - base;
+            k2_instance<T, PMAX, NPL>(a, smem, step, total, first, grid);
+            next += (passes - first + grid - 1) / grid * grid;
+        }
+        base += passes;
     }
 }
 

@@ -154,3 +154,39 @@ def test_sweep_of_64_instances(sg):
         alone.init_particles()
         alone.step(20)
         assert_same(snapshot(batch, j), snapshot(alone), f"instance {j}")
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_autotune_keeps_the_run(sg, batched):
+    """The autotuner's trials leave state, step and counters as they were, and
+    the run continued in the chosen shape matches an untuned run exactly."""
+    cfgs = mixed_instances()[:3] if batched else cfg_of(n_particles=40_000)
+    print(f"\n[gpu case] autotune batched={batched}", flush=True)
+    tuned = sg.Simulation(cfgs)
+    plain = sg.Simulation(cfgs)
+    for s in (tuned, plain):
+        s.init_particles()
+        s.step(5)
+    n = tuned.n_inst
+    before = [snapshot(tuned, j) for j in range(n)]
+    ms = tuned.autotune(trial_steps=4)
+    assert ms > 0
+    assert tuned.step_count == 5
+    for j in range(n):
+        after = snapshot(tuned, j)
+        for k in ("kx", "ky", "H", "M", "cnt"):
+            if isinstance(after[k], dict):
+                assert after[k] == before[j][k], (j, k)
+            else:
+                assert np.array_equal(after[k], before[j][k]), (j, k)
+        shape = tuned.launch_shape(j)
+        assert shape["chunk"] % 256 == 0 and shape["collider_workgroups"] in (512, 1024, 2048)
+    for s in (tuned, plain):
+        s.step(12)
+    for j in range(n):
+        a, b = snapshot(tuned, j), snapshot(plain, j)
+        for k in ("kx", "ky", "H", "M", "cnt"):
+            if isinstance(a[k], dict):
+                assert a[k] == b[k], (j, k)
+            else:
+                assert np.array_equal(a[k], b[k]), (j, k)
