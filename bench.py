@@ -68,9 +68,10 @@ def kernel_bytes(cfg: dict, P: int, Q: int, n_drift: int, cand: float) -> dict:
 
 
 def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True, tune: bool = True):
-    """Autotuned launch shape (from the initial datum, put back afterwards),
-    warm-up, K timed steps in the default launch mode, then K profiled steps.
-    cfgs: one workload or a list (batched instances)."""
+    """Warm-up, the autotuned launch shape (trials from the warmed-up state,
+    which is put back; the moment record restarts there), K timed steps in
+    the default launch mode, then K profiled steps.  cfgs: one workload or a
+    list (batched instances)."""
     import numpy as np
     import torch
     import paper_2404_19602_amd as sg
@@ -79,10 +80,10 @@ def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True, tune: bool = Tr
     sim = sg.Simulation(cfgs, max_steps=warmup + 2 * steps)
     sim.init_particles()
     dt = (cfgs[0] if many else cfgs)["dt"]
-    tuned_ms = sim.autotune(trial_steps=10, dt=dt) if tune else None
-    shape = sim.launch_shape(0)
     if warmup:
         sim.step(warmup, dt)
+    tuned_ms = sim.autotune(trial_steps=10, dt=dt) if tune else None
+    shape = sim.launch_shape(0)
     c0 = [sim.counters(j) for j in range(sim.n_inst)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -94,7 +95,7 @@ def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True, tune: bool = Tr
     out = dict(sim=sim, wall=wall, dev_ms=dev_ms, shape=shape, tuned_ms=tuned_ms,
                cand=[(b["candidates"] - a["candidates"]) / steps for a, b in zip(c0, c1)])
     if not many:
-        out["moments"] = sim.moments(0, warmup + steps + 1)
+        out["moments"] = sim.moments(0, steps + 1)
         t = sim.tables()
         out["n_drift"] = int(np.count_nonzero(t["ehat"]))
     if profile:

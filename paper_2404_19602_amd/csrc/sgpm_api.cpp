@@ -28,6 +28,7 @@ namespace {
 constexpr double kECharge = 1.602176634e-19;
 constexpr int kMaxBins = 4096;
 constexpr int kDefaultGraphSteps = 16;
+constexpr int kMaxLdsBudget = 72 * 1024;   // largest window budget the slabs are sized for
 constexpr int kMaxGraphSteps = 256;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -41,6 +42,7 @@ struct Instance {
     int64_t chunk = kBlock1;
     int nwg = 1, nb = 1;
     int win = 0, win_r0 = 0, win_l0 = 0, hwin_words = 0;
+    int lds_budget = kLdsK1Bytes;   // LDS bytes of a stream workgroup (sizes the window)
     int64_t hstride = 0;       // words per histogram buffer (padded)
     int64_t hmstride = 0;      // words per maximum buffer
     int64_t step = 0;          // global step counter (random streams)
@@ -145,11 +147,13 @@ int64_t min_chunk(int64_t n) {
 
 // LDS histogram window of the stream kernel: the largest even square of
 // packed 16-bit counters per node that fits the budget left by the tables,
-// centred on the grid.
-void window_for(int P, int Q, int nk, bool fp32, int chunk, int* win, int* r0, int* l0,
-                int* words) {
+// centred on the grid.  The window is kept large: the distribution widens as
+// the field heats it, and counts outside the window go through device
+// atomics, which are far slower than the slab traffic a wide window costs.
+void window_for(int P, int Q, int nk, bool fp32, int chunk, int budget, int* win, int* r0,
+                int* l0, int* words) {
     const size_t fixed = k1_lds_bytes(P, Q, fp32 ? 1 : 0, 0, chunk) + 64;
-    const double room = fixed < (size_t)kLdsK1Bytes ? (double)(kLdsK1Bytes - fixed) : 0.0;
+    const double room = fixed < (size_t)budget ? (double)(budget - fixed) : 0.0;
     int w = (int)std::floor(std::sqrt(room / (2.0 * Q)));
     w &= ~1;
     if (w > nk) w = nk & ~1;
@@ -196,7 +200,8 @@ Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
         // the smallest chunk has both the most workgroups and the largest window
         int w, r0, l0, words;
         const int64_t mc = min_chunk(d.n_particles);
-        window_for(t.P, t.Q, d.nk, d.precision == SGPM_FP32, (int)mc, &w, &r0, &l0, &words);
+        window_for(t.P, t.Q, d.nk, d.precision == SGPM_FP32, (int)mc, kMaxLdsBudget, &w, &r0, &l0,
+                   &words);
         const size_t nwg_slab = (size_t)((d.n_particles + mc - 1) / mc);
         L.add(nwg_slab * (size_t)words * 4);          // 35 slabs
     }
@@ -549,7 +554,8 @@ void set_chunk(Instance& I, int64_t chunk) {
     I.chunk = chunk > 0 ? chunk : auto_chunk(I.n);
     I.nwg = (int)((I.n + I.chunk - 1) / I.chunk);
     I.nb = I.nwg < kNumBatches ? I.nwg : kNumBatches;
-    window_for(I.P, I.Q, I.nk, I.fp32, (int)I.chunk, &I.win, &I.win_r0, &I.win_l0, &I.hwin_words);
+    window_for(I.P, I.Q, I.nk, I.fp32, (int)I.chunk, I.lds_budget, &I.win, &I.win_r0, &I.win_l0,
+               &I.hwin_words);
 }
 
 // histogram, its maximum and record index 0 for the current state

@@ -17,7 +17,7 @@ constexpr int kMaxQ = 128;           // largest node count
 constexpr int kEdgePts = 32;         // trapezoid points of the edge integral
 constexpr int kEdgeTries = 64;       // edge-angle proposals per collision
 constexpr int kNumBatches = 32;      // batch-means batches of the moment record
-constexpr int kLdsK1Bytes = 72 * 1024;   // LDS budget of a stream workgroup
+constexpr int kLdsK1Bytes = 72 * 1024;   // default LDS budget of a stream workgroup
 
 // Host FP64 set-up of one instance (Sec. 4.1 tables, Appendix rate constants).
 struct HostTables {

@@ -19,6 +19,8 @@
 //                 the stale buffer for the next step, and the fixed-order
 //                 reduction of the moment sums into the record.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 #include "sgpm_internal.h"
@@ -273,6 +275,26 @@ __device__ __forceinline__ void k1_bin(const K1Args<T>& a, const K1Lds<T>& L, co
     }
 }
 
+// Node value into H^n with the common case made cheap: when every active lane
+// of the wave falls inside the LDS window (compared in floating point, so a
+// NaN fails), one packed LDS increment each; otherwise the general path.
+template <typename T>
+__device__ __forceinline__ void k1_bin_fast(const K1Args<T>& a, const K1Lds<T>& L,
+                                            const Consts<T>& c, int q, T kx, T ky, bool act) {
+    const T fr = floor((kx + c.lk) * c.inv_dk) - (T)a.win_r0;
+    const T fl = floor((ky + c.lk) * c.inv_dk) - (T)a.win_l0;
+    const T w = (T)a.win;
+    const bool inwin = fr >= (T)0 && fr < w && fl >= (T)0 && fl < w;
+    if (__ballot(act && !inwin) == 0) {
+        if (act) {
+            const int idx = (q * a.win + (int)fr) * a.win + (int)fl;
+            atomicAdd(&L.hwin[idx >> 1], 1u << ((idx & 1) << 4));
+        }
+    } else if (act) {
+        k1_bin<T>(a, L, c, q, kx, ky);
+    }
+}
+
 // Is a collision possible in this step?  ub: upper bound of every nodal
 // energy after the drift.  No collision iff -log(xi) / G~ >= dt; with
 // G~ <= gb and -log(xi) >= 1 - xi the test needs the logarithm only when
@@ -304,7 +326,8 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
     const K1Lds<T> L = k1_lds<T>(smem, PMAX, Q, a.hwin_words, (int)a.chunk);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    for (int w = tid; w < a.hwin_words; w += kBlock1) L.hwin[w] = 0u;
+    for (int w = tid; w < (a.hwin_words >> 2); w += kBlock1)        // whole 16-byte rows
+        reinterpret_cast<uint4*>(L.hwin)[w] = make_uint4(0u, 0u, 0u, 0u);
     if (tid == 0) *L.c = *a.tab.consts;
     for (int k = tid; k < Q * PMAX; k += kBlock1) {
         const int q = k / PMAX, h = k - q * PMAX;
@@ -337,84 +360,110 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
     }
     const T zero[PMAX] = {};
 
-    for (int64_t base = begin; base < end; base += kBlock1) {
-        const int64_t i = base + tid;
-        const bool act = i < end;
+    // the tiles of this workgroup's chunk; FULL: every lane of every tile holds a
+    // particle (all chunks but the last), so the per-lane guards fold away
+    // The next tile's coefficients are loaded while this one is processed.
+    auto tiles = [&](auto full) {
+        constexpr bool FULL = decltype(full)::value;
         T cx[PMAX], cy[PMAX];
-        load_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, act ? i : begin, zero, cx, cy);
-        bool cand = false;
-        if constexpr (QMAX > 0) {
-            T e2max = (T)0;
-#pragma unroll
-            for (int q = 0; q < QMAX; ++q) {
-                if (q < Q && act) {
-                    T kx, ky;
-                    eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
-                    // state at t^n: histogram and moments (Sec. 4.2)
-                    const T e2 = kx * kx + ky * ky + L.eps0sq[q];
-                    const T rs = rsqrt_nr(e2);
-                    acc[q][0] += (double)(c.v_f * kx * rs);
-                    acc[q][1] += (double)(c.v_f * ky * rs);
-                    acc[q][2] += (double)(e2 * rs);
-                    k1_bin<T>(a, L, c, q, kx, ky);
-                    // after the drift, for the rate bound
-                    const T dx = kx - L.shift[q];
-                    const T d2 = dx * dx + ky * ky + L.eps0sq[q];
-                    e2max = d2 > e2max ? d2 : e2max;
-                }
-            }
-            // the nodal energies after the drift, bounded with a relative
-            // margin for the rounding of the shifted evaluation
-            if (act && moving) cand = k1_candidate<T>(a, c, i, sqrt(e2max) * c.b_margin, step, dt);
-        } else {
-            for (int q = 0; q < Q; ++q) {
-                double vx = 0.0, vy = 0.0, en = 0.0;
-                if (act) {
-                    T kx, ky;
-                    eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
-                    const T e2 = kx * kx + ky * ky + L.eps0sq[q];
-                    const T rs = rsqrt_nr(e2);
-                    vx = (double)(c.v_f * kx * rs);
-                    vy = (double)(c.v_f * ky * rs);
-                    en = (double)(e2 * rs);
-                    k1_bin<T>(a, L, c, q, kx, ky);
-                }
-                vx = wave_sum(vx); vy = wave_sum(vy); en = wave_sum(en);
-                if (lane == 0) {
-                    double* m = L.red + ((size_t)wave * Q + q) * 3;
-                    m[0] += vx; m[1] += vy; m[2] += en;
-                }
-            }
-            if (act && moving) {
-                // |k(z_q)| <= sum_h |k_h| max_q |Psi_h(z_q)| per component, after the drift
-                T bx = (T)0, by = (T)0;
-#pragma unroll
-                for (int h = 0; h < PMAX; ++h) {
-                    bx += fabs(cx[h] - L.drift[h]) * L.psimax[h];
-                    by += fabs(cy[h]) * L.psimax[h];
-                }
-                cand = k1_candidate<T>(a, c, i, sqrt(bx * bx + by * by + c.eps0max_sq), step, dt);
-            }
+        {
+            const int64_t i0 = begin + tid;
+            load_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, (FULL || i0 < end) ? i0 : begin, zero, cx, cy);
         }
-        if (act && moving && !cand) {
-            // the particle does not collide: its step is the drift alone
-#pragma unroll
-            for (int h = 0; h < PMAX; ++h)
-                if (h < P && L.drift[h] != (T)0) a.kx[(size_t)h * a.n + i] = cx[h] - L.drift[h];
-        }
-        // candidates of this workgroup collected in LDS
-        const uint64_t mask = __ballot(cand);
-        if (mask) {
-            uint32_t base_slot = 0;
-            if (lane == 0) base_slot = atomicAdd(&L.cnt[SGPM_CNT_CANDIDATES], (uint32_t)__popcll(mask));
-            base_slot = __shfl(base_slot, 0, 64);
-            if (cand) {
-                const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                L.cbuf[base_slot + pos] = (int)i;
+        for (int64_t base = begin; base < end; base += kBlock1) {
+            const int64_t i = base + tid;
+            const bool act = FULL || i < end;
+            T nx[PMAX], ny[PMAX];
+            if (base + kBlock1 < end) {
+                const int64_t in = i + kBlock1;
+                load_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, (FULL || in < end) ? in : begin, zero, nx, ny);
             }
+            bool cand = false;
+            if constexpr (QMAX > 0) {
+                // the nodes of one particle
+                auto nodes = [&]() -> T {
+                    const bool on = act;
+                    T e2max = (T)0;
+    #pragma unroll
+                    for (int q = 0; q < QMAX; ++q) {
+                        if (q < Q) {
+                            T kx, ky;
+                            eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
+                            // state at t^n: histogram and moments (Sec. 4.2)
+                            const T e2 = kx * kx + ky * ky + L.eps0sq[q];
+                            const T rs = rsqrt_nr(e2);
+                            if (on) {
+                                acc[q][0] += (double)(c.v_f * kx * rs);
+                                acc[q][1] += (double)(c.v_f * ky * rs);
+                                acc[q][2] += (double)(e2 * rs);
+                            }
+                            k1_bin_fast<T>(a, L, c, q, kx, ky, on);
+                            // after the drift, for the rate bound
+                            const T dx = kx - L.shift[q];
+                            const T d2 = dx * dx + ky * ky + L.eps0sq[q];
+                            e2max = d2 > e2max ? d2 : e2max;
+                        }
+                    }
+                    return e2max;
+                };
+                const T e2max = nodes();
+                // the nodal energies after the drift, bounded with a relative
+                // margin for the rounding of the shifted evaluation
+                if (act && moving) cand = k1_candidate<T>(a, c, i, sqrt(e2max) * c.b_margin, step, dt);
+            } else {
+                for (int q = 0; q < Q; ++q) {
+                    double vx = 0.0, vy = 0.0, en = 0.0;
+                    if (act) {
+                        T kx, ky;
+                        eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
+                        const T e2 = kx * kx + ky * ky + L.eps0sq[q];
+                        const T rs = rsqrt_nr(e2);
+                        vx = (double)(c.v_f * kx * rs);
+                        vy = (double)(c.v_f * ky * rs);
+                        en = (double)(e2 * rs);
+                        k1_bin<T>(a, L, c, q, kx, ky);
+                    }
+                    vx = wave_sum(vx); vy = wave_sum(vy); en = wave_sum(en);
+                    if (lane == 0) {
+                        double* m = L.red + ((size_t)wave * Q + q) * 3;
+                        m[0] += vx; m[1] += vy; m[2] += en;
+                    }
+                }
+                if (act && moving) {
+                    // |k(z_q)| <= sum_h |k_h| max_q |Psi_h(z_q)| per component, after the drift
+                    T bx = (T)0, by = (T)0;
+    #pragma unroll
+                    for (int h = 0; h < PMAX; ++h) {
+                        bx += fabs(cx[h] - L.drift[h]) * L.psimax[h];
+                        by += fabs(cy[h]) * L.psimax[h];
+                    }
+                    cand = k1_candidate<T>(a, c, i, sqrt(bx * bx + by * by + c.eps0max_sq), step, dt);
+                }
+            }
+            if (act && moving && !cand) {
+                // the particle does not collide: its step is the drift alone
+    #pragma unroll
+                for (int h = 0; h < PMAX; ++h)
+                    if (h < P && L.drift[h] != (T)0) a.kx[(size_t)h * a.n + i] = cx[h] - L.drift[h];
+            }
+            // candidates of this workgroup collected in LDS
+            const uint64_t mask = __ballot(cand);
+            if (mask) {
+                uint32_t base_slot = 0;
+                if (lane == 0) base_slot = atomicAdd(&L.cnt[SGPM_CNT_CANDIDATES], (uint32_t)__popcll(mask));
+                base_slot = __shfl(base_slot, 0, 64);
+                if (cand) {
+                    const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                    L.cbuf[base_slot + pos] = (int)i;
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < PMAX; ++h) { cx[h] = nx[h]; cy[h] = ny[h]; }
         }
-    }
+    };
+    if (end - begin == a.chunk) tiles(std::true_type{});
+    else tiles(std::false_type{});
     if constexpr (QMAX > 0) {
 #pragma unroll
         for (int q = 0; q < QMAX; ++q) {
