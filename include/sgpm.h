@@ -198,6 +198,17 @@ sgpm_status sgpm_moments(sgpm_ctx* ctx, int32_t inst, int64_t t_first, int64_t c
 sgpm_status sgpm_reconstruct_f(sgpm_ctx* ctx, int32_t inst, int32_t nbins, double emin_eV,
                                double emax_eV, double* nodes, double* modes);
 
+/* Moments of the particle expansion at points z (Sec. 4.2): every particle's
+ * wave-vector evaluated at z, k_i(z) = sum_h k_h Psi_h(z), on the band of
+ * that z.  z is [n_z][dim_z] (ignored for dim_z = 0); out is [n_z][4]:
+ * V_x, V_y (m/s), mean energy (eV) and J_x = -e n(z) V_x (A/m) with the
+ * Fermi-Dirac equilibrium density n(z) of that band.  Sums in FP64 in a
+ * fixed order.  The gap must be positive at every z.  Synchronises the
+ * stream.  Used for the quantities at z between the nodes: percentile bands
+ * over z, the L2(z) error of a truncation order. */
+sgpm_status sgpm_moments_at(sgpm_ctx* ctx, int32_t inst, int32_t n_z, const double* z,
+                            double* out);
+
 /* Energy distribution of the particles reconstructed at arbitrary points z
  * (k_i(z) = sum_h k_h Psi_h(z)); z[n_z][dim_z], out[n_z][nbins].  Positive
  * by construction.  Synchronises. */

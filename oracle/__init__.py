@@ -95,6 +95,9 @@ def lib():
         L.orc_edge_kappa_coef.restype = C.c_double
         L.orc_reconstruct_f.argtypes = [P, C.c_int, C.c_double, C.c_double, dp, dp]
         L.orc_reconstruct_f_at.argtypes = [P, dp, C.c_int, C.c_double, C.c_double, dp]
+        L.orc_moments_at.argtypes = [P, C.c_int, dp, dp]
+        L.orc_density_closed.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double]
+        L.orc_density_closed.restype = C.c_double
         L.orc_init_particles.argtypes = [P, lp, C.c_long, dp, dp]
         L.orc_pauli_lookup.argtypes = [P, C.c_int, C.c_double, C.c_double, C.c_double]
         L.orc_pauli_lookup.restype = C.c_double
@@ -152,6 +155,11 @@ def gauss_legendre(n: int):
 
 def legendre_orthonormal(k: int, x: float) -> float:
     return lib().orc_legendre_orthonormal(k, x)
+
+
+def density_closed(e0: float, mu: float, kT: float) -> float:
+    """Equilibrium electron density (1/m^2) of a band with minimum e0, closed form."""
+    return lib().orc_density_closed(e0, mu, kT, 6.62607015e-34 / (2 * np.pi))
 
 
 def edge_integral(kap: float, c: float) -> float:
@@ -302,6 +310,14 @@ class OracleSim:
         return out
 
     # ------------------------------------------------ quantities of interest
+    def moments_at(self, z) -> dict:
+        """V_x, V_y, mean energy, J_x of the particle expansion at points z."""
+        dz = int(self.cfg.get("dim_z", 0))
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.float64).reshape(-1, max(dz, 1)))
+        out = np.zeros((z.shape[0], 4))
+        lib().orc_moments_at(self._h, z.shape[0], _dp(z), _dp(out))
+        return {"V_x": out[:, 0], "V_y": out[:, 1], "energy": out[:, 2], "J_x": out[:, 3]}
+
     def qoi(self, rec=None) -> dict:
         """Expectation and variance over z (nodal quadrature) of V_x, J_x and
         the mean energy, for every recorded time (Sec. 4.2)."""

@@ -864,6 +864,80 @@ void orc_reconstruct_f_at(const orc_sim *s, const double *z, int nbins, double e
     for (int b = 0; b < nbins; ++b) out[b] /= ((double)N * width);
 }
 
+/* Dilogarithm Li2(w) for 0 <= w <= 1/2 by its power series sum w^k / k^2
+ * (terms shrink at least as 2^-k). */
+static double dilog_small(double w)
+{
+    double term = w, sum = 0.0;
+    for (int k = 1; k < 200 && term > 1e-20 * fabs(sum + 1e-300); ++k) {
+        sum += term / ((double)k * (double)k);
+        term *= w;
+    }
+    return sum;
+}
+
+/* Li2(-x) for x >= 0: Landen's identity Li2(-x) = -Li2(x/(1+x)) - ln^2(1+x)/2
+ * maps 0 <= x <= 1 onto the series range; the inversion formula
+ * Li2(-x) = -pi^2/6 - ln^2(x)/2 - Li2(-1/x) takes x > 1 there. */
+static double dilog_neg(double x)
+{
+    if (x <= 1.0) {
+        double l = log1p(x);
+        return -dilog_small(x / (1.0 + x)) - 0.5 * l * l;
+    }
+    double l = log(x);
+    return -PI_D * PI_D / 6.0 - 0.5 * l * l - dilog_neg(1.0 / x);
+}
+
+/* Equilibrium density of a band with minimum e0 (Sec. 3 eq. den with the
+ * Fermi-Dirac datum of Sec. 2), in closed form:
+ *   int_e0^inf eps / (1 + exp((eps - mu)/kT)) d eps
+ *     = kT e0 ln(1 + e^eta) - kT^2 Li2(-e^eta),   eta = (mu - e0)/kT,
+ * (integrate by parts; the Fermi-Dirac integral of order 1), then
+ *   n = (2/pi) (hbar v_F)^-2 times it. */
+double orc_density_closed(double e0, double mu, double kT, double hbar)
+{
+    double eta = (mu - e0) / kT;
+    double lg = eta > 30.0 ? eta + log1p(exp(-eta)) : log1p(exp(eta));
+    double z = kT * e0 * lg - kT * kT * dilog_neg(exp(eta));
+    double hvf = hbar * V_F / Q_E;
+    return (2.0 / PI_D) * z / (hvf * hvf);
+}
+
+/* Moments of the particle expansion at points z (Sec. 4.2): every particle's
+ * wave-vector evaluated at z, k_i(z) = sum_h k_h Psi_h(z), on the band of
+ * that z; out[j] = (V_x, V_y, mean energy, J_x = -e n(z) V_x). */
+void orc_moments_at(const orc_sim *s, int nz, const double *z, double *out)
+{
+    int P = s->P, dz = s->p.dim_z;
+    size_t N = (size_t)s->p.n_particles;
+    double hvf_eV_m = s->hbar * V_F / Q_E;
+    for (int j = 0; j < nz; ++j) {
+        double zz[2] = {0.0, 0.0}, psi[ORC_PMAX];
+        for (int d = 0; d < dz; ++d) zz[d] = z[(size_t)j * dz + d];
+        for (int h = 0; h < P; ++h) psi[h] = basis_eval(dz, h, zz);
+        double zg = (s->p.gap_dim >= 0) ? zz[s->p.gap_dim] : 0.0;
+        double e0;
+        if (s->p.gap_mode == 0) e0 = 0.5 * s->p.gap0 * (1.0 + s->p.gap_rel * zg);
+        else e0 = PI_D * hvf_eV_m / (s->p.gap0 * 1e-9 * (1.0 + s->p.gap_rel * zg));
+        double vx = 0.0, vy = 0.0, en = 0.0;
+        for (size_t i = 0; i < N; ++i) {
+            double ax = 0.0, ay = 0.0;
+            for (int h = 0; h < P; ++h) { ax += s->kx[h * N + i] * psi[h]; ay += s->ky[h * N + i] * psi[h]; }
+            double eps = energy(ax, ay, e0);
+            vx += V_F * ax / eps;
+            vy += V_F * ay / eps;
+            en += eps;
+        }
+        double kT = K_B * s->p.temp_K / Q_E;
+        double n = orc_density_closed(e0, s->p.fermi_eV, kT, s->hbar);
+        out[j * 4 + 0] = vx / (double)N;
+        out[j * 4 + 1] = vy / (double)N;
+        out[j * 4 + 2] = en / (double)N;
+        out[j * 4 + 3] = -Q_E * n * out[j * 4 + 0];
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Accessors for the test wrapper.                                           */
 /* ------------------------------------------------------------------------ */

@@ -74,6 +74,12 @@ void orc_init(orc_sim *s);
 void orc_run(orc_sim *s, double dt, int n_steps, double *moments_out);
 void orc_reconstruct_f(const orc_sim *s, int nbins, double emin, double emax,
                        double *nodes_out, double *modes_out);
+/* Moments at points z ([nz][dim_z]) of the particle expansion: out[nz][4] =
+ * V_x, V_y (m/s), mean energy (eV), J_x (A/m). */
+void orc_moments_at(const orc_sim *s, int nz, const double *z, double *out);
+/* Equilibrium electron density (1/m^2) of a band with minimum e0 (eV), in
+ * closed form with the dilogarithm. */
+double orc_density_closed(double e0, double mu, double kT, double hbar);
 void orc_reconstruct_f_at(const orc_sim *s, const double *z, int nbins, double emin,
                           double emax, double *out);
 

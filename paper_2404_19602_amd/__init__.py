@@ -212,6 +212,17 @@ class Simulation:
               "reconstruct_f_at")
         return out
 
+    def moments_at(self, z, inst: int = 0) -> dict:
+        """V_x, V_y, mean energy and J_x of the particle expansion at points z
+        ([n_z][dim_z]; a plain list of scalars for one uncertain input)."""
+        dz = int(self.cfgs[inst].get("dim_z", 0))
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.float64).reshape(-1, max(dz, 1)))
+        nz = z.shape[0]
+        out = np.zeros((nz, 4))
+        check(lib().sgpm_moments_at(self._ctx, inst, nz, z.ctypes.data_as(C.c_void_p),
+                                    out.ctypes.data_as(C.c_void_p)), self._ctx, "moments_at")
+        return {"V_x": out[:, 0], "V_y": out[:, 1], "energy": out[:, 2], "J_x": out[:, 3]}
+
     def synchronize(self):
         self.stream.synchronize()
 

@@ -60,7 +60,8 @@ struct Instance {
     double* record = nullptr;  // [max_steps+1][NB][Q][3]
     unsigned long long* counters = nullptr;
     unsigned long long* bins = nullptr;  // [max(Q,1)][kMaxBins]
-    double* zpsi = nullptr;    // [P] basis at a point + eps0 (reconstruction at z)
+    double* zpsi = nullptr;    // [kMomZ][P+1] basis at points z + eps0 (evaluation at z)
+    double* mom_part = nullptr;   // [kMomWG][kMomZ][3] partial sums of the moments at z
     // tables
     double* d_psi = nullptr; double* d_wpsi = nullptr; double* d_eps0 = nullptr;
     double* d_eps0sq = nullptr; double* d_cedge = nullptr; double* d_vfield = nullptr;
@@ -180,7 +181,7 @@ Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
     L.add(64);                                         // 6 candidate counters
     L.add(SGPM_N_COUNTERS * 8);                        // 7 counters
     L.add((size_t)Q * kMaxBins * 8);                   // 8 bins
-    L.add((P + 2) * 8);                                // 9 zpsi
+    L.add((size_t)kMomZ * (P + 1) * 8);               // 9 zpsi: basis + eps0 at points z
     L.add(Q * P * 8); L.add(Q * P * 8);                // 10,11 d_psi, d_wpsi
     L.add(Q * 8); L.add(Q * 8); L.add(Q * 8); L.add(Q * 8);  // 12-15 eps0 eps0sq cedge vfield
     L.add(32 * 8);                                     // 16 ecos
@@ -205,6 +206,7 @@ Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
         const size_t nwg_slab = (size_t)((d.n_particles + mc - 1) / mc);
         L.add(nwg_slab * (size_t)words * 4);          // 35 slabs
     }
+    L.add((size_t)kMomWG * kMomZ * 3 * 8);             // 36 partials of the moments at z
     return L;
 }
 
@@ -751,6 +753,7 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         I.qc = (uint32_t*)at(6);
         I.extra = (uint32_t*)at(34);
         I.slabs = (uint32_t*)at(35);
+        I.mom_part = (double*)at(36);
         base += L.total;
         set_chunk(I, 0);
         std::memset(&dyn0[I.pos], 0, sizeof(Dyn));
@@ -1279,6 +1282,65 @@ sgpm_status sgpm_reconstruct_f(sgpm_ctx* c, int32_t inst, int32_t nbins, double 
                 for (int q = 0; q < I.Q; ++q) acc += I.t.wpsi[q * I.P + h] * F[(size_t)q * nbins + j];
                 modes[(size_t)h * nbins + j] = acc;
             }
+    return SGPM_OK;
+}
+
+// band minimum eps0 at a point z (eV), 0 when the gap is not positive there
+static double eps0_at(const Instance& I, const double* zz) {
+    const double hvf_eVm = 6.62607015e-34 / (2 * 3.14159265358979323846) * I.t.v_f / kECharge;
+    const double zg = I.d.gap_dim >= 0 ? zz[I.d.gap_dim] : 0.0;
+    const double g = I.d.gap0 * (1.0 + I.d.gap_rel * zg);
+    if (!(g > 0)) return 0.0;
+    return I.d.gap_mode == 0 ? 0.5 * g : 3.14159265358979323846 * hvf_eVm / (g * 1e-9);
+}
+
+sgpm_status sgpm_moments_at(sgpm_ctx* c, int32_t inst, int32_t n_z, const double* z, double* out) {
+    sgpm_status s = check_ctx(c, inst);
+    if (s) return s;
+    Instance& I = c->inst[inst];
+    const int dz = I.t.dim_z;
+    if (n_z < 0 || (n_z > 0 && (!out || (dz > 0 && !z)))) return fail(c, SGPM_EINVAL, "bad arguments");
+    if (!I.initialised) return fail(c, SGPM_ESTATE, "no particles yet");
+    for (int64_t k = 0; k < (int64_t)n_z * dz; ++k)
+        if (!std::isfinite(z[k])) return fail(c, SGPM_EINVAL, "non-finite z");
+    const int P = I.P;
+    const int nwg = (int)std::min<int64_t>(kMomWG, (I.n + kBlock - 1) / kBlock);
+    std::vector<double> host((size_t)kMomZ * (P + 1)), part((size_t)nwg * kMomZ * 3);
+    std::vector<double> dens(kMomZ);
+    for (int k0 = 0; k0 < n_z; k0 += kMomZ) {
+        const int nz = std::min(kMomZ, n_z - k0);
+        for (int j = 0; j < nz; ++j) {
+            double zz[2] = {0.0, 0.0};
+            for (int d = 0; d < dz; ++d) zz[d] = z[(size_t)(k0 + j) * dz + d];
+            eval_basis_all(dz, P, zz, host.data() + (size_t)j * (P + 1));
+            const double e0 = eps0_at(I, zz);
+            if (!(e0 > 0)) return fail(c, SGPM_EINVAL, "gap not positive at a requested z");
+            host[(size_t)j * (P + 1) + P] = e0;
+            dens[j] = density_at(e0, I.d.fermi_eV, I.t.kT);
+        }
+        HIPCHK(c, hipMemcpyAsync(I.zpsi, host.data(), (size_t)nz * (P + 1) * 8,
+                                 hipMemcpyHostToDevice, c->stream));
+        MomAtArgs a;
+        a.kx = I.kx; a.ky = I.ky; a.fp32 = I.fp32 ? 1 : 0; a.n = I.n; a.P = P; a.nz = nz;
+        a.zpsi = I.zpsi; a.v_f = I.t.v_f; a.partial = I.mom_part;
+        int e = launch_moments_at(a, nwg, c->stream);
+        if (e) return dev_fail(c, (hipError_t)e, "moments-at-z launch");
+        HIPCHK(c, hipMemcpyAsync(part.data(), I.mom_part, part.size() * 8, hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int j = 0; j < nz; ++j) {
+            double sx = 0.0, sy = 0.0, se = 0.0;
+            for (int w = 0; w < nwg; ++w) {
+                const double* pw = part.data() + ((size_t)w * kMomZ + j) * 3;
+                sx += pw[0]; sy += pw[1]; se += pw[2];
+            }
+            double* o = out + (size_t)(k0 + j) * 4;
+            o[0] = sx / (double)I.n;
+            o[1] = sy / (double)I.n;
+            o[2] = se / (double)I.n;
+            o[3] = -kECharge * dens[j] * o[0];
+        }
+    }
     return SGPM_OK;
 }
 

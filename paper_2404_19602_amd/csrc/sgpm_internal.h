@@ -206,6 +206,19 @@ struct EnergyHistArgs {
     unsigned long long* bins;  // [Q][nbins]
 };
 
+// Moments of the particle expansion at up to kMomZ points z per launch.
+constexpr int kMomZ = 8;          // points per launch
+constexpr int kMomWG = 256;       // workgroups per launch (partials)
+struct MomAtArgs {
+    const void* kx; const void* ky;
+    int fp32;
+    int64_t n;
+    int P, nz;
+    const double* zpsi;   // [nz][P + 1]: Psi_h(z_j), then eps0(z_j)
+    double v_f;           // m/s
+    double* partial;      // [kMomWG][kMomZ][3] sums of v_x, v_y, eps
+};
+
 // Kernel launchers (sgpm_kernels.hip).  Return hipError_t as int.  The
 // batched launchers take device arrays of descriptors of n_inst instances of
 // one shape group and wg0[n_inst + 1], the first workgroup of each instance.
@@ -221,6 +234,8 @@ int pmax_bucket(int P);
 int qmax_bucket(int Q);
 int launch_init(const InitArgs& a, void* stream);
 int launch_energy_hist(const EnergyHistArgs& a, void* stream);
+int launch_moments_at(const MomAtArgs& a, int nwg, void* stream);
+double density_at(double eps0, double mu, double kT);   // electrons per m^2
 int launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n,
                   void* stream);
 size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words, int chunk);

@@ -1135,6 +1135,75 @@ int launch_energy_hist(const EnergyHistArgs& a, void* stream) {
     return (int)hipGetLastError();
 }
 
+// ------------------------------------------------- moments at given z
+// Each particle's expansion evaluated at up to kMomZ points z (Sec. 4.2: the
+// particle reconstruction at arbitrary z): sums of v_x, v_y and eps per point
+// in FP64, one partial per workgroup, reduced in fixed order.
+template <typename T>
+__device__ __forceinline__ void moments_at_t(const MomAtArgs& a, const double* zt, double (&acc)[kMomZ][3]) {
+    const T* kx = static_cast<const T*>(a.kx);
+    const T* ky = static_cast<const T*>(a.ky);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n;
+         i += (int64_t)gridDim.x * kBlock) {
+        // modes outer, points inner: k(z_j) = sum_h k_h Psi_h(z_j)
+        double x[kMomZ], y[kMomZ];
+#pragma unroll
+        for (int j = 0; j < kMomZ; ++j) { x[j] = 0.0; y[j] = 0.0; }
+        for (int h = 0; h < a.P; ++h) {
+            const double cx = (double)kx[(size_t)h * a.n + i];
+            const double cy = (double)ky[(size_t)h * a.n + i];
+#pragma unroll
+            for (int j = 0; j < kMomZ; ++j) {
+                const double p = zt[j * (a.P + 1) + h];
+                x[j] += cx * p;
+                y[j] += cy * p;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kMomZ; ++j) {
+            if (j < a.nz) {
+                const double e0 = zt[j * (a.P + 1) + a.P];
+                const double e = sqrt(x[j] * x[j] + y[j] * y[j] + e0 * e0);
+                acc[j][0] += a.v_f * x[j] / e;
+                acc[j][1] += a.v_f * y[j] / e;
+                acc[j][2] += e;
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) moments_at_kernel(const MomAtArgs a) {
+    __shared__ double zt[kMomZ * (kMaxP + 1)];
+    __shared__ double red[kWaves][kMomZ][3];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int k = tid; k < kMomZ * (a.P + 1); k += kBlock)
+        zt[k] = k < a.nz * (a.P + 1) ? a.zpsi[k] : 0.0;
+    __syncthreads();
+    double acc[kMomZ][3];
+#pragma unroll
+    for (int j = 0; j < kMomZ; ++j) { acc[j][0] = 0.0; acc[j][1] = 0.0; acc[j][2] = 0.0; }
+    if (a.fp32) moments_at_t<float>(a, zt, acc); else moments_at_t<double>(a, zt, acc);
+#pragma unroll
+    for (int j = 0; j < kMomZ; ++j)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const double v = wave_sum(acc[j][m]);
+            if (lane == 0) red[wave][j][m] = v;
+        }
+    __syncthreads();
+    if (tid < kMomZ * 3) {
+        const int j = tid / 3, m = tid - 3 * (tid / 3);
+        double v = 0.0;
+        for (int w = 0; w < kWaves; ++w) v += red[w][j][m];
+        a.partial[((size_t)blockIdx.x * kMomZ + j) * 3 + m] = v;
+    }
+}
+
+int launch_moments_at(const MomAtArgs& a, int nwg, void* stream) {
+    hipLaunchKernelGGL(moments_at_kernel, dim3((unsigned)nwg), dim3(kBlock), 0, (hipStream_t)stream, a);
+    return (int)hipGetLastError();
+}
+
 // ------------------------------------------------------ Philox test hook
 __global__ void philox_kernel(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -266,4 +266,23 @@ const char* build_tables(const sgpm_instance_desc& d, HostTables& t) {
     return "";
 }
 
+// Equilibrium density of a band with minimum eps0 (Sec. 3 eq. den with the
+// Fermi-Dirac datum): n = (2/pi) (hbar v_F)^-2 int_eps0^inf eps f_FD d eps, by
+// panels of kT/2 up to max(mu, eps0) + 80 kT with 10-point Gauss per panel.
+double density_at(double eps0, double mu, double kT) {
+    double gx[10], gw[10];
+    gauss_legendre(10, gx, gw);
+    const double h = 0.5 * kT, top = std::fmax(mu, eps0) + 80.0 * kT;
+    const int np = (int)std::ceil((top - eps0) / h);
+    double z = 0.0;
+    for (int j = 0; j < np; ++j) {
+        const double a = eps0 + j * h, c = a + 0.5 * h, hw = 0.5 * h;
+        double s = 0.0;
+        for (int k = 0; k < 10; ++k) s += gw[k] * fd_density(c + hw * gx[k], mu, kT);
+        z += s * hw;
+    }
+    const double hvf_eVm = kH / (2.0 * kPi) * kVF / kE;
+    return (2.0 / kPi) * z / (hvf_eVm * hvf_eVm);
+}
+
 }  // namespace sgpm

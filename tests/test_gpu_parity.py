@@ -321,3 +321,30 @@ def test_error_paths(sg):
     assert sim.record_length() == 6
     with pytest.raises(sg.SgpmError):
         sg.Simulation(small_cfg(n_particles=0))
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1, n_particles=30_000, field0=2e6),
+    dict(dim_z=2, degree=4, nodes_1d=8, gap_dim=0, gap0=0.3, gap_rel=0.15, field_dim=1,
+         field0=1.5e6, field_rel=0.2, n_particles=6_000),
+])
+def test_moments_at_parity(sg, orc, kw):
+    """Moments of the particle expansion at points z between the nodes, on a
+    state taken from the oracle after 30 steps."""
+    cfg = small_cfg(**kw)
+    announce("moments_at", cfg)
+    ref = orc.OracleSim(cfg, threads=8)
+    ref.init()
+    ref.run(cfg["dt"], 30)
+    kx, ky = ref.get_state()
+    sim = sg.Simulation(cfg)
+    sim.set_state(kx, ky, step=30)
+    rng = np.random.default_rng(5)
+    dz = cfg["dim_z"]
+    z = np.concatenate([rng.uniform(-1, 1, size=(19, dz)), -np.ones((1, dz)), np.ones((1, dz))])
+    g = sim.moments_at(z)
+    o = ref.moments_at(z)
+    for k in ("V_x", "V_y"):
+        assert np.allclose(g[k], o[k], rtol=1e-12, atol=1e-12 * np.abs(o[k]).max()), k
+    assert np.allclose(g["energy"], o["energy"], rtol=1e-13)
+    assert np.allclose(g["J_x"], o["J_x"], rtol=1e-9, atol=1e-9 * np.abs(o["J_x"]).max())

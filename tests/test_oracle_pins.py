@@ -622,3 +622,69 @@ def test_single_event_angles(orc, mech, cos_mean):
     c = (kx[one, 0] * ox[one, 0] + ky[one, 0] * oy[one, 0]) / (
         np.hypot(kx[one, 0], ky[one, 0]) * np.hypot(ox[one, 0], oy[one, 0]))
     assert abs(c.mean() - cos_mean) < 4 * c.std() / math.sqrt(one.sum())
+
+
+# ------------------------------------------------ moments at arbitrary z
+def _density_quad(e0, mu, kT):
+    """(2/pi)(hbar v_F)^-2 int_e0^inf eps f_FD d eps by scipy quadrature."""
+    hvf = HBAR * 1e6 / E_CH
+    f = lambda e: e * ss.expit(-(e - mu) / kT)
+    mid = max(mu, e0)
+    a, _ = si.quad(f, e0, mid, epsabs=0, epsrel=2e-14, limit=400) if mid > e0 else (0.0, 0)
+    b, _ = si.quad(f, mid, mid + 60 * kT, epsabs=0, epsrel=2e-14, limit=400)
+    return (2 / math.pi) * (a + b) / hvf ** 2
+
+
+@pytest.mark.parametrize("e0,mu,T", [(0.1, 0.4, 300.0), (0.15, 0.4, 300.0), (0.25, 0.2, 300.0),
+                                     (0.05, 0.6, 77.0), (0.3, 0.3, 600.0)])
+def test_density_closed_form_against_quadrature(orc, e0, mu, T):
+    kT = K_B * T / E_CH
+    assert orc.density_closed(e0, mu, kT) == pytest.approx(_density_quad(e0, mu, kT), rel=1e-11)
+
+
+def test_density_closed_form_special_cases(orc):
+    hvf = HBAR * 1e6 / E_CH
+    kT = K_B * 300.0 / E_CH
+    # eta = 0: the integral is kT e0 ln 2 + kT^2 pi^2 / 12 (Li2(-1) = -pi^2/12)
+    e0 = 0.2
+    ref = (2 / math.pi) * (kT * e0 * math.log(2) + kT ** 2 * math.pi ** 2 / 12) / hvf ** 2
+    assert orc.density_closed(e0, e0, kT) == pytest.approx(ref, rel=1e-13)
+    # degenerate limit: (mu^2 - e0^2)/2 + pi^2 kT^2 / 6 (Sommerfeld), error ~ e^-eta
+    mu, e0 = 0.9, 0.1
+    ref = (2 / math.pi) * ((mu ** 2 - e0 ** 2) / 2 + math.pi ** 2 * kT ** 2 / 6) / hvf ** 2
+    assert orc.density_closed(e0, mu, kT) == pytest.approx(ref, rel=1e-12)
+
+
+def test_node_densities_agree_with_closed_form(orc):
+    cfg = small(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1, n_particles=4)
+    t = orc.OracleSim(cfg).tables()
+    kT = K_B * 300.0 / E_CH
+    for q in range(8):
+        assert t["density"][q] == pytest.approx(orc.density_closed(t["eps0"][q], 0.4, kT), rel=1e-10)
+
+
+def test_moments_at_the_nodes_are_the_node_moments(orc):
+    cfg = small(dim_z=1, degree=4, nodes_1d=6, gap_dim=0, gap_rel=0.15, n_particles=3000,
+                field0=3e6)
+    s = orc.OracleSim(cfg)
+    s.init()
+    s.run(cfg["dt"], 25)
+    t = s.tables()
+    m = s.moments_at(t["z"][:, 0])
+    rec = np.asarray(s.record)[-1]          # per node: v_x, v_y, energy at the last time
+    assert np.allclose(m["V_x"], rec[:, 0], rtol=1e-11, atol=1e-6)
+    assert np.allclose(m["V_y"], rec[:, 1], rtol=1e-11, atol=1e-6)
+    assert np.allclose(m["energy"], rec[:, 2], rtol=1e-13)
+    assert np.allclose(m["J_x"], -E_CH * t["density"] * rec[:, 0], rtol=1e-9, atol=1e-12)
+
+
+def test_moments_at_constant_in_z_without_uncertainty(orc):
+    # z-independent inputs: every mode past the mean stays zero, so the
+    # expansion is the same at every z
+    cfg = small(dim_z=1, degree=3, nodes_1d=5, gap_dim=0, gap_rel=0.0, n_particles=1500)
+    s = orc.OracleSim(cfg)
+    s.init()
+    s.run(cfg["dt"], 10)
+    m = s.moments_at(np.linspace(-1, 1, 7))
+    for k in ("V_x", "V_y", "energy", "J_x"):
+        assert np.allclose(m[k], m[k][0], rtol=1e-12, atol=1e-9 * np.abs(m[k]).max() + 1e-12), k
