@@ -215,6 +215,16 @@ sgpm_status sgpm_moments_at(sgpm_ctx* ctx, int32_t inst, int32_t n_z, const doub
 sgpm_status sgpm_reconstruct_f_at(sgpm_ctx* ctx, int32_t inst, int32_t n_z, const double* z,
                                   int32_t nbins, double emin_eV, double emax_eV, double* out);
 
+/* Pauli violation (Sec. 5, Test 1): for each recorded time, the number of
+ * particles above the maximum occupation number, sum over the cells c of
+ * max(0, H_q[c] - cap_q), per node q.  cap_q is the largest cell count of
+ * node q at record index 0 (the initial datum, or the state given to
+ * sgpm_set_state): the occupation of a full cell for this Fermi level and
+ * particle count.  out is [count][Q]; synchronises the stream.  The paper's
+ * N-bar is the maximum over the times divided by N. */
+sgpm_status sgpm_occupancy_excess(sgpm_ctx* ctx, int32_t inst, int64_t t_first, int64_t count,
+                                  uint32_t* out);
+
 /* Copy the coefficients in or out (host FP64 arrays kx[P][N] then ky[P][N]
  * in one buffer of 2*P*N doubles).  set_state rebuilds the histogram of the
  * given state, records it as time index 0 and sets the step counter (the

@@ -71,7 +71,7 @@ def lib():
         L.orc_step_count.argtypes = [P]; L.orc_step_count.restype = C.c_long
         L.orc_set_threads.argtypes = [P, C.c_int]
         L.orc_init.argtypes = [P]
-        L.orc_run.argtypes = [P, C.c_double, C.c_int, dp]
+        L.orc_run.argtypes = [P, C.c_double, C.c_int, dp, up]
         L.orc_tables.argtypes = [P, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_get_state.argtypes = [P, dp, dp]
         L.orc_set_state.argtypes = [P, dp, dp, C.c_long]
@@ -209,11 +209,14 @@ class OracleSim:
     def init(self):
         lib().orc_init(self._h)
         self.record = [self.moments()]
+        self.excess = [np.zeros(self.Q, dtype=np.uint32)]
 
     def run(self, dt: float, n_steps: int):
         out = np.zeros((n_steps, self.Q, 3))
-        lib().orc_run(self._h, dt, n_steps, _dp(out))
+        ex = np.zeros((n_steps, self.Q), dtype=np.uint32)
+        lib().orc_run(self._h, dt, n_steps, _dp(out), _up(ex))
         self.record.extend(list(out))
+        self.excess.extend(list(ex))
         return out
 
     @property
@@ -235,6 +238,7 @@ class OracleSim:
         ky = np.ascontiguousarray(ky, dtype=np.float64).reshape(self.P, self.N)
         lib().orc_set_state(self._h, _dp(kx), _dp(ky), step)
         self.record = [self.moments()]
+        self.excess = [np.zeros(self.Q, dtype=np.uint32)]
 
     def histogram(self):
         H = np.zeros((self.Q, self.nk, self.nk), dtype=np.uint32)

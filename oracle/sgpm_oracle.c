@@ -412,6 +412,8 @@ orc_sim *orc_create(const orc_params *p)
     s->ky = (double *)calloc((size_t)P * N, sizeof(double));
     s->H = (uint32_t *)calloc((size_t)Q * p->nk * p->nk, sizeof(uint32_t));
     s->Hmax = (uint32_t *)calloc((size_t)Q, sizeof(uint32_t));
+    s->cap = (uint32_t *)calloc((size_t)Q, sizeof(uint32_t));
+    s->excess = (uint32_t *)calloc((size_t)Q, sizeof(uint32_t));
     s->threads = 1;
     return s;
 }
@@ -423,7 +425,7 @@ void orc_destroy(orc_sim *s)
     free(s->cdf_x); free(s->cdf_lo); free(s->cdf_hi); free(s->cdf_np);
     free(s->z); free(s->w); free(s->psi); free(s->eps0); free(s->width); free(s->field);
     free(s->Ehat); free(s->C_edge); free(s->density);
-    free(s->kx); free(s->ky); free(s->H); free(s->Hmax);
+    free(s->kx); free(s->ky); free(s->H); free(s->Hmax); free(s->cap); free(s->excess);
     free(s);
 }
 
@@ -702,6 +704,21 @@ static void rebuild_histogram(orc_sim *s)
         for (size_t c = 0; c < cells; ++c) if (s->H[q * cells + c] > m) m = s->H[q * cells + c];
         s->Hmax[q] = m;
     }
+    /* Pauli violation (Sec. 5 Test 1): particles above the maximum occupation
+     * number of a cell, summed over the cells of each node */
+    for (int q = 0; q < Q; ++q) {
+        uint32_t ex = 0;
+        for (size_t c = 0; c < cells; ++c)
+            if (s->H[q * cells + c] > s->cap[q]) ex += s->H[q * cells + c] - s->cap[q];
+        s->excess[q] = ex;
+    }
+}
+
+/* the maximum occupation number per node: the largest cell count of the
+ * current histogram (the initial datum, or a state set from outside) */
+static void take_cap(orc_sim *s)
+{
+    for (int q = 0; q < s->Q; ++q) { s->cap[q] = s->Hmax[q]; s->excess[q] = 0; }
 }
 
 /* per node: V_x, V_y (m/s), mean energy (eV)  (Sec. 3 eq. Vx, eq. en; Sec. 4.2) */
@@ -766,12 +783,13 @@ void orc_init(orc_sim *s)
     s->step = 0;
     memset(&s->counters, 0, sizeof(s->counters));
     rebuild_histogram(s);
+    take_cap(s);
 }
 
 /* One or more time steps: drift (Sec. 4.1 sG electric forcing), collisions
  * (Algorithm 2) against the histogram of the previous step, then the new
  * histogram and the moments at t^{n+1}.  moments_out: [n_steps][Q][3]. */
-void orc_run(orc_sim *s, double dt, int n_steps, double *moments_out)
+void orc_run(orc_sim *s, double dt, int n_steps, double *moments_out, uint32_t *excess_out)
 {
     int P = s->P, Q = s->Q;
     size_t N = (size_t)s->p.n_particles;
@@ -803,6 +821,7 @@ void orc_run(orc_sim *s, double dt, int n_steps, double *moments_out)
         rebuild_histogram(s);
         s->step += 1;
         if (moments_out) orc_moments(s, moments_out + (size_t)n * Q * 3);
+        if (excess_out) memcpy(excess_out + (size_t)n * Q, s->excess, sizeof(uint32_t) * Q);
     }
 }
 
@@ -975,6 +994,7 @@ void orc_set_state(orc_sim *s, const double *kx, const double *ky, long step)
     memcpy(s->ky, ky, sizeof(double) * n);
     s->step = step;
     rebuild_histogram(s);
+    take_cap(s);
 }
 
 void orc_get_histogram(const orc_sim *s, uint32_t *H, uint32_t *Hmax)

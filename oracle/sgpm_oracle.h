@@ -50,6 +50,9 @@ typedef struct {
     double **cdf_x, **cdf_lo, **cdf_hi;
     double *kx, *ky;        /* [P][N] coefficients, kappa units (eV) */
     uint32_t *H, *Hmax;     /* [Q][nk*nk] histogram of the current state, [Q] max */
+    uint32_t *cap;          /* [Q] maximum occupation: the largest cell count of the
+                               state given to init / set_state, per node       */
+    uint32_t *excess;       /* [Q] particles above the cap in the current histogram */
     long step;
     orc_counters counters;
     int threads;
@@ -71,7 +74,7 @@ void orc_collide_particle(const orc_sim *s, long i, uint32_t step, double dt,
                           double *chx, double *chy, orc_counters *cnt);
 void orc_moments(const orc_sim *s, double *out);
 void orc_init(orc_sim *s);
-void orc_run(orc_sim *s, double dt, int n_steps, double *moments_out);
+void orc_run(orc_sim *s, double dt, int n_steps, double *moments_out, uint32_t *excess_out);
 void orc_reconstruct_f(const orc_sim *s, int nbins, double emin, double emax,
                        double *nodes_out, double *modes_out);
 /* Moments at points z ([nz][dim_z]) of the particle expansion: out[nz][4] =

@@ -143,6 +143,18 @@ class Simulation:
         out["per_node_jx"] = per[:, :, 3]
         return out
 
+    def occupancy_excess(self, first: int = 0, count: int | None = None, inst: int = 0):
+        """[count][Q] particles above the maximum occupation number per
+        recorded time and node (Pauli violation)."""
+        _, Q = self.sizes[inst]
+        if count is None:
+            count = self.record_length(inst) - first
+        out = np.zeros((count, Q), dtype=np.uint32)
+        check(lib().sgpm_occupancy_excess(self._ctx, inst, first, count,
+                                          out.ctypes.data_as(C.c_void_p)), self._ctx,
+              "occupancy_excess")
+        return out
+
     def record_length(self, inst: int = 0) -> int:
         n = C.c_int64(0)
         check(lib().sgpm_record_length(self._ctx, inst, C.byref(n)), self._ctx, "record_length")

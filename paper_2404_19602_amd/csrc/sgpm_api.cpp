@@ -62,6 +62,8 @@ struct Instance {
     unsigned long long* bins = nullptr;  // [max(Q,1)][kMaxBins]
     double* zpsi = nullptr;    // [kMomZ][P+1] basis at points z + eps0 (evaluation at z)
     double* mom_part = nullptr;   // [kMomWG][kMomZ][3] partial sums of the moments at z
+    uint32_t* cap = nullptr;      // [Q] maximum occupation number (largest count at record 0)
+    uint32_t* excess = nullptr;   // [max_steps+1][Q] particles above it per recorded time
     // tables
     double* d_psi = nullptr; double* d_wpsi = nullptr; double* d_eps0 = nullptr;
     double* d_eps0sq = nullptr; double* d_cedge = nullptr; double* d_vfield = nullptr;
@@ -207,6 +209,8 @@ Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
         L.add(nwg_slab * (size_t)words * 4);          // 35 slabs
     }
     L.add((size_t)kMomWG * kMomZ * 3 * 8);             // 36 partials of the moments at z
+    L.add(Q * 4);                                      // 37 maximum occupation per node
+    L.add(((size_t)d.max_steps + 1) * Q * 4);          // 38 excess over it, per time
     return L;
 }
 
@@ -350,6 +354,7 @@ K1Args<T> make_k1(const sgpm_ctx* cx, const Instance& I) {
     a.qc = I.qc;
     a.counters = I.counters;
     a.chunk = I.chunk;
+    a.excess = I.excess;
     return a;
 }
 
@@ -392,6 +397,8 @@ K3Args make_k3(const sgpm_ctx* cx, const Instance& I) {
     a.partial = I.partial;
     a.record = I.record;
     a.dyn = cx->dyn + I.pos;
+    a.cap = I.cap;
+    a.excess = I.excess;
     return a;
 }
 
@@ -571,7 +578,13 @@ sgpm_status rebuild(sgpm_ctx* c, Instance& I) {
     int e = launch_set_dyn(c->dyn + I.pos, 1, 1, (uint32_t)I.step, (uint32_t)I.rec_base, 0, 0.0,
                            c->stream);
     if (e) return dev_fail(c, (hipError_t)e, "step state launch");
-    return state_pass_one(c, I);
+    sgpm_status st = state_pass_one(c, I);
+    if (st) return st;
+    // maximum occupation number: the largest cell count of this state, per node
+    HIPCHK(c, hipMemcpyAsync(I.cap, I.Hmax + (size_t)(I.step % 3) * I.hmstride, (size_t)I.Q * 4,
+                             hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(I.excess, 0, (size_t)I.Q * 4, c->stream));
+    return SGPM_OK;
 }
 
 // Raw copy of an instance's state, step and counters (autotuner trials).
@@ -754,6 +767,8 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         I.extra = (uint32_t*)at(34);
         I.slabs = (uint32_t*)at(35);
         I.mom_part = (double*)at(36);
+        I.cap = (uint32_t*)at(37);
+        I.excess = (uint32_t*)at(38);
         base += L.total;
         set_chunk(I, 0);
         std::memset(&dyn0[I.pos], 0, sizeof(Dyn));
@@ -810,6 +825,7 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         if (e == hipSuccess) e = up(I.d_ehat, t.ehat.data(), P * 8);
         if (e == hipSuccess) e = hipMemsetAsync(I.counters, 0, SGPM_N_COUNTERS * 8, c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(I.qc, 0, 64, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(I.cap, 0xFF, (size_t)Q * 4, c->stream);
         // host vectors above are released at scope end: wait for the copies
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) {
@@ -1169,6 +1185,22 @@ sgpm_status sgpm_moments(sgpm_ctx* c, int32_t inst, int64_t first, int64_t count
             g[SGPM_AGG_SE_E_VX + k] = se;
         }
     }
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_occupancy_excess(sgpm_ctx* c, int32_t inst, int64_t first, int64_t count,
+                                  uint32_t* out) {
+    sgpm_status s = check_ctx(c, inst);
+    if (s) return s;
+    Instance& I = c->inst[inst];
+    if (!I.initialised) return fail(c, SGPM_ESTATE, "no particles yet");
+    const int64_t avail = I.step - I.rec_base + 1;
+    if (first < 0 || count < 0 || first + count > avail || (count > 0 && !out))
+        return fail(c, SGPM_EINVAL, "requested times outside the record");
+    if (count == 0) return SGPM_OK;
+    HIPCHK(c, hipMemcpyAsync(out, I.excess + (size_t)first * I.Q, (size_t)count * I.Q * 4,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return SGPM_OK;
 }
 

@@ -133,6 +133,7 @@ struct K1Args {
     uint32_t* qc;           // [2][2] candidate count (and a spare word), by step parity
     unsigned long long* counters;
     int64_t chunk;
+    uint32_t* excess;       // [max_steps + 1][Q]: this time's slot is cleared here
 };
 
 // Collider kernel: a group of G lanes per candidate, one node per lane;
@@ -177,6 +178,8 @@ struct K3Args {
     const double* partial;  // [nwg][Q][3]
     double* record;         // [max_steps + 1][nb][Q][3]
     Dyn* dyn;
+    const uint32_t* cap;    // [Q] maximum occupation number per node
+    uint32_t* excess;       // [max_steps + 1][Q] particles above it, per time
 };
 
 struct InitArgs {

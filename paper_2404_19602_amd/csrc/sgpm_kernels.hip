@@ -321,6 +321,9 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
     const double vfdt = a.dyn->vfdt;
     // the collider of the previous step is done with its copy of n
     if (moving && wg == 0 && threadIdx.x == 0) a.dyn->step_k2 = step;
+    // the finalize kernel of this time accumulates into a cleared slot
+    if (wg == 0 && (int)threadIdx.x < a.Q)
+        a.excess[(size_t)(step - a.dyn->rec_base) * a.Q + threadIdx.x] = 0u;
     const T dt = (T)a.dyn->dt;
     const int P = a.P, Q = a.Q;
     const K1Lds<T> L = k1_lds<T>(smem, PMAX, Q, a.hwin_words, (int)a.chunk);
@@ -837,7 +840,8 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
     const int wcells = a.win * a.win;
     __shared__ uint32_t part[kK3Lanes][kK3Words][2];
     __shared__ uint32_t smax[kMaxQ];
-    for (int k = tid; k < a.Q; k += kBlock) smax[k] = 0u;
+    __shared__ uint32_t scap[kMaxQ], sex[kMaxQ];
+    for (int k = tid; k < a.Q; k += kBlock) { smax[k] = 0u; scap[k] = a.cap[k]; sex[k] = 0u; }
     __syncthreads();
     if (wg < a.n_win_wg) {
         // 16 columns of four words, kK3Lanes slab lanes; 16-byte loads
@@ -874,6 +878,7 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
                 a.extra[g] = 0u;
                 h_out[g] = sum;
                 if (sum) atomicMax(&smax[q], sum);
+                if (sum > scap[q]) atomicAdd(&sex[q], sum - scap[q]);
             }
         }
     } else {
@@ -888,11 +893,15 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
             a.extra[g] = 0u;
             h_out[g] = v;
             if (v) atomicMax(&smax[q], v);
+            if (v > scap[q]) atomicAdd(&sex[q], v - scap[q]);
         }
     }
     __syncthreads();
     for (int k = tid; k < a.Q; k += kBlock)
         if (smax[k]) atomicMax(&hmax_out[k], smax[k]);
+    // particles above the maximum occupation number at this time (Pauli violation)
+    for (int k = tid; k < a.Q; k += kBlock)
+        if (sex[k]) atomicAdd(&a.excess[(size_t)(step - a.dyn->rec_base) * a.Q + k], sex[k]);
     if (wg == 0) {
         // stale maximum slot of step n + 1 and the counters of that step
         uint32_t* hmax_clr = a.Hmax + (size_t)((step + 1u) % 3u) * a.hmstride;

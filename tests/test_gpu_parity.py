@@ -162,6 +162,8 @@ def test_step_parity(sg, orc, name):
         H, M = sim.histogram()
         Ho, Mo = ref.histogram()
         assert np.array_equal(H, Ho) and np.array_equal(M, Mo)
+        # particles above the maximum occupation number, every step (Pauli violation)
+        assert np.array_equal(sim.occupancy_excess(), np.asarray(ref.excess, dtype=np.uint32))
     assert gc["collisions"] > 0 or cfg["n_particles"] == 1
     m = sim.moments()
     rec = np.asarray(ref.record)
@@ -348,3 +350,25 @@ def test_moments_at_parity(sg, orc, kw):
         assert np.allclose(g[k], o[k], rtol=1e-12, atol=1e-12 * np.abs(o[k]).max()), k
     assert np.allclose(g["energy"], o["energy"], rtol=1e-13)
     assert np.allclose(g["J_x"], o["J_x"], rtol=1e-9, atol=1e-9 * np.abs(o["J_x"]).max())
+
+
+def test_occupancy_excess_parity_without_pauli(sg, orc):
+    """A degenerate gas pushed hard with the Pauli acceptance off: many cells
+    exceed the maximum occupation; the per-step excess matches the oracle."""
+    cfg = small_cfg(n_particles=20_000, field0=3e7, nk=60, fermi_eV=0.6, pauli=0,
+                    rate_scale=(20.0,) * 6)
+    announce("occupancy excess", cfg)
+    ref = orc.OracleSim(cfg, threads=8)
+    ref.init()
+    kx, ky = ref.get_state()
+    sim = sg.Simulation(cfg, max_steps=30)
+    sim.set_state(kx, ky, step=0)
+    sim.step(30, cfg["dt"])
+    ref.run(cfg["dt"], 30)
+    gx, gy = sim.get_state()
+    ox, oy = ref.get_state()
+    assert int((rel_err(gx, gy, ox, oy) > TOL).sum()) == 0
+    g = sim.occupancy_excess()
+    o = np.asarray(ref.excess, dtype=np.uint32)
+    assert g.max() > 0
+    assert np.array_equal(g, o)

@@ -688,3 +688,30 @@ def test_moments_at_constant_in_z_without_uncertainty(orc):
     m = s.moments_at(np.linspace(-1, 1, 7))
     for k in ("V_x", "V_y", "energy", "J_x"):
         assert np.allclose(m[k], m[k][0], rtol=1e-12, atol=1e-9 * np.abs(m[k]).max() + 1e-12), k
+
+
+# --------------------------------------------- Pauli violation (Test 1)
+def test_occupancy_excess_is_the_cell_excess_over_the_initial_maximum(orc):
+    cfg = small(dim_z=1, degree=3, nodes_1d=4, gap_dim=0, gap_rel=0.1, n_particles=20_000,
+                field0=1e7, nk=60)
+    s = orc.OracleSim(cfg)
+    s.init()
+    _, cap = s.histogram()                  # maximum occupation: largest count at t = 0
+    assert np.all(s.excess[0] == 0)
+    s.run(cfg["dt"], 20)
+    H, _ = s.histogram()
+    ref = np.maximum(H.astype(np.int64) - cap[:, None, None].astype(np.int64), 0).sum(axis=(1, 2))
+    assert np.array_equal(np.asarray(s.excess[-1], dtype=np.int64), ref)
+
+
+def test_pauli_acceptance_limits_occupation_violations(orc):
+    # a degenerate gas pushed by a strong field: without the 1 - f factor
+    # particles pile into cells above the maximum occupation far more often
+    base = small(n_particles=20_000, field0=3e7, nk=60, fermi_eV=0.6, rate_scale=(20.0,) * 6)
+    worst = {}
+    for pauli in (0, 1):
+        s = orc.OracleSim(dict(base, pauli=pauli))
+        s.init()
+        s.run(base["dt"], 30)
+        worst[pauli] = int(np.max(np.asarray(s.excess)))
+    assert worst[0] > 2 * worst[1], worst
