@@ -121,6 +121,11 @@ typedef struct {
     uint32_t instance_id;   /* Philox counter word 3                                */
     int32_t c_max;          /* cap on collisions per particle per step [32], <= 255 */
     int32_t max_steps;      /* capacity of the moment record (steps after init)    */
+    int32_t splitting;      /* 0: drift dt, then the collisions (the paper's first- */
+                            /*    order splitting) [0]; 1: Strang, drift dt/2,      */
+                            /*    collisions, drift dt/2 (higher-order splittings,  */
+                            /*    Sec. 3); the Pauli lookup then moves the grid by  */
+                            /*    the first half drift                              */
 } sgpm_instance_desc;
 
 /* Fill a descriptor with the paper's defaults (Table 1 and Sec. 5). */

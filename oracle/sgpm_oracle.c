@@ -297,6 +297,7 @@ static double z_coord(const orc_sim *s, int q, int d) { return s->z[q * 2 + d]; 
 orc_sim *orc_create(const orc_params *p)
 {
     if (p->dim_z < 0 || p->dim_z > 2) return NULL;
+    if (p->splitting != 0 && p->splitting != 1) return NULL;
     if (p->degree < 0 || p->nodes_1d < 1) return NULL;
     if (p->n_particles < 1) return NULL;
     if (p->temp_K <= 0 || p->nk < 1 || p->lk_eV <= 0 || p->alpha < 0) return NULL;
@@ -670,7 +671,7 @@ void orc_collide_particle(const orc_sim *s, long i, uint32_t step, double dt,
             cnt->events += 1;
             /* Pauli acceptance against the previous-step distribution
              * (eq. Pauli / Pauli_gPC). */
-            double f = s->p.pauli ? pauli_f(s, q, px, py, dt) : 0.0;
+            double f = s->p.pauli ? pauli_f(s, q, px, py, s->p.splitting ? 0.5 * dt : dt) : 0.0;
             if (f < eta) { newx[q] = px; newy[q] = py; }
             else { newx[q] = kx; newy[q] = ky; cnt->pauli_rejected += 1; }
         }
@@ -806,11 +807,13 @@ void orc_run(orc_sim *s, double dt, int n_steps, double *moments_out, uint32_t *
             orc_counters loc;
             memset(&loc, 0, sizeof(loc));
             for (int h = 0; h < P; ++h) {
-                /* k_h^{n+1} = k_h^n - (e/hbar) dt E_h, in kappa units */
-                chx[h] = s->kx[h * N + i] - drift[h];
+                /* k_h -= (e/hbar) dt E_h, in kappa units (dt/2 with Strang) */
+                chx[h] = s->kx[h * N + i] - (s->p.splitting ? 0.5 * drift[h] : drift[h]);
                 chy[h] = s->ky[h * N + i];
             }
             orc_collide_particle(s, i, step, dt, chx, chy, &loc);
+            if (s->p.splitting)   /* the second half of the drift */
+                for (int h = 0; h < P; ++h) chx[h] -= 0.5 * drift[h];
             for (int h = 0; h < P; ++h) { s->kx[h * N + i] = chx[h]; s->ky[h * N + i] = chy[h]; }
             c_coll += loc.collisions; c_ev += loc.events; c_rej += loc.pauli_rejected;
             c_exh += loc.edge_exhausted; c_cmax += loc.cmax_hits;
@@ -1034,10 +1037,13 @@ void orc_step_particles(const orc_sim *s, const long *idx, long count, uint32_t 
         orc_counters loc;
         memset(&loc, 0, sizeof(loc));
         for (int h = 0; h < P; ++h) {
-            chx[h] = kx[t * P + h] - V_F * dt * s->Ehat[h];
+            double d = V_F * dt * s->Ehat[h];
+            chx[h] = kx[t * P + h] - (s->p.splitting ? 0.5 * d : d);
             chy[h] = ky[t * P + h];
         }
         orc_collide_particle(s, idx[t], step, dt, chx, chy, &loc);
+        if (s->p.splitting)
+            for (int h = 0; h < P; ++h) chx[h] -= 0.5 * (V_F * dt * s->Ehat[h]);
         for (int h = 0; h < P; ++h) { kx[t * P + h] = chx[h]; ky[t * P + h] = chy[h]; }
         if (ncoll) ncoll[t] = loc.collisions;
     }

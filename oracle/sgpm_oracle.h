@@ -31,6 +31,9 @@ typedef struct {
     uint64_t seed;
     uint32_t instance;
     int c_max;          /* cap on collisions per particle per step            */
+    int splitting;      /* 0: drift dt then collisions (the paper's first-order
+                           splitting); 1: Strang, drift dt/2, collisions, drift
+                           dt/2 (Sec. 3 mentions higher-order splittings)      */
 } orc_params;
 
 typedef struct {

@@ -330,6 +330,7 @@ Consts<T> make_consts(const sgpm_instance_desc& d, const HostTables& t) {
     c.pauli = d.pauli;
     c.final_state = d.final_state;
     c.c_max = d.c_max;
+    c.splitting = d.splitting;
     return c;
 }
 
@@ -641,7 +642,7 @@ void sgpm_default_desc(sgpm_instance_desc* d) {
     d->fermi_eV = 0.4; d->temp_K = 300.0; d->alpha = 0.1;
     d->nk = 240; d->lk_eV = 5.0; d->pauli = 1; d->final_state = 0;
     for (int m = 0; m < 6; ++m) d->rate_scale[m] = 1.0;
-    d->seed = 1; d->instance_id = 0; d->c_max = 32; d->max_steps = 1000;
+    d->seed = 1; d->instance_id = 0; d->c_max = 32; d->max_steps = 1000; d->splitting = 0;
 }
 
 const char* sgpm_status_string(sgpm_status s) {

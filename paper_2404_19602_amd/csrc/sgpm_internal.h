@@ -65,6 +65,8 @@ struct Consts {
     T eps0max_sq;
     T lk, dk, inv_dk;
     int32_t nk, pauli, final_state, c_max;
+    int32_t splitting;                // 1: Strang (half drift before and after the collisions)
+    int32_t pad_;
 };
 
 // Device tables of one instance in one precision (all [Q][P] row-major).

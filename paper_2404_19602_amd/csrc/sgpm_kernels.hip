@@ -215,7 +215,7 @@ size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words, int chunk) {
     off = (off + 15) & ~(size_t)15;
     off += sizeof(Consts<double>);                       // consts (either precision fits)
     off = (off + 15) & ~(size_t)15;
-    off += s * ((size_t)Q * PM + 2 * Q + 2 * PM);       // psi, eps0sq, shift, psimax, drift
+    off += s * ((size_t)Q * PM + 2 * Q + 3 * PM);       // psi, eps0sq, shift, psimax, drift, pdrift
     off = (off + 15) & ~(size_t)15;
     off += (size_t)kWaves1 * Q * 3 * 8;                  // per-wave moment sums
     off += 16 * 4;                                       // counters
@@ -227,7 +227,9 @@ struct K1Lds {
     uint32_t* hwin;
     int* cbuf;
     Consts<T>* c;
-    T* psi; T* eps0sq; T* shift; T* psimax; T* drift;
+    T* psi; T* eps0sq; T* shift; T* psimax;
+    T* drift;    // applied before the collisions (dt, or dt/2 with Strang)
+    T* pdrift;   // applied after them (0, or dt/2 with Strang)
     double* red;
     uint32_t* cnt;
 };
@@ -248,7 +250,8 @@ __device__ __forceinline__ K1Lds<T> k1_lds(unsigned char* smem, int PM, int Q, i
     L.shift = L.eps0sq + Q;
     L.psimax = L.shift + Q;
     L.drift = L.psimax + PM;
-    off += sizeof(T) * ((size_t)Q * PM + 2 * Q + 2 * PM);
+    L.pdrift = L.drift + PM;
+    off += sizeof(T) * ((size_t)Q * PM + 2 * Q + 3 * PM);
     off = (off + 15) & ~(size_t)15;
     L.red = reinterpret_cast<double*>(smem + off);
     off += (size_t)kWaves1 * Q * 3 * 8;
@@ -336,9 +339,12 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
         const int q = k / PMAX, h = k - q * PMAX;
         L.psi[k] = h < P ? a.tab.psi[q * P + h] : (T)0;
     }
+    const bool strang = a.tab.consts->splitting != 0;
     for (int k = tid; k < PMAX; k += kBlock1) {
         L.psimax[k] = k < P ? a.tab.psimax[k] : (T)0;
-        L.drift[k] = (moving && k < P) ? (T)(vfdt * a.ehat[k]) : (T)0;
+        const T full = (moving && k < P) ? (T)(vfdt * a.ehat[k]) : (T)0;
+        L.drift[k] = strang ? full * (T)0.5 : full;
+        L.pdrift[k] = strang ? full * (T)0.5 : (T)0;
     }
     for (int k = tid; k < kWaves1 * Q * 3; k += kBlock1) L.red[k] = 0.0;
     if (tid < 16) L.cnt[tid] = 0u;
@@ -447,7 +453,8 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
                 // the particle does not collide: its step is the drift alone
     #pragma unroll
                 for (int h = 0; h < PMAX; ++h)
-                    if (h < P && L.drift[h] != (T)0) a.kx[(size_t)h * a.n + i] = cx[h] - L.drift[h];
+                    if (h < P && L.drift[h] != (T)0)
+                        a.kx[(size_t)h * a.n + i] = (cx[h] - L.drift[h]) - L.pdrift[h];
             }
             // candidates of this workgroup collected in LDS
             const uint64_t mask = __ballot(cand);
@@ -523,7 +530,7 @@ size_t k2_lds_bytes(int P, int Q, int fp32) {
     const int groups = kBlock / k2_group_width(Q);
     size_t off = sizeof(Consts<double>);
     off = (off + 15) & ~(size_t)15;
-    off += s * (2 * (size_t)Q * PM + 4 * (size_t)Q + 32 + PM);   // psi wpsi eps0 eps0sq cedge vfield ecos drift
+    off += s * (2 * (size_t)Q * PM + 4 * (size_t)Q + 32 + 2 * PM);   // psi wpsi eps0 eps0sq cedge vfield ecos drift pdrift
     off = (off + 15) & ~(size_t)15;
     off += s * (size_t)groups * (2 * (size_t)Q + 2 * PM);         // per-group projection scratch
     off = (off + 15) & ~(size_t)15;
@@ -534,7 +541,9 @@ size_t k2_lds_bytes(int P, int Q, int fp32) {
 template <typename T>
 struct K2Lds {
     Consts<T>* c;
-    T* psi; T* wpsi; T* eps0; T* eps0sq; T* cedge; T* vfield; T* ecos; T* drift;
+    T* psi; T* wpsi; T* eps0; T* eps0sq; T* cedge; T* vfield; T* ecos;
+    T* drift;            // applied before the collisions (dt, or dt/2 with Strang)
+    T* pdrift;           // applied after them (0, or dt/2 with Strang)
     T* scratch;          // [groups][2Q + 2PM]: new node values, then new modes
     uint32_t* cnt;
 };
@@ -554,7 +563,8 @@ __device__ __forceinline__ K2Lds<T> k2_lds(unsigned char* smem, int PM, int Q, i
     L.vfield = L.cedge + Q;
     L.ecos = L.vfield + Q;
     L.drift = L.ecos + 32;
-    off += sizeof(T) * (2 * (size_t)Q * PM + 4 * (size_t)Q + 32 + PM);
+    L.pdrift = L.drift + PM;
+    off += sizeof(T) * (2 * (size_t)Q * PM + 4 * (size_t)Q + 32 + 2 * PM);
     off = (off + 15) & ~(size_t)15;
     L.scratch = reinterpret_cast<T*>(smem + off);
     off += sizeof(T) * (size_t)groups * (2 * (size_t)Q + 2 * PM);
@@ -614,10 +624,17 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
         L.cedge[k] = a.tab.cedge[k]; L.vfield[k] = a.tab.vfield[k];
     }
     for (int k = tid; k <= kEdgePts / 2; k += kBlock) L.ecos[k] = a.tab.edge_cos[k];
-    for (int k = tid; k < PMAX; k += kBlock) L.drift[k] = k < P ? (T)(vfdt * a.ehat[k]) : (T)0;
+    const bool strang = a.tab.consts->splitting != 0;
+    for (int k = tid; k < PMAX; k += kBlock) {
+        const T full = k < P ? (T)(vfdt * a.ehat[k]) : (T)0;
+        L.drift[k] = strang ? full * (T)0.5 : full;
+        L.pdrift[k] = strang ? full * (T)0.5 : (T)0;
+    }
     if (tid < 16) L.cnt[tid] = 0u;
     __syncthreads();
     const Consts<T>& c = *L.c;
+    // the grid of H^n moved with the drift applied before the collisions
+    const T dt_grid = strang ? dt * (T)0.5 : dt;
 
     const int g = tid % G;                // rank in the group = node handled
     const int grp = tid / G;
@@ -737,7 +754,7 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
                     }
                     if (ok) {
                         ++nev;
-                        const T f = c.pauli ? pauli_f<T>(h_read, hmax_read, L, c, q, px, py, dt)
+                        const T f = c.pauli ? pauli_f<T>(h_read, hmax_read, L, c, q, px, py, dt_grid)
                                             : (T)0;
                         if (f < eta) { nx = px; ny = py; } else { ++nrej; }
                     }
@@ -778,7 +795,7 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
 #pragma unroll
         for (int h = 0; h < PMAX; ++h)
             if (h < P && (h % G) == g) {
-                a.kx[(size_t)h * a.n + i] = cx[h];
+                a.kx[(size_t)h * a.n + i] = cx[h] - L.pdrift[h];
                 a.ky[(size_t)h * a.n + i] = cy[h];
             }
     }

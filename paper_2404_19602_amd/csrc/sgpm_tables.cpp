@@ -134,6 +134,7 @@ const char* build_tables(const sgpm_instance_desc& d, HostTables& t) {
     if (d.precision != SGPM_FP64 && d.precision != SGPM_FP32) return "unknown precision";
     if (d.pauli != 0 && d.pauli != 1) return "pauli must be 0 or 1";
     if (d.final_state != 0 && d.final_state != 1) return "final_state must be 0 or 1";
+    if (d.splitting != 0 && d.splitting != 1) return "splitting must be 0 or 1";
     if (d.gap_mode != 0 && d.gap_mode != 1) return "gap_mode must be 0 or 1";
     if (d.max_steps < 0) return "max_steps must be >= 0";
     if (!std::isfinite(d.field0) || !std::isfinite(d.field_rel) || !std::isfinite(d.fermi_eV))

@@ -115,6 +115,8 @@ def test_init_parity(sg, orc, name):
 
 # ---------------------------------------------------------------- steps
 STEP_CASES = {
+    "strang_sg_gap": (small_cfg(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1,
+                                n_particles=20_001, field0=5e6, splitting=1), 120, 512),
     "det_n1e4": (small_cfg(n_particles=10_000), 300, None),
     "sg_gap_ragged": (small_cfg(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1,
                                 n_particles=20_001, field0=2e6), 120, 512),

@@ -715,3 +715,60 @@ def test_pauli_acceptance_limits_occupation_violations(orc):
         s.run(base["dt"], 30)
         worst[pauli] = int(np.max(np.asarray(s.excess)))
     assert worst[0] > 2 * worst[1], worst
+
+
+# ------------------------------------------------------ Strang splitting
+def test_strang_collisionless_is_the_closed_form_drift(orc):
+    cfg = small(dim_z=1, degree=3, nodes_1d=5, field_dim=0, field_rel=0.2, field0=2e6,
+                n_particles=500, rate_scale=(0.0,) * 6, splitting=1)
+    s = orc.OracleSim(cfg)
+    s.init()
+    kx0, ky0 = s.get_state()
+    s.run(cfg["dt"], 40)
+    kx, ky = s.get_state()
+    t = s.tables()
+    ref = kx0 - 40 * 1e6 * cfg["dt"] * t["ehat"][:, None]
+    assert np.allclose(kx, ref, rtol=0, atol=1e-12 * np.abs(kx0).max())
+    assert np.array_equal(ky, ky0)
+
+
+def test_strang_without_field_is_the_first_order_scheme(orc):
+    base = small(dim_z=1, degree=2, nodes_1d=4, gap_dim=0, gap_rel=0.1, field0=0.0,
+                 n_particles=800, rate_scale=(5.0,) * 6)
+    out = []
+    for sp in (0, 1):
+        s = orc.OracleSim(dict(base, splitting=sp))
+        s.init()
+        s.run(base["dt"], 15)
+        out.append(s.get_state())
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_strang_collides_at_the_half_drifted_state(orc):
+    # acoustic scattering only (elastic) and no Pauli factor: a particle that
+    # collides once keeps |k| at the point where the collision happens, i.e.
+    # |k_final + d/2| = |k_0 - d/2| with Strang and |k_final| = |k_0 - d| with
+    # the first-order splitting, d = v_F E dt x^
+    E, dt = 5e7, 2e-15
+    d = 1e6 * E * dt
+    for sp in (0, 1):
+        cfg = small(n_particles=4000, field0=E, pauli=0, splitting=sp,
+                    rate_scale=(400.0, 0.0, 0.0, 0.0, 0.0, 0.0))
+        s = orc.OracleSim(cfg)
+        s.init()
+        kx0, ky0 = s.get_state()
+        idx = np.arange(4000)
+        kx, ky, nc = s.step_particles(idx, kx0.T, ky0.T, 0, dt)
+        one = nc == 1
+        assert one.sum() > 100
+        a0, b0 = kx0[0][one], ky0[0][one]
+        a, b = kx[one, 0], ky[one, 0]
+        if sp:
+            lhs, rhs = np.hypot(a + d / 2, b), np.hypot(a0 - d / 2, b0)
+        else:
+            lhs, rhs = np.hypot(a, b), np.hypot(a0 - d, b0)
+        assert np.allclose(lhs, rhs, rtol=1e-12), sp
+        # and the other placement does not hold
+        wrong = np.hypot(a, b) if sp else np.hypot(a + d / 2, b)
+        assert not np.allclose(wrong, np.hypot(a0 - d, b0) if sp else np.hypot(a0 - d / 2, b0),
+                               rtol=1e-6)
