@@ -139,6 +139,47 @@ def measured_traffic(kernel: str):
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
 
 
+def uq_timings(cfg: dict, steps: int = 100, n: int = 50_000, samples: int = 256) -> dict:
+    """Sec. 5 Test 4 shapes: Monte Carlo sampling of z with `samples`
+    deterministic runs of n particles (one batched launch per kernel and step)
+    against the sG-PM of the headline workload at the same n, and the rate of
+    the evaluation of the particle expansion at points z."""
+    import numpy as np
+    import torch
+    import paper_2404_19602_amd as sg
+    from paper_2404_19602_amd import uq
+
+    log(f"uq: MC-MC with {samples} samples x {n} particles vs MC-sG, {steps} steps")
+    z = uq.sample_z(samples, 1, 7)
+    cfgs = []
+    for k in range(samples):
+        c = uq.deterministic_at(cfg, z[k])
+        c.update(instance=k, n_particles=n)
+        cfgs.append(c)
+    res = {}
+    for name, cf in (("mc_mc", cfgs), ("mc_sg", dict(cfg, n_particles=n))):
+        sim = sg.Simulation(cf, max_steps=steps + 10)
+        sim.init_particles()
+        sim.step(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[name] = {"ms_per_step": wall * 1e3 / steps, "instances": sim.n_inst}
+        if name == "mc_sg":
+            zz = np.linspace(-1, 1, 256)
+            sim.moments_at(zz[:8])
+            t0 = time.perf_counter()
+            sim.moments_at(zz)
+            res["moments_at_256_points_ms"] = (time.perf_counter() - t0) * 1e3
+        del sim
+    res["cost_ratio_mc_mc_over_mc_sg"] = res["mc_mc"]["ms_per_step"] / res["mc_sg"]["ms_per_step"]
+    res["config"] = {"n_particles": n, "samples": samples, "steps": steps,
+                     "sg_modes": cfg["degree"] + 1, "sg_nodes": cfg["nodes_1d"]}
+    return res
+
+
 def cpu_baseline(cfg: dict):
     """The FP64 oracle on a bounded sample: 50 000 of the particles for 200
     steps, every host thread the box gives this process."""
@@ -171,6 +212,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison run")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance sweep")
     ap.add_argument("--batched-steps", type=int, default=100)
+    ap.add_argument("--no-uq", action="store_true", help="skip the MC-MC / moments-at-z timings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run five plain 256 MiB device copies (calibrates the HBM "
                          "byte counters of a profiler run)")
@@ -263,6 +305,9 @@ def main():
             "kernels": {k: {"avg_ms": ms, "launches": n} for k, (ms, n) in rb["kernels"].items()},
         }
         del rb
+
+    if not args.no_uq:
+        out["uq"] = uq_timings(cfg)
 
     if not args.no_cpu:
         log("CPU oracle baseline")

@@ -38,6 +38,7 @@ struct Instance {
     HostTables t;
     int P = 1, Q = 1, nk = 0;
     int64_t n = 0;
+    int64_t n_all = 0;         // particles of all instances of the context
     bool fp32 = false;
     int64_t chunk = kBlock1;
     int nwg = 1, nb = 1;
@@ -131,9 +132,12 @@ int64_t wg_cap_chunk(int64_t n) {
     return c < kBlock1 ? kBlock1 : c;
 }
 
-int64_t auto_chunk(int64_t n) {
-    // about two stream workgroups per compute unit, whole sub-tiles
-    int64_t c = (n + 511) / 512;
+// n: the instance's particles; n_all: all particles of the context.  About
+// two stream workgroups per compute unit for the whole context (a batch of
+// small instances fills the device once, not once per instance), whole
+// sub-tiles.
+int64_t auto_chunk(int64_t n, int64_t n_all) {
+    int64_t c = (n_all + 511) / 512;
     c = (c + kBlock1 - 1) / kBlock1 * kBlock1;
     if (c < wg_cap_chunk(n)) c = wg_cap_chunk(n);
     if (c > kMaxChunk) c = kMaxChunk;
@@ -142,8 +146,8 @@ int64_t auto_chunk(int64_t n) {
 
 // smallest chunk a launch shape may use: a quarter of the automatic one
 // (bounds the slab region, one window slab per stream workgroup)
-int64_t min_chunk(int64_t n) {
-    int64_t c = auto_chunk(n) / 4 / kBlock1 * kBlock1;
+int64_t min_chunk(int64_t n, int64_t n_all) {
+    int64_t c = auto_chunk(n, n_all) / 4 / kBlock1 * kBlock1;
     if (c < wg_cap_chunk(n)) c = wg_cap_chunk(n);
     return c < kBlock1 ? kBlock1 : c;
 }
@@ -167,7 +171,7 @@ void window_for(int P, int Q, int nk, bool fp32, int chunk, int budget, int* win
     *words = ((Q * w * w + 1) / 2 + 3) / 4 * 4;   // whole 16-byte slab rows
 }
 
-Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
+Layout layout_of(const sgpm_instance_desc& d, const HostTables& t, int64_t n_all) {
     Layout L;
     const size_t n_cand = (size_t)d.n_particles + 32768 + kBlock1;
     const size_t s = d.precision == SGPM_FP32 ? 4 : 8;
@@ -202,7 +206,7 @@ Layout layout_of(const sgpm_instance_desc& d, const HostTables& t) {
     {
         // the smallest chunk has both the most workgroups and the largest window
         int w, r0, l0, words;
-        const int64_t mc = min_chunk(d.n_particles);
+        const int64_t mc = min_chunk(d.n_particles, n_all);
         window_for(t.P, t.Q, d.nk, d.precision == SGPM_FP32, (int)mc, kMaxLdsBudget, &w, &r0, &l0,
                    &words);
         const size_t nwg_slab = (size_t)((d.n_particles + mc - 1) / mc);
@@ -561,7 +565,7 @@ sgpm_status graph_for(sgpm_ctx* c, int steps, hipGraphExec_t* out) {
 // launch shape of the stream kernel: chunk, workgroups, batches and the LDS
 // window that fits beside the chunk's candidate list
 void set_chunk(Instance& I, int64_t chunk) {
-    I.chunk = chunk > 0 ? chunk : auto_chunk(I.n);
+    I.chunk = chunk > 0 ? chunk : auto_chunk(I.n, I.n_all);
     I.nwg = (int)((I.n + I.chunk - 1) / I.chunk);
     I.nb = I.nwg < kNumBatches ? I.nwg : kNumBatches;
     window_for(I.P, I.Q, I.nk, I.fp32, (int)I.chunk, I.lds_budget, &I.win, &I.win_r0, &I.win_l0,
@@ -623,8 +627,8 @@ sgpm_status restore_instance(sgpm_ctx* c, Instance& I, const Saved& S) {
 }
 
 int64_t scaled_chunk(const Instance& I, double f) {
-    int64_t ch = (int64_t)std::llround(auto_chunk(I.n) * f / kBlock1) * kBlock1;
-    ch = std::max<int64_t>(ch, min_chunk(I.n));
+    int64_t ch = (int64_t)std::llround(auto_chunk(I.n, I.n_all) * f / kBlock1) * kBlock1;
+    ch = std::max<int64_t>(ch, min_chunk(I.n, I.n_all));
     return std::min<int64_t>(ch, kMaxChunk);
 }
 
@@ -661,11 +665,13 @@ const char* sgpm_status_string(sgpm_status s) {
 sgpm_status sgpm_workspace_bytes(const sgpm_instance_desc* descs, int32_t n_inst, size_t* bytes) {
     if (!descs || n_inst < 1 || !bytes || n_inst > SGPM_MAX_INSTANCES) return SGPM_EINVAL;
     size_t total = ctx_layout(n_inst).total;
+    int64_t n_all = 0;
+    for (int k = 0; k < n_inst; ++k) n_all += descs[k].n_particles > 0 ? descs[k].n_particles : 0;
     for (int k = 0; k < n_inst; ++k) {
         HostTables t;
         const char* why = build_tables(descs[k], t);
         if (why[0]) return SGPM_EINVAL;
-        total += layout_of(descs[k], t).total;
+        total += layout_of(descs[k], t, n_all).total;
     }
     *bytes = total;
     return SGPM_OK;
@@ -690,6 +696,8 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
     }
     const CtxLayout CL = ctx_layout(n_inst);
     size_t need = CL.total;
+    int64_t n_all = 0;
+    for (int k = 0; k < n_inst; ++k) n_all += descs[k].n_particles > 0 ? descs[k].n_particles : 0;
     for (int k = 0; k < n_inst; ++k) {
         Instance& I = c->inst[k];
         I.d = descs[k];
@@ -699,7 +707,7 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
             delete c;
             return SGPM_EINVAL;
         }
-        need += layout_of(I.d, I.t).total;
+        need += layout_of(I.d, I.t, n_all).total;
     }
     if (!ws || ((uintptr_t)ws & 255) != 0 || ws_bytes < need) {
         fprintf(stderr, "sgpm_create: workspace %p of %zu bytes, need %zu (256-byte aligned)\n", ws,
@@ -742,9 +750,9 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
     for (int k = 0; k < n_inst; ++k) {
         Instance& I = c->inst[k];
         const HostTables& t = I.t;
-        Layout L = layout_of(I.d, t);
+        Layout L = layout_of(I.d, t, n_all);
         auto at = [&](int r) { return base + L.off[r]; };
-        I.P = t.P; I.Q = t.Q; I.nk = I.d.nk; I.n = I.d.n_particles;
+        I.P = t.P; I.Q = t.Q; I.nk = I.d.nk; I.n = I.d.n_particles; I.n_all = n_all;
         I.fp32 = I.d.precision == SGPM_FP32;
         I.hstride = ((int64_t)I.Q * I.nk * I.nk + 63) / 64 * 64;
         I.hmstride = 64 * ((I.Q + 63) / 64);
@@ -887,7 +895,7 @@ sgpm_status sgpm_set_chunk(sgpm_ctx* c, int32_t inst, int32_t chunk) {
     if (chunk < 0 || chunk % kBlock1 != 0 || chunk > kMaxChunk)
         return fail(c, SGPM_EINVAL, "chunk must be a multiple of 256 up to 8192 (0 = automatic)");
     Instance& I = c->inst[inst];
-    if (chunk > 0 && chunk < min_chunk(I.n))
+    if (chunk > 0 && chunk < min_chunk(I.n, I.n_all))
         return fail(c, SGPM_EINVAL,
                     "chunk too small: at least a quarter of the automatic chunk and at most "
                     "4096 stream workgroups");
