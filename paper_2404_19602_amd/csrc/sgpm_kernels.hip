@@ -925,12 +925,20 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
         for (int k = tid; k < a.Q; k += kBlock) hmax_clr[k] = 0u;
         if (tid < 2) a.qc[2 * ((step + 1u) & 1u) + tid] = 0u;
     }
-    // moment record: batch b of node q collects the stream workgroups w = b (mod NB)
-    if (wg < a.Q * nb && tid < 3) {
+    // moment record: batch b of node q collects the stream workgroups w = b (mod NB),
+    // one wave, lane j taking w = b + j nb, b + (j + 64) nb, ...; then a fixed tree
+    if (wg < a.Q * nb && tid < 64) {
         const int q = wg % a.Q, b = wg / a.Q;
-        double sum = 0.0;
-        for (int w = b; w < nwg; w += nb) sum += partial[((size_t)w * a.Q + q) * 3 + tid];
-        record[((size_t)b * a.Q + q) * 3 + tid] = sum;
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+        for (int w = b + tid * nb; w < nwg; w += 64 * nb) {
+            const double* pw = partial + ((size_t)w * a.Q + q) * 3;
+            v0 += pw[0]; v1 += pw[1]; v2 += pw[2];
+        }
+        v0 = wave_sum(v0); v1 = wave_sum(v1); v2 = wave_sum(v2);
+        if (tid == 0) {
+            double* r = record + ((size_t)b * a.Q + q) * 3;
+            r[0] = v0; r[1] = v1; r[2] = v2;
+        }
     }
 }
 
