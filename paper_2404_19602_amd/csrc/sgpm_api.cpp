@@ -28,7 +28,7 @@ namespace {
 constexpr double kECharge = 1.602176634e-19;
 constexpr int kMaxBins = 4096;
 constexpr int kDefaultGraphSteps = 16;
-constexpr int kMaxLdsBudget = 72 * 1024;   // largest window budget the slabs are sized for
+constexpr int kMaxLdsBudget = 80 * 1024;   // largest window budget the slabs are sized for
 constexpr int kMaxGraphSteps = 256;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -133,11 +133,11 @@ int64_t wg_cap_chunk(int64_t n) {
 }
 
 // n: the instance's particles; n_all: all particles of the context.  About
-// two stream workgroups per compute unit for the whole context (a batch of
-// small instances fills the device once, not once per instance), whole
-// sub-tiles.
+// one stream workgroup (eight waves) per compute unit for the whole context
+// (a batch of small instances fills the device once, not once per instance),
+// whole sub-tiles.
 int64_t auto_chunk(int64_t n, int64_t n_all) {
-    int64_t c = (n_all + 511) / 512;
+    int64_t c = (n_all + 255) / 256;
     c = (c + kBlock1 - 1) / kBlock1 * kBlock1;
     if (c < wg_cap_chunk(n)) c = wg_cap_chunk(n);
     if (c > kMaxChunk) c = kMaxChunk;

@@ -17,7 +17,7 @@ constexpr int kMaxQ = 128;           // largest node count
 constexpr int kEdgePts = 32;         // trapezoid points of the edge integral
 constexpr int kEdgeTries = 64;       // edge-angle proposals per collision
 constexpr int kNumBatches = 32;      // batch-means batches of the moment record
-constexpr int kLdsK1Bytes = 72 * 1024;   // default LDS budget of a stream workgroup
+constexpr int kLdsK1Bytes = 80 * 1024;   // default LDS budget of a stream workgroup
 
 // Host FP64 set-up of one instance (Sec. 4.1 tables, Appendix rate constants).
 struct HostTables {
@@ -83,7 +83,7 @@ struct DevTab {
     const Consts<T>* consts;
 };
 
-constexpr int kWaves1 = 4;            // waves per workgroup of the stream kernel
+constexpr int kWaves1 = 8;            // waves per workgroup of the stream kernel
 constexpr int kBlock1 = 64 * kWaves1;
 constexpr int kMaxStreamWG = 4096;    // cap on stream workgroups of one instance (sizes the slabs)
 constexpr int kMaxChunk = 8192;       // cap on particles per stream workgroup (LDS list)

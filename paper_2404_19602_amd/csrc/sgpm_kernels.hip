@@ -35,8 +35,10 @@ __device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2,
                                           uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        // one 32 x 32 -> 64-bit product gives both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t n0 = hi1 ^ c1 ^ k0;
         const uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
@@ -371,22 +373,13 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
 
     // the tiles of this workgroup's chunk; FULL: every lane of every tile holds a
     // particle (all chunks but the last), so the per-lane guards fold away
-    // The next tile's coefficients are loaded while this one is processed.
     auto tiles = [&](auto full) {
         constexpr bool FULL = decltype(full)::value;
-        T cx[PMAX], cy[PMAX];
-        {
-            const int64_t i0 = begin + tid;
-            load_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, (FULL || i0 < end) ? i0 : begin, zero, cx, cy);
-        }
         for (int64_t base = begin; base < end; base += kBlock1) {
             const int64_t i = base + tid;
             const bool act = FULL || i < end;
-            T nx[PMAX], ny[PMAX];
-            if (base + kBlock1 < end) {
-                const int64_t in = i + kBlock1;
-                load_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, (FULL || in < end) ? in : begin, zero, nx, ny);
-            }
+            T cx[PMAX], cy[PMAX];
+            load_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, act ? i : begin, zero, cx, cy);
             bool cand = false;
             if constexpr (QMAX > 0) {
                 // the nodes of one particle
@@ -468,8 +461,6 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
                     L.cbuf[base_slot + pos] = (int)i;
                 }
             }
-#pragma unroll
-            for (int h = 0; h < PMAX; ++h) { cx[h] = nx[h]; cy[h] = ny[h]; }
         }
     };
     if (end - begin == a.chunk) tiles(std::true_type{});

@@ -180,7 +180,7 @@ def test_autotune_keeps_the_run(sg, batched):
             else:
                 assert np.array_equal(after[k], before[j][k]), (j, k)
         shape = tuned.launch_shape(j)
-        assert shape["chunk"] % 256 == 0 and shape["collider_workgroups"] in (512, 1024, 2048)
+        assert shape["chunk"] % 512 == 0 and shape["collider_workgroups"] in (512, 1024, 2048)
     for s in (tuned, plain):
         s.step(12)
     for j in range(n):
