@@ -200,13 +200,19 @@ __device__ __forceinline__ D load_desc(const D* all, int j) {
 }
 
 // Instance of a workgroup of a batched launch: the last j with wg0[j] <= b.
+// wg0 ascends from wg0[0] = 0, so j is the number of entries j' >= 1 with
+// wg0[j'] <= b: every wave counts them with independent loads and ballots
+// (no chain of dependent loads as in a bisection).
 __device__ __forceinline__ int find_slot(const uint32_t* __restrict__ wg0, int n_inst, uint32_t b) {
-    int lo = 0, hi = n_inst - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (b >= wg0[mid]) lo = mid; else hi = mid - 1;
+    const int lane = threadIdx.x & 63;
+    int cnt = 0;
+#pragma unroll 4
+    for (int j0 = 0; j0 < n_inst; j0 += 64) {
+        const int j = j0 + lane;
+        const bool le = j >= 1 && j < n_inst && wg0[j] <= b;
+        cnt += __popcll(__ballot(le));
     }
-    return lo;
+    return cnt;
 }
 
 // ======================================================= K1: stream kernel
@@ -797,29 +803,66 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
 }
 
 // Collider grid of a group.  The passes of all instances, concatenated in
-// instance order, are dealt out round-robin: workgroup b takes global passes
-// b, b + grid, ..., so a group of many small lists spreads like one long
-// list.  Thread 0 of workgroup 0 advances the finalize kernel's copy of the
-// step of every instance (that kernel is done).
+// instance order, are dealt out round-robin.  Workgroup 0 advances the
+// finalize kernel's copy of the step of every instance (that kernel is done).
 template <typename T, int PMAX, int NPL>
 __global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T>* __restrict__ all, int n_inst) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    constexpr int kPer = (SGPM_MAX_INSTANCES + kBlock - 1) / kBlock;   // instances per thread
+    __shared__ uint32_t s_base[SGPM_MAX_INSTANCES + 1];   // first global pass of instance j
+    __shared__ uint32_t s_step[SGPM_MAX_INSTANCES];
+    __shared__ uint32_t s_total[SGPM_MAX_INSTANCES];
+    __shared__ uint32_t s_scan[kBlock];
+    typedef const __attribute__((address_space(4))) K2Args<T> CA;
     const uint32_t grid = gridDim.x;
-    uint32_t base = 0;            // global index of instance j's first pass
-    uint32_t next = blockIdx.x;   // this workgroup's next global pass
-    for (int j = 0; j < n_inst; ++j) {
-        const K2Args<T> a = load_desc(all, j);
-        const uint32_t step = a.dyn->step_k2;
-        if (blockIdx.x == 0 && threadIdx.x == 0) a.dyn->step_k3 = step + 1u;
-        const uint32_t total = a.qc[2 * (step & 1u)];
-        const uint32_t per_pass = (uint32_t)(kBlock / a.G);
-        const uint32_t passes = (total + per_pass - 1) / per_pass;
-        if (next < base + passes) {
-            const uint32_t first = next - base;
-            k2_instance<T, PMAX, NPL>(a, smem, step, total, first, grid);
-            next += (passes - first + grid - 1) / grid * grid;
+    const int tid = threadIdx.x;
+    // every instance's step, list length and pass count, read in parallel
+    uint32_t loc[kPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int j = tid * kPer + u;
+        uint32_t passes = 0;
+        if (j < n_inst) {
+            Dyn* dyn = ((CA*)all)[j].dyn;
+            const uint32_t step = dyn->step_k2;
+            const uint32_t total = ((CA*)all)[j].qc[2 * (step & 1u)];
+            const uint32_t per_pass = (uint32_t)(kBlock / ((CA*)all)[j].G);
+            passes = (total + per_pass - 1) / per_pass;
+            s_step[j] = step;
+            s_total[j] = total;
+            if (blockIdx.x == 0) dyn->step_k3 = step + 1u;   // the finalize kernel is done
         }
-        base += passes;
+        loc[u] = passes;
+        sum += passes;
+    }
+    // exclusive prefix sums of the pass counts (instances concatenated in order)
+    s_scan[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const uint32_t v = tid >= off ? s_scan[tid - off] : 0u;
+        __syncthreads();
+        s_scan[tid] += v;
+        __syncthreads();
+    }
+    uint32_t run = s_scan[tid] - sum;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int j = tid * kPer + u;
+        if (j < n_inst) s_base[j] = run;
+        run += loc[u];
+    }
+    if (tid == 0) s_base[n_inst] = s_scan[kBlock - 1];
+    __syncthreads();
+    // The global passes b, b + grid, ... of the concatenation belong to this
+    // workgroup (b = blockIdx.x), so a group of many small lists spreads like
+    // one long list.  Its first pass in instance j is r = (b - base_j) mod grid.
+    for (int j = 0; j < n_inst; ++j) {
+        const uint32_t base = s_base[j], passes = s_base[j + 1] - base;
+        const uint32_t r = (blockIdx.x + grid - base % grid) % grid;
+        if (r >= passes) continue;
+        const K2Args<T> a = load_desc(all, j);
+        k2_instance<T, PMAX, NPL>(a, smem, s_step[j], s_total[j], r, grid);
     }
 }
 
