@@ -158,7 +158,7 @@ def uq_timings(cfg: dict, steps: int = 100, n: int = 50_000, samples: int = 256)
         cfgs.append(c)
     res = {}
     for name, cf in (("mc_mc", cfgs), ("mc_sg", dict(cfg, n_particles=n))):
-        sim = sg.Simulation(cf, max_steps=steps + 10)
+        sim = sg.Simulation(cf, max_steps=steps + 30)
         sim.init_particles()
         sim.step(10)
         torch.cuda.synchronize()
@@ -166,7 +166,12 @@ def uq_timings(cfg: dict, steps: int = 100, n: int = 50_000, samples: int = 256)
         sim.step(steps)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        res[name] = {"ms_per_step": wall * 1e3 / steps, "instances": sim.n_inst}
+        sim.set_profiling(True)
+        sim.step(20)
+        kt = sim.kernel_times()
+        sim.set_profiling(False)
+        res[name] = {"ms_per_step": wall * 1e3 / steps, "instances": sim.n_inst,
+                     "kernels_us": {k: round(v[0] * 1e3, 2) for k, v in kt.items()}}
         if name == "mc_sg":
             zz = np.linspace(-1, 1, 256)
             sim.moments_at(zz[:8])

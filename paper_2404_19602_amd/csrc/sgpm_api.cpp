@@ -387,6 +387,19 @@ K2Args<T> make_k2(const sgpm_ctx* cx, const Instance& I) {
     return a;
 }
 
+// Window blocks per finalize workgroup: a block sums kK3Words words of every
+// slab, so with few stream workgroups one finalize workgroup takes several
+// blocks (about 64 slab rows each), with many it takes one.
+int k3_fold(const Instance& I) {
+    const int f = (64 + I.nwg - 1) / I.nwg;
+    return f < 1 ? 1 : (f > 16 ? 16 : f);
+}
+
+int k3_win_wg(const Instance& I) {
+    const int per = kK3Words * k3_fold(I);
+    return (I.hwin_words + per - 1) / per;
+}
+
 K3Args make_k3(const sgpm_ctx* cx, const Instance& I) {
     K3Args a;
     std::memset(&a, 0, sizeof(a));
@@ -397,7 +410,8 @@ K3Args make_k3(const sgpm_ctx* cx, const Instance& I) {
     a.H = I.H; a.Hmax = I.Hmax;
     a.hstride = I.hstride; a.hmstride = I.hmstride;
     a.qc = I.qc;
-    a.n_win_wg = (I.hwin_words + kK3Words - 1) / kK3Words;
+    a.fold = k3_fold(I);
+    a.n_win_wg = k3_win_wg(I);
     a.nwg = I.nwg; a.nb = I.nb;
     a.partial = I.partial;
     a.record = I.record;
@@ -408,7 +422,7 @@ K3Args make_k3(const sgpm_ctx* cx, const Instance& I) {
 }
 
 int k3_grid(const Instance& I) {
-    return k3_grid_of(I.Q, I.nk, (I.hwin_words + kK3Words - 1) / kK3Words, I.nb);
+    return k3_grid_of(I.Q, I.nk, k3_win_wg(I), I.nb);
 }
 
 // workgroup tables: group tables of K1, K3 and single-instance tables of K1, K3

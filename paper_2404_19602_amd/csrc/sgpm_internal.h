@@ -163,7 +163,7 @@ struct K2Args {
 // the moment record of t^n, and the reset of the next step's counters.
 constexpr int kK3Words = 64;      // window words per finalize workgroup
 constexpr int kK3Lanes = 16;      // slab lanes per column of four words
-constexpr int kK3Rest = 256;      // cells per workgroup of the outside part
+constexpr int kK3Rest = 2048;     // cells per workgroup of the outside part
 
 struct K3Args {
     int Q, nk;
@@ -176,7 +176,7 @@ struct K3Args {
     uint32_t* qc;           // [2][2] counters by step parity
     int n_win_wg;           // workgroups of the window part
     int nwg, nb;            // stream workgroups and moment batches
-    int pad;
+    int fold;               // window blocks of kK3Words words per workgroup
     const double* partial;  // [nwg][Q][3]
     double* record;         // [max_steps + 1][nb][Q][3]
     Dyn* dyn;

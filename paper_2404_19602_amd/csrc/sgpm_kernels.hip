@@ -894,11 +894,13 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
     __shared__ uint32_t scap[kMaxQ], sex[kMaxQ];
     for (int k = tid; k < a.Q; k += kBlock) { smax[k] = 0u; scap[k] = a.cap[k]; sex[k] = 0u; }
     __syncthreads();
-    if (wg < a.n_win_wg) {
+    // window blocks wg * fold, ..., wg * fold + fold - 1
+    for (int blk = 0; wg < a.n_win_wg && blk < a.fold; ++blk) {
+        const int wb = wg * a.fold + blk;
         // 16 columns of four words, kK3Lanes slab lanes; 16-byte loads
         const int col = tid % (kK3Words / 4);
         const int lane = tid / (kK3Words / 4);
-        const int word0 = wg * kK3Words + 4 * col;
+        const int word0 = wb * kK3Words + 4 * col;
         uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
         if (word0 < a.hwin_words) {
             const uint32_t* src = a.slabs + word0;
@@ -916,7 +918,7 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
         __syncthreads();
         if (tid < 2 * kK3Words) {
             const int wl = tid >> 1, half = tid & 1;
-            const int word = wg * kK3Words + wl;
+            const int word = wb * kK3Words + wl;
             uint32_t sum = 0u;
 #pragma unroll
             for (int k = 0; k < kK3Lanes; ++k) sum += part[k][wl][half];
@@ -932,7 +934,9 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
                 if (sum > scap[q]) atomicAdd(&sex[q], sum - scap[q]);
             }
         }
-    } else {
+        __syncthreads();   // part[] is rewritten by the next block
+    }
+    if (wg >= a.n_win_wg) {
         const int64_t c0 = (int64_t)(wg - a.n_win_wg) * kK3Rest;
         const int64_t total = (int64_t)a.Q * cells;
         for (int64_t g = c0 + tid; g < c0 + kK3Rest && g < total; g += kBlock) {
