@@ -186,15 +186,15 @@ def uq_timings(cfg: dict, steps: int = 100, n: int = 50_000, samples: int = 256)
 
 
 def cpu_baseline(cfg: dict):
-    """The FP64 oracle on a bounded sample: 50 000 of the particles for 200
-    steps, every host thread the box gives this process."""
+    """The FP64 oracle on a bounded sample: 200 000 of the particles for 200
+    steps (about ten seconds), every host thread this process may use."""
     import oracle
     try:
         threads = len(os.sched_getaffinity(0))
     except AttributeError:
         threads = os.cpu_count() or 1
     threads = max(1, min(threads, int(os.environ.get("OMP_NUM_THREADS", threads))))
-    n_s, steps_s = 50_000, 200
+    n_s, steps_s = 200_000, 200
     scfg = dict(cfg, n_particles=n_s)
     sim = oracle.OracleSim(scfg, threads=threads)
     sim.init()
@@ -223,8 +223,8 @@ def main():
                          "byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); how the "
-              "path would shard over several GPUs is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs the step on one GPU (asked for {args.gpus}); the path is not "
+              "sharded over several GPUs", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -63,7 +63,7 @@ typedef enum {
     SGPM_EWORKSPACE = 3,   /* workspace missing, too small or misaligned    */
     SGPM_EDEVICE = 4,      /* a HIP call failed (context is now poisoned)   */
     SGPM_ESTATE = 5,       /* call not valid in the current state           */
-    SGPM_EUNSUPPORTED = 6  /* combination not supported by this build       */
+    SGPM_EUNSUPPORTED = 6  /* combination the library does not support     */
 } sgpm_status;
 
 typedef enum { SGPM_FP64 = 0, SGPM_FP32 = 1 } sgpm_precision;

@@ -64,8 +64,9 @@ static const double A_EDGE = 1.0e-10;         /* 1e-8 cm -> m               */
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), from its published     */
-/* definition.  Counter layout (fixed by this build, shared by definition    */
-/* only): c0 = particle, c1 = step (0xFFFFFFFF during initialisation),       */
+/* definition.  Counter layout (a convention of this code, which the GPU     */
+/* path follows by definition only): c0 = particle, c1 = step (0xFFFFFFFF   */
+/* during initialisation),                                                   */
 /* c2 = (collision << 8) | purpose, c3 = instance; key = seed.               */
 /* ------------------------------------------------------------------------ */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])

@@ -147,8 +147,8 @@ const char* build_tables(const sgpm_instance_desc& d, HostTables& t) {
     t.nodes_1d = d.dim_z == 0 ? 1 : d.nodes_1d;
     t.P = num_modes(d.dim_z, d.degree);
     t.Q = d.dim_z == 0 ? 1 : (d.dim_z == 1 ? t.nodes_1d : t.nodes_1d * t.nodes_1d);
-    if (t.P > kMaxP) return "too many gPC modes for this build (P <= 32)";
-    if (t.Q > kMaxQ) return "too many nodes for this build (Q <= 128)";
+    if (t.P > kMaxP) return "too many gPC modes (the kernels take P <= 32)";
+    if (t.Q > kMaxQ) return "too many nodes (the kernels take Q <= 128)";
     const int P = t.P, Q = t.Q, n1 = t.nodes_1d;
 
     std::vector<double> gx(n1), gw(n1);
