@@ -1,0 +1,75 @@
+"""Host logic of bench.py (no GPU): the one-GPU contract, the algorithmic
+byte model of each step kernel, the choice of the dominant kernel for the
+roofline, and the rule that measured traffic is reported only for the kernel
+sources it was taken on."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def headline():
+    from workloads import workload
+    return workload("sg_gap_m5_q8_n1e6")
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+    assert p.stdout.strip() == ""
+
+
+def test_kernel_bytes_of_the_headline_workload():
+    cfg = headline()
+    N, P, Q, nk = cfg["n_particles"], 6, 8, cfg.get("nk", 240)
+    cand = 15_696
+    b = bench.kernel_bytes(cfg, P, Q, n_drift=1, cand=cand)
+    # every coefficient read once; the drifted mode written for the non-candidates
+    assert b["stream"] == 2 * P * 8 * N + (N - cand) * 1 * 8
+    # H^n written and the overflow grid cleared
+    assert b["finalize"] == 2 * Q * nk * nk * 4
+    # the candidates' coefficients read and written
+    assert b["collide"] == cand * 4 * P * 8
+    b32 = bench.kernel_bytes(dict(cfg, precision="fp32"), P, Q, n_drift=1, cand=cand)
+    assert b32["stream"] * 2 == b["stream"] and b32["collide"] * 2 == b["collide"]
+
+
+def test_roofline_is_the_dominant_kernel():
+    cfg = headline()
+    r = {"n_drift": 1, "cand": (15_696.0,),
+         "kernels": {"stream": (0.050, 200), "finalize": (0.012, 200), "collide": (0.045, 200)}}
+    roof, per = bench.roofline_of(cfg, r, 6, 8)
+    assert roof["kernel"] == "sgpm::k1_stream"
+    assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
+    want = per["stream"]["bytes_per_launch"] / 50e-6 / 1e9
+    assert roof["achieved"] == pytest.approx(want)
+    assert roof["frac"] == pytest.approx(want / 8000.0)
+    r["kernels"]["collide"] = (0.060, 200)
+    roof, _ = bench.roofline_of(cfg, r, 6, 8)
+    assert roof["kernel"] == "sgpm::k2_collide"
+
+
+def test_traffic_only_for_the_profiled_sources(monkeypatch):
+    with open(bench.TRAFFIC_FILE) as fh:
+        rec = json.load(fh)
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "not the profiled sources")
+    assert bench.measured_traffic("stream") is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: rec["source_sha256"])
+    k = rec["kernels"]["stream"]
+    assert bench.measured_traffic("stream") == k["fetch_bytes"] + k["write_bytes"]
+    # the calibration factors of a plain copy are recorded beside the figures
+    assert rec["calibration"]["fetch_factor"] > 0 and rec["calibration"]["write_factor"] > 0
+
+
+def test_entry_points_exist():
+    import __graft_entry__ as e
+    assert callable(e.build) and callable(e.smoke)
