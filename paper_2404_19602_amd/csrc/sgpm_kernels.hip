@@ -1,23 +1,29 @@
 // gfx950 kernels of the sG-PM hot path (arXiv:2404.19602, Algorithm 2).
 //
-// One time step of one instance is three launches:
-//  K1 stream   -- lane per particle over a chunk per workgroup: Galerkin drift
-//                 (Sec. 4.1), an upper bound of the node-maximum collision
-//                 rate from the coefficients (eq. deltat) that proves most
-//                 particles do not collide in this step; for those, the node
-//                 values k_i(z_q) (eq. gPC), their cells in H^{n+1} through a
-//                 privatised LDS window, and FP64 sums of v_x, v_y and the
-//                 energy per node (Sec. 4.2).  The others are listed, in a
-//                 fixed order, as collision candidates.
-//  K2 collide  -- the candidates of one K1 workgroup, a group of lanes per
-//                 candidate and one node per lane: exact node rates, the
-//                 node maximum, free flight, mechanism selection (eq.
-//                 update_gPC), final states, Pauli acceptance against H^n on
-//                 the moved grid (eq. Pauli_gPC) and the projection of eq.
-//                 update_sG as a group sum; then their H^{n+1} cells and sums.
-//  K3 finalize -- one workgroup per node: the maximum of H^{n+1}, clearing of
-//                 the stale buffer for the next step, and the fixed-order
-//                 reduction of the moment sums into the record.
+// One time step n of a group of instances is three launches, in this order:
+//  K1 stream   -- a lane per particle, a chunk of particles per 512-thread
+//                 workgroup.  For every particle: the node values k_i(z_q)
+//                 of the state at t^n (eq. gPC), their cells in H^n through
+//                 a privatised LDS window (flushed as one slab per
+//                 workgroup, overflow cells by global atomics), and FP64
+//                 sums of v_x, v_y and the energy per node (Sec. 4.2).  Then
+//                 the Galerkin drift (Sec. 4.1) and an upper bound of the
+//                 node-maximum collision rate (eq. deltat) that proves most
+//                 particles do not collide in this step: those write back
+//                 their drifted modes, the others are listed as candidates.
+//  K3 finalize -- H^n from the slabs and the overflow grid, its maximum per
+//                 node, the occupancy excess, the fixed-order reduction of
+//                 the moment sums into the record of t^n, and the clearing
+//                 of the next step's counters and stale buffers.
+//  K2 collide  -- the candidates, a group of lanes per candidate and one
+//                 node per lane: exact node rates, the node maximum, free
+//                 flight, mechanism selection (eq. update_gPC), final states,
+//                 Pauli acceptance against H^n on the moved grid (eq.
+//                 Pauli_gPC) and the projection of eq. update_sG as a group
+//                 sum, repeated while the flight ends inside the step; then
+//                 the candidate's modes are written back.
+// Each kernel reads its own copy of the step counter in device memory and
+// advances the copy of the kernel that runs after it (struct Dyn).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
