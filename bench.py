@@ -185,6 +185,44 @@ def uq_timings(cfg: dict, steps: int = 100, n: int = 50_000, samples: int = 256)
     return res
 
 
+OTHER_CONFIGS = (("gnr_det_n1e4", ("fp64",)),
+                 ("sg_gap_field_td4_q64_n4e6", ("fp64", "fp32")),
+                 ("sg_gap_m8_q12_n3e7", ("fp64", "fp32")))
+
+
+def other_configs(steps: int = 50) -> dict:
+    """The other workloads at their full sizes, each with its autotuned launch
+    shape: wall time per step of `steps` graph-replayed steps after 10 warm-up
+    steps, in particle-node updates per second."""
+    import torch
+    import paper_2404_19602_amd as sg
+    from workloads import workload
+
+    res = {}
+    for name, precs in OTHER_CONFIGS:
+        res[name] = {}
+        for prec in precs:
+            cfg = workload(name, precision=prec)
+            log(f"{name} {prec}: 10 warm-up + autotune + {steps} timed steps")
+            sim = sg.Simulation(cfg, max_steps=steps + 40)
+            sim.init_particles()
+            sim.step(10, cfg["dt"])
+            sim.autotune(trial_steps=5, dt=cfg["dt"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(steps, cfg["dt"])
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            P, Q = sim.sizes[0]
+            res[name][prec] = {"ms_per_step": wall * 1e3 / steps,
+                               "value": cfg["n_particles"] * Q * steps / wall,
+                               "unit": "particle-node updates/s", "n_particles": cfg["n_particles"],
+                               "gpc_modes": P, "nodes": Q, "chunk": sim.launch_shape(0)["chunk"]}
+            del sim
+            torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(cfg: dict):
     """The FP64 oracle on a bounded sample: 200 000 of the particles for 200
     steps (about ten seconds), every host thread this process may use."""
@@ -218,6 +256,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance sweep")
     ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--no-uq", action="store_true", help="skip the MC-MC / moments-at-z timings")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the timings of the other workloads at full size")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run five plain 256 MiB device copies (calibrates the HBM "
                          "byte counters of a profiler run)")
@@ -313,6 +353,9 @@ def main():
 
     if not args.no_uq:
         out["uq"] = uq_timings(cfg)
+
+    if not args.no_configs:
+        out["other_configs"] = other_configs()
 
     if not args.no_cpu:
         log("CPU oracle baseline")

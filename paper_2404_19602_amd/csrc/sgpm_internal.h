@@ -139,7 +139,7 @@ struct K1Args {
 };
 
 // Collider kernel: a group of G lanes per candidate, one node per lane;
-// candidates pulled from each instance's list by its work counter.
+// the passes of the instances' candidate lists dealt out round-robin.
 template <typename T>
 struct K2Args {
     T* kx;
