@@ -670,16 +670,38 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
                     T run = (T)0;
 #pragma unroll
                     for (int m = 0; m < 5; ++m) { run += r[m]; cum[j][m] = run; }
-                    run += edge_rate<T>(c, L.ecos, L.cedge[q], L.eps0[q], nkx[j], nky[j], ne[j]);
+                    // first an upper bound of the edge rate: every trapezoid
+                    // term is at most 1, so the integral is at most 2 pi
+                    run += (ne[j] - L.eps0[q] >= (T)0)
+                               ? L.cedge[q] * ne[j] * ((T)kEdgePts * Num<T>::trap) : (T)0;
+                    smax = run > smax ? run : smax;
+                }
+            }
+            smax = group_max<T>(smax, G);
+            const Words wx = philox10(ctr0, step, (coll << 8) | kPurXi, a.instance, a.seed_lo,
+                                      a.seed_hi);
+            const T lxi = -dlog(uni<T>(wx.w0, wx.w1));
+            // A flight that ends past the step under the bound of Gamma~ ends
+            // past it under Gamma~: the bound's sums, maximum, product and the
+            // division are each monotone in rounding, and the margin covers a
+            // different rounding of the exact sum.  So the decision is the one
+            // of the exact rates, and the edge integral (17 exponentials per
+            // node) is evaluated only when the flight may end inside the step.
+            if (!(tc + lxi / (c.alpha1 * smax * ((T)1 + (T)16 * Num<T>::eps)) < dt)) break;
+            smax = (T)0;
+#pragma unroll
+            for (int j = 0; j < NPL; ++j) {
+                const int q = g + j * G;
+                if (q < Q) {
+                    const T run = cum[j][4] + edge_rate<T>(c, L.ecos, L.cedge[q], L.eps0[q],
+                                                           nkx[j], nky[j], ne[j]);
                     cum[j][5] = run;
                     smax = run > smax ? run : smax;
                 }
             }
             smax = group_max<T>(smax, G);
             const T Gt = c.alpha1 * smax;
-            const Words wx = philox10(ctr0, step, (coll << 8) | kPurXi, a.instance, a.seed_lo,
-                                      a.seed_hi);
-            const T dtc = -dlog(uni<T>(wx.w0, wx.w1)) / Gt;   // eq. dt, node maximum
+            const T dtc = lxi / Gt;   // eq. dt, node maximum
             if (!(tc + dtc < dt)) break;
             if (g == 0) atomicAdd(&L.cnt[SGPM_CNT_COLLISIONS], 1u);
 
@@ -812,7 +834,7 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
 // instance order, are dealt out round-robin.  Workgroup 0 advances the
 // finalize kernel's copy of the step of every instance (that kernel is done).
 template <typename T, int PMAX, int NPL>
-__global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T>* __restrict__ all, int n_inst) {
+__device__ __forceinline__ void k2_body(const K2Args<T>* __restrict__ all, int n_inst) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     constexpr int kPer = (SGPM_MAX_INSTANCES + kBlock - 1) / kBlock;   // instances per thread
     __shared__ uint32_t s_base[SGPM_MAX_INSTANCES + 1];   // first global pass of instance j
@@ -870,6 +892,27 @@ __global__ void __launch_bounds__(kBlock) k2_collide(const K2Args<T>* __restrict
         const K2Args<T> a = load_desc(all, j);
         k2_instance<T, PMAX, NPL>(a, smem, s_step[j], s_total[j], r, grid);
     }
+}
+
+// Compiled for three waves per SIMD (at most 168 VGPRs, so three workgroups
+// share a compute unit, which the throughput of the collisions depends on)
+// where that costs at most a few spilled registers: FP32, and FP64 up to six
+// modes with one node per lane.  The others keep their registers (wide).
+template <typename T, int PMAX, int NPL>
+struct K2Narrow {
+    static constexpr bool value = sizeof(T) == 4 || (PMAX <= 6 && NPL == 1);
+};
+
+template <typename T, int PMAX, int NPL>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+k2_collide(const K2Args<T>* __restrict__ all, int n_inst) {
+    k2_body<T, PMAX, NPL>(all, n_inst);
+}
+
+template <typename T, int PMAX, int NPL>
+__global__ void __launch_bounds__(kBlock) k2_collide_wide(const K2Args<T>* __restrict__ all,
+                                                          int n_inst) {
+    k2_body<T, PMAX, NPL>(all, n_inst);
 }
 
 // ===================================================== K3: finalize kernel
@@ -1033,17 +1076,25 @@ int launch_k1(int fp32, int pmax, int qmax, const void* args, const uint32_t* wg
     return launch_k1_any<double>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream);
 }
 
+template <typename T, int PMAX, int NPL>
+static void launch_k2_p(const K2Args<T>* a, int n_inst, dim3 g, size_t lds, hipStream_t s) {
+    if constexpr (K2Narrow<T, PMAX, NPL>::value)
+        hipLaunchKernelGGL((k2_collide<T, PMAX, NPL>), g, dim3(kBlock), lds, s, a, n_inst);
+    else
+        hipLaunchKernelGGL((k2_collide_wide<T, PMAX, NPL>), g, dim3(kBlock), lds, s, a, n_inst);
+}
+
 template <typename T, int NPL>
 static int launch_k2_n(int pmax, const K2Args<T>* a, int n_inst, unsigned grid, size_t lds,
                        hipStream_t s) {
-    const dim3 g(grid), blk(kBlock);
+    const dim3 g(grid);
     switch (pmax) {
-    case 1: hipLaunchKernelGGL((k2_collide<T, 1, NPL>), g, blk, lds, s, a, n_inst); break;
-    case 3: hipLaunchKernelGGL((k2_collide<T, 3, NPL>), g, blk, lds, s, a, n_inst); break;
-    case 6: hipLaunchKernelGGL((k2_collide<T, 6, NPL>), g, blk, lds, s, a, n_inst); break;
-    case 9: hipLaunchKernelGGL((k2_collide<T, 9, NPL>), g, blk, lds, s, a, n_inst); break;
-    case 16: hipLaunchKernelGGL((k2_collide<T, 16, NPL>), g, blk, lds, s, a, n_inst); break;
-    default: hipLaunchKernelGGL((k2_collide<T, 32, NPL>), g, blk, lds, s, a, n_inst); break;
+    case 1: launch_k2_p<T, 1, NPL>(a, n_inst, g, lds, s); break;
+    case 3: launch_k2_p<T, 3, NPL>(a, n_inst, g, lds, s); break;
+    case 6: launch_k2_p<T, 6, NPL>(a, n_inst, g, lds, s); break;
+    case 9: launch_k2_p<T, 9, NPL>(a, n_inst, g, lds, s); break;
+    case 16: launch_k2_p<T, 16, NPL>(a, n_inst, g, lds, s); break;
+    default: launch_k2_p<T, 32, NPL>(a, n_inst, g, lds, s); break;
     }
     return (int)hipGetLastError();
 }
