@@ -841,6 +841,8 @@ __device__ __forceinline__ void k2_body(const K2Args<T>* __restrict__ all, int n
     __shared__ uint32_t s_step[SGPM_MAX_INSTANCES];
     __shared__ uint32_t s_total[SGPM_MAX_INSTANCES];
     __shared__ uint32_t s_scan[kBlock];
+    __shared__ uint32_t s_list[SGPM_MAX_INSTANCES];   // instances holding a pass of this workgroup
+    __shared__ uint32_t s_nlist;
     typedef const __attribute__((address_space(4))) K2Args<T> CA;
     const uint32_t grid = gridDim.x;
     const int tid = threadIdx.x;
@@ -880,15 +882,30 @@ __device__ __forceinline__ void k2_body(const K2Args<T>* __restrict__ all, int n
         if (j < n_inst) s_base[j] = run;
         run += loc[u];
     }
-    if (tid == 0) s_base[n_inst] = s_scan[kBlock - 1];
+    if (tid == 0) {
+        s_base[n_inst] = s_scan[kBlock - 1];
+        s_nlist = 0u;
+    }
     __syncthreads();
     // The global passes b, b + grid, ... of the concatenation belong to this
     // workgroup (b = blockIdx.x), so a group of many small lists spreads like
-    // one long list.  Its first pass in instance j is r = (b - base_j) mod grid.
-    for (int j = 0; j < n_inst; ++j) {
-        const uint32_t base = s_base[j], passes = s_base[j + 1] - base;
-        const uint32_t r = (blockIdx.x + grid - base % grid) % grid;
-        if (r >= passes) continue;
+    // one long list.  Its first pass in instance j is r = (b - base_j) mod grid;
+    // the instances where that pass exists are listed in parallel (in any order:
+    // the instances share nothing but this workgroup's LDS, restaged for each).
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int j = tid * kPer + u;
+        if (j < n_inst) {
+            const uint32_t base = s_base[j], passes = s_base[j + 1] - base;
+            const uint32_t r = (blockIdx.x + grid - base % grid) % grid;
+            if (r < passes) s_list[atomicAdd(&s_nlist, 1u)] = (uint32_t)j;
+        }
+    }
+    __syncthreads();
+    const uint32_t nlist = s_nlist;
+    for (uint32_t t = 0; t < nlist; ++t) {
+        const int j = (int)s_list[t];
+        const uint32_t r = (blockIdx.x + grid - s_base[j] % grid) % grid;
         const K2Args<T> a = load_desc(all, j);
         k2_instance<T, PMAX, NPL>(a, smem, s_step[j], s_total[j], r, grid);
     }
