@@ -396,7 +396,8 @@ int k3_fold(const Instance& I) {
 }
 
 int k3_win_wg(const Instance& I) {
-    const int per = kK3Words * k3_fold(I);
+    // few slabs: kBlock threads of four words each; else fold blocks of kK3Words
+    const int per = I.nwg <= kK3Direct ? 4 * kBlock : kK3Words * k3_fold(I);
     return (I.hwin_words + per - 1) / per;
 }
 

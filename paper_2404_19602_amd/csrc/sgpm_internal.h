@@ -164,6 +164,7 @@ struct K2Args {
 constexpr int kK3Words = 64;      // window words per finalize workgroup
 constexpr int kK3Lanes = 16;      // slab lanes per column of four words
 constexpr int kK3Rest = 2048;     // cells per workgroup of the outside part
+constexpr int kK3Direct = 16;     // at most this many slabs: a thread sums whole words itself
 
 struct K3Args {
     int Q, nk;

@@ -960,8 +960,48 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
     __shared__ uint32_t scap[kMaxQ], sex[kMaxQ];
     for (int k = tid; k < a.Q; k += kBlock) { smax[k] = 0u; scap[k] = a.cap[k]; sex[k] = 0u; }
     __syncthreads();
-    // window blocks wg * fold, ..., wg * fold + fold - 1
-    for (int blk = 0; wg < a.n_win_wg && blk < a.fold; ++blk) {
+    if (nwg <= kK3Direct && wg < a.n_win_wg) {
+        // few slabs: a thread sums its four words of every slab itself, then
+        // settles its eight cells, their overflow counts loaded together
+        const int word0 = (wg * kBlock + tid) * 4;
+        if (word0 < a.hwin_words) {
+            uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
+            const uint32_t* src = a.slabs + word0;
+#pragma unroll 4
+            for (int sl = 0; sl < nwg; ++sl) {
+                const uint4 v = *reinterpret_cast<const uint4*>(src + (size_t)sl * a.hwin_words);
+                lo[0] += v.x & 0xFFFFu; hi[0] += v.x >> 16;
+                lo[1] += v.y & 0xFFFFu; hi[1] += v.y >> 16;
+                lo[2] += v.z & 0xFFFFu; hi[2] += v.z >> 16;
+                lo[3] += v.w & 0xFFFFu; hi[3] += v.w >> 16;
+            }
+            size_t gc[8];
+            int qc[8];
+            uint32_t ex[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int idx = 2 * word0 + k;          // cell k of the thread's four words
+                const bool ok = idx < a.Q * wcells;
+                const int q = ok ? idx / wcells : 0, rem = idx - q * wcells;
+                const int r = a.win_r0 + rem / a.win, l = a.win_l0 + rem % a.win;
+                qc[k] = ok ? q : -1;
+                gc[k] = (size_t)q * cells + (size_t)r * a.nk + l;
+                ex[k] = ok ? a.extra[gc[k]] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (qc[k] < 0) continue;
+                const uint32_t sum = ((k & 1) ? hi[k >> 1] : lo[k >> 1]) + ex[k];
+                a.extra[gc[k]] = 0u;
+                h_out[gc[k]] = sum;
+                if (sum) atomicMax(&smax[qc[k]], sum);
+                if (sum > scap[qc[k]]) atomicAdd(&sex[qc[k]], sum - scap[qc[k]]);
+            }
+        }
+    }
+    // many slabs: window blocks wg * fold, ..., wg * fold + fold - 1, the slabs
+    // split over kK3Lanes lanes and summed through LDS
+    for (int blk = 0; nwg > kK3Direct && wg < a.n_win_wg && blk < a.fold; ++blk) {
         const int wb = wg * a.fold + blk;
         // 16 columns of four words, kK3Lanes slab lanes; 16-byte loads
         const int col = tid % (kK3Words / 4);
@@ -1003,18 +1043,32 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
         __syncthreads();   // part[] is rewritten by the next block
     }
     if (wg >= a.n_win_wg) {
+        // kK3Rest cells outside the window, kK3Rest / kBlock per thread, their
+        // overflow counts loaded together
+        constexpr int kPer = kK3Rest / kBlock;
         const int64_t c0 = (int64_t)(wg - a.n_win_wg) * kK3Rest;
         const int64_t total = (int64_t)a.Q * cells;
-        for (int64_t g = c0 + tid; g < c0 + kK3Rest && g < total; g += kBlock) {
-            const int q = (int)(g / cells), rem = (int)(g - (int64_t)q * cells);
+        int qc[kPer];
+        uint32_t v[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int64_t g = c0 + tid + (int64_t)u * kBlock;
+            const int q = g < total ? (int)(g / cells) : 0;
+            const int rem = (int)(g - (int64_t)q * cells);
             const int r = rem / a.nk, l = rem - r * a.nk;
             const int wr = r - a.win_r0, wl = l - a.win_l0;
-            if ((unsigned)wr < (unsigned)a.win && (unsigned)wl < (unsigned)a.win) continue;
-            const uint32_t v = a.extra[g];
+            const bool inwin = (unsigned)wr < (unsigned)a.win && (unsigned)wl < (unsigned)a.win;
+            qc[u] = (g < total && !inwin) ? q : -1;
+            v[u] = qc[u] >= 0 ? a.extra[g] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            if (qc[u] < 0) continue;
+            const int64_t g = c0 + tid + (int64_t)u * kBlock;
             a.extra[g] = 0u;
-            h_out[g] = v;
-            if (v) atomicMax(&smax[q], v);
-            if (v > scap[q]) atomicAdd(&sex[q], v - scap[q]);
+            h_out[g] = v[u];
+            if (v[u]) atomicMax(&smax[qc[u]], v[u]);
+            if (v[u] > scap[qc[u]]) atomicAdd(&sex[qc[u]], v[u] - scap[qc[u]]);
         }
     }
     __syncthreads();
