@@ -30,6 +30,7 @@ constexpr int kMaxBins = 4096;
 constexpr int kDefaultGraphSteps = 16;
 constexpr int kMaxLdsBudget = 80 * 1024;   // largest window budget the slabs are sized for
 constexpr int kMaxGraphSteps = 256;
+constexpr double kWinEv = 2.0;     // half-width (eV) beyond which the LDS window does not grow
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -154,14 +155,20 @@ int64_t min_chunk(int64_t n, int64_t n_all) {
 
 // LDS histogram window of the stream kernel: the largest even square of
 // packed 16-bit counters per node that fits the budget left by the tables,
-// centred on the grid.  The window is kept large: the distribution widens as
-// the field heats it, and counts outside the window go through device
-// atomics, which are far slower than the slab traffic a wide window costs.
-void window_for(int P, int Q, int nk, bool fp32, int chunk, int budget, int* win, int* r0,
-                int* l0, int* words) {
+// centred on the grid, but no wider than the energies within kWinEv of the
+// centre.  The window is kept large: the distribution widens as the field
+// heats it, and counts outside the window go through device atomics, which
+// are far slower than the slab traffic a wide window costs.  The energy cap
+// binds only with one or two nodes, where the budget alone would cover much
+// more of the grid than the distribution occupies (every workgroup zeroes and
+// flushes its whole window).
+void window_for(int P, int Q, int nk, double lk_eV, bool fp32, int chunk, int budget, int* win,
+                int* r0, int* l0, int* words) {
     const size_t fixed = k1_lds_bytes(P, Q, fp32 ? 1 : 0, 0, chunk) + 64;
     const double room = fixed < (size_t)budget ? (double)(budget - fixed) : 0.0;
     int w = (int)std::floor(std::sqrt(room / (2.0 * Q)));
+    const int cap = 2 * (int)std::ceil(kWinEv / (2.0 * lk_eV / nk));
+    if (w > cap) w = cap;
     w &= ~1;
     if (w > nk) w = nk & ~1;
     if (w < 2) w = 2;
@@ -207,7 +214,8 @@ Layout layout_of(const sgpm_instance_desc& d, const HostTables& t, int64_t n_all
         // the smallest chunk has both the most workgroups and the largest window
         int w, r0, l0, words;
         const int64_t mc = min_chunk(d.n_particles, n_all);
-        window_for(t.P, t.Q, d.nk, d.precision == SGPM_FP32, (int)mc, kMaxLdsBudget, &w, &r0, &l0,
+        window_for(t.P, t.Q, d.nk, d.lk_eV, d.precision == SGPM_FP32, (int)mc, kMaxLdsBudget, &w,
+                   &r0, &l0,
                    &words);
         const size_t nwg_slab = (size_t)((d.n_particles + mc - 1) / mc);
         L.add(nwg_slab * (size_t)words * 4);          // 35 slabs
@@ -583,7 +591,8 @@ void set_chunk(Instance& I, int64_t chunk) {
     I.chunk = chunk > 0 ? chunk : auto_chunk(I.n, I.n_all);
     I.nwg = (int)((I.n + I.chunk - 1) / I.chunk);
     I.nb = I.nwg < kNumBatches ? I.nwg : kNumBatches;
-    window_for(I.P, I.Q, I.nk, I.fp32, (int)I.chunk, I.lds_budget, &I.win, &I.win_r0, &I.win_l0,
+    window_for(I.P, I.Q, I.nk, I.d.lk_eV, I.fp32, (int)I.chunk, I.lds_budget, &I.win, &I.win_r0,
+               &I.win_l0,
                &I.hwin_words);
 }
 
