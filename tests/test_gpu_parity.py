@@ -118,6 +118,10 @@ STEP_CASES = {
     "strang_sg_gap": (small_cfg(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1,
                                 n_particles=20_001, field0=5e6, splitting=1), 120, 512),
     "det_n1e4": (small_cfg(n_particles=10_000), 300, None),
+    # a fine grid (0.0083 eV cells): the Fermi disk spans about +-48 cells while the LDS
+    # window of eight nodes spans +-31, so much of H^n goes through the overflow grid
+    "window_overflow": (small_cfg(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1,
+                                  n_particles=20_001, field0=2e6, lk_eV=1.0), 80, 512),
     "sg_gap_ragged": (small_cfg(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1,
                                 n_particles=20_001, field0=2e6), 120, 512),
     "sg_2d_q64": (small_cfg(dim_z=2, degree=4, nodes_1d=8, gap_dim=0, gap0=0.3, gap_rel=0.15,
