@@ -126,6 +126,9 @@ STEP_CASES = {
                                 n_particles=20_001, field0=2e6), 120, 512),
     "sg_2d_q64": (small_cfg(dim_z=2, degree=4, nodes_1d=8, gap_dim=0, gap0=0.3, gap_rel=0.15,
                             field_dim=1, field0=1.5e6, field_rel=0.2, n_particles=3_000), 25, None),
+    # 81 nodes: two nodes per collider lane
+    "sg_2d_q81": (small_cfg(dim_z=2, degree=3, nodes_1d=9, gap_dim=0, gap0=0.3, gap_rel=0.15,
+                            field_dim=1, field0=1.5e6, field_rel=0.2, n_particles=2_000), 25, None),
     "hot_field_small_grid": (small_cfg(dim_z=1, degree=2, nodes_1d=3, gap_dim=0, gap_rel=0.2,
                                        field0=3e7, n_particles=5_000, nk=64, lk_eV=1.2), 120, 512),
     "pauli_off_literal": (small_cfg(dim_z=1, degree=3, nodes_1d=4, gap_dim=0, gap_rel=0.1,
