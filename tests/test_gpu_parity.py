@@ -126,6 +126,10 @@ STEP_CASES = {
                                 n_particles=20_001, field0=2e6), 120, 512),
     "sg_2d_q64": (small_cfg(dim_z=2, degree=4, nodes_1d=8, gap_dim=0, gap0=0.3, gap_rel=0.15,
                             field_dim=1, field0=1.5e6, field_rel=0.2, n_particles=3_000), 25, None),
+    # 28 modes: the kernels' largest mode bucket (32)
+    "sg_2d_td6_p28": (small_cfg(dim_z=2, degree=6, nodes_1d=7, gap_dim=0, gap0=0.3, gap_rel=0.15,
+                                field_dim=1, field0=1.5e6, field_rel=0.2, n_particles=1_500),
+                      20, None),
     # 81 nodes: two nodes per collider lane
     "sg_2d_q81": (small_cfg(dim_z=2, degree=3, nodes_1d=9, gap_dim=0, gap0=0.3, gap_rel=0.15,
                             field_dim=1, field0=1.5e6, field_rel=0.2, n_particles=2_000), 25, None),
