@@ -246,6 +246,47 @@ def cpu_baseline(cfg: dict):
                       f"same physical and gPC parameters ({dt:.1f} s of CPU work)"}
 
 
+def pmc_summary(fetch_csv: str, write_csv: str, out_path: str = TRAFFIC_FILE) -> dict:
+    """The traffic record from two rocprofv3 --pmc runs of this bench with
+    --copy-calibration (FETCH_SIZE, then WRITE_SIZE; csv counter collections):
+    the medians over the headline's dispatches of each step kernel, scaled by
+    what the same counter reads for the 268435456-byte device copies, with the
+    SHA-256 of the kernel sources they were taken on."""
+    import csv
+    import statistics
+
+    def load(path, counter):
+        by = {}
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    by.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return by
+
+    copy = 268435456
+    f, w = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+
+    def factor(by):   # counters are in KiB; the copies are the large copyBuffer dispatches
+        vals = [v for k, vs in by.items() if "copyBuffer" in k for v in vs if v > 100000]
+        return copy / (statistics.median(vals) * 1024)
+
+    cf, cw = factor(f), factor(w)
+    names = {"stream": "k1_stream<double, 6, 8>", "finalize": "k3_finalize",
+             "collide": "k2_collide<double, 6, 1>"}
+    out = {"workload": WORKLOAD + " (FP64 state)", "source_sha256": kernel_source_hash(),
+           "calibration": {"copy_bytes": copy, "fetch_factor": cf, "write_factor": cw},
+           "kernels": {}}
+    for key, pat in names.items():
+        fk = [v for k, vs in f.items() if pat in k for v in vs]
+        wk = [v for k, vs in w.items() if pat in k for v in vs]
+        out["kernels"][key] = {"dispatches": len(fk),
+                               "fetch_bytes": statistics.median(fk) * 1024 * cf,
+                               "write_bytes": statistics.median(wk) * 1024 * cw}
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,7 +302,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run five plain 256 MiB device copies (calibrates the HBM "
                          "byte counters of a profiler run)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic record from two counter runs and exit (no GPU)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        print(json.dumps(pmc_summary(*args.pmc_summary), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs the step on one GPU (asked for {args.gpus}); the path is not "
               "sharded over several GPUs", file=sys.stderr)

@@ -73,3 +73,29 @@ def test_traffic_only_for_the_profiled_sources(monkeypatch):
 def test_entry_points_exist():
     import __graft_entry__ as e
     assert callable(e.build) and callable(e.smoke)
+
+
+def test_pmc_summary_scales_by_the_copy(tmp_path):
+    """Synthetic counter files: the copy reads half its bytes on FETCH_SIZE and
+    all of them on WRITE_SIZE; the kernels' medians are scaled accordingly."""
+    head = "Kernel_Name,Counter_Name,Counter_Value\n"
+    copy_kib = 268435456 / 1024
+    fetch = [("__amd_rocclr_copyBuffer", copy_kib / 2)] * 5 + [
+        ("void sgpm::k1_stream<double, 6, 8>(x)", v) for v in (1000.0, 1100.0, 900.0)] + [
+        ("sgpm::k3_finalize(x)", 50.0), ("void sgpm::k2_collide<double, 6, 1>(x)", 20.0),
+        ("void sgpm::k1_stream<float, 6, 8>(x)", 1e9)]   # another instantiation: ignored
+    write = [("__amd_rocclr_copyBuffer", copy_kib)] * 5 + [
+        ("void sgpm::k1_stream<double, 6, 8>(x)", 300.0), ("sgpm::k3_finalize(x)", 4.0),
+        ("void sgpm::k2_collide<double, 6, 1>(x)", 6.0)]
+    fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
+    fp.write_text(head + "".join(f'"{k}",FETCH_SIZE,{v}\n' for k, v in fetch))
+    wp.write_text(head + "".join(f'"{k}",WRITE_SIZE,{v}\n' for k, v in write))
+    out = bench.pmc_summary(str(fp), str(wp), str(tmp_path / "t.json"))
+    assert out["calibration"]["fetch_factor"] == pytest.approx(2.0)
+    assert out["calibration"]["write_factor"] == pytest.approx(1.0)
+    k1 = out["kernels"]["stream"]
+    assert k1["dispatches"] == 3
+    assert k1["fetch_bytes"] == pytest.approx(1000.0 * 1024 * 2.0)
+    assert k1["write_bytes"] == pytest.approx(300.0 * 1024)
+    assert out["source_sha256"] == bench.kernel_source_hash()
+    assert json.loads((tmp_path / "t.json").read_text()) == out
