@@ -70,8 +70,11 @@ def kernel_bytes(cfg: dict, P: int, Q: int, n_drift: int, cand: float) -> dict:
 def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True, tune: bool = True):
     """Warm-up, the autotuned launch shape (trials from the warmed-up state,
     which is put back; the moment record restarts there), K timed steps in
-    the default launch mode, then K profiled steps.  cfgs: one workload or a
-    list (batched instances)."""
+    the default launch mode, then the same K steps once more from the same
+    state and step (the random streams are keyed by the step, so the run is
+    replayed exactly) with a HIP event around every kernel: the per-kernel
+    means describe the timed steps.  cfgs: one workload or a list (batched
+    instances)."""
     import numpy as np
     import torch
     import paper_2404_19602_amd as sg
@@ -84,6 +87,8 @@ def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True, tune: bool = Tr
         sim.step(warmup, dt)
     tuned_ms = sim.autotune(trial_steps=10, dt=dt) if tune else None
     shape = sim.launch_shape(0)
+    s0 = sim.step_count
+    saved = [sim.get_state(j) for j in range(sim.n_inst)] if profile else None
     c0 = [sim.counters(j) for j in range(sim.n_inst)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -99,6 +104,8 @@ def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True, tune: bool = Tr
         t = sim.tables()
         out["n_drift"] = int(np.count_nonzero(t["ehat"]))
     if profile:
+        for j, (kx, ky) in enumerate(saved):
+            sim.set_state(kx, ky, step=s0, inst=j)
         sim.set_profiling(True)
         sim.step(steps, dt)
         out["kernels"] = sim.kernel_times()
@@ -119,7 +126,7 @@ def roofline_of(cfg, r, P, Q) -> tuple:
             "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": KERNEL_SYMBOLS[dom],
             "kernel_ms": per[dom]["avg_ms"], "bytes_per_launch": per[dom]["bytes_per_launch"],
             "timing": "HIP events around each launch on the library's stream, "
-                      "profiled pass of the same number of steps"}
+                      "in a replay of the timed steps from the same state"}
     traffic = measured_traffic(dom)
     if traffic is not None:
         roof["traffic"] = traffic

@@ -254,7 +254,7 @@ sgpm_status sgpm_tables(const sgpm_ctx* ctx, int32_t inst, double* z, double* w,
                         double* ehat, double* eps0, double* width_m, double* field,
                         double* density_m2);
 
-/* Launch shape: particles per workgroup chunk (a multiple of 512, at most
+/* Launch shape: particles per workgroup chunk (a multiple of 1024, at most
  * 8192, at least a quarter of the automatic choice of about N/256, and large
  * enough for at most 4096 workgroups) of the step kernels of instance inst;
  * 0 restores the automatic

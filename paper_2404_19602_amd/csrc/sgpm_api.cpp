@@ -134,7 +134,7 @@ int64_t wg_cap_chunk(int64_t n) {
 }
 
 // n: the instance's particles; n_all: all particles of the context.  About
-// one stream workgroup (eight waves) per compute unit for the whole context
+// one stream workgroup (sixteen or eight waves) per compute unit for the whole context
 // (a batch of small instances fills the device once, not once per instance),
 // whole sub-tiles.
 int64_t auto_chunk(int64_t n, int64_t n_all) {
@@ -917,7 +917,7 @@ sgpm_status sgpm_set_chunk(sgpm_ctx* c, int32_t inst, int32_t chunk) {
     sgpm_status s = check_ctx(c, inst);
     if (s) return s;
     if (chunk < 0 || chunk % kBlock1 != 0 || chunk > kMaxChunk)
-        return fail(c, SGPM_EINVAL, "chunk must be a multiple of 256 up to 8192 (0 = automatic)");
+        return fail(c, SGPM_EINVAL, "chunk must be a multiple of 1024 up to 8192 (0 = automatic)");
     Instance& I = c->inst[inst];
     if (chunk > 0 && chunk < min_chunk(I.n, I.n_all))
         return fail(c, SGPM_EINVAL,

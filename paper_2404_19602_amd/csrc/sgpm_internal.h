@@ -83,8 +83,8 @@ struct DevTab {
     const Consts<T>* consts;
 };
 
-constexpr int kWaves1 = 8;            // waves per workgroup of the stream kernel
-constexpr int kBlock1 = 64 * kWaves1;
+constexpr int kWaves1 = 16;           // most waves per workgroup of the stream kernel
+constexpr int kBlock1 = 64 * kWaves1; // chunk quantum: a multiple of every stream block size
 constexpr int kMaxStreamWG = 4096;    // cap on stream workgroups of one instance (sizes the slabs)
 constexpr int kMaxChunk = 8192;       // cap on particles per stream workgroup (LDS list)
 constexpr int kK2Grid = 1024;         // persistent collider workgroups of one launch

@@ -1,8 +1,8 @@
 // gfx950 kernels of the sG-PM hot path (arXiv:2404.19602, Algorithm 2).
 //
 // One time step n of a group of instances is three launches, in this order:
-//  K1 stream   -- a lane per particle, a chunk of particles per 512-thread
-//                 workgroup.  For every particle: the node values k_i(z_q)
+//  K1 stream   -- a lane per particle, a chunk of particles per 1024- (or
+//                 512-) thread workgroup.  For every particle: the node values k_i(z_q)
 //                 of the state at t^n (eq. gPC), their cells in H^n through
 //                 a privatised LDS window (flushed as one slab per
 //                 workgroup, overflow cells by global atomics), and FP64
@@ -326,11 +326,24 @@ __device__ __forceinline__ bool k1_candidate(const K1Args<T>& a, const Consts<T>
     return !(-dlog(xi) >= t);
 }
 
+// Threads per stream workgroup of an instantiation: 1024 (sixteen waves, four
+// per SIMD, so at most 128 VGPRs) where the kernel fits that with at most a few
+// spilled registers, else 512.  Both divide the chunk quantum kBlock1.
 template <typename T, int PMAX, int QMAX>
-__global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict__ all,
+struct K1Block {
+    static constexpr bool wide =
+        sizeof(T) == 8 ? (QMAX == 12 ? PMAX > 1 : (QMAX == 8 ? PMAX > 6 : PMAX > 16))
+                       : ((PMAX >= 16 && QMAX == 12) || (PMAX == 32 && QMAX == 8));
+    static constexpr int value = wide ? 512 : 1024;
+};
+
+template <typename T, int PMAX, int QMAX>
+__global__ void __launch_bounds__((K1Block<T, PMAX, QMAX>::value))
+k1_stream(const K1Args<T>* __restrict__ all,
                                                      const uint32_t* __restrict__ wg0, int n_inst,
                                                      int moving) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    constexpr int BLOCK = K1Block<T, PMAX, QMAX>::value, WAVES = BLOCK / 64;
     const int slot = find_slot(wg0, n_inst, blockIdx.x);
     const K1Args<T> a = load_desc(all, slot);
     const uint32_t wg = blockIdx.x - wg0[slot];
@@ -346,25 +359,25 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
     const K1Lds<T> L = k1_lds<T>(smem, PMAX, Q, a.hwin_words, (int)a.chunk);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
-    for (int w = tid; w < (a.hwin_words >> 2); w += kBlock1)        // whole 16-byte rows
+    for (int w = tid; w < (a.hwin_words >> 2); w += BLOCK)        // whole 16-byte rows
         reinterpret_cast<uint4*>(L.hwin)[w] = make_uint4(0u, 0u, 0u, 0u);
     if (tid == 0) *L.c = *a.tab.consts;
-    for (int k = tid; k < Q * PMAX; k += kBlock1) {
+    for (int k = tid; k < Q * PMAX; k += BLOCK) {
         const int q = k / PMAX, h = k - q * PMAX;
         L.psi[k] = h < P ? a.tab.psi[q * P + h] : (T)0;
     }
     const bool strang = a.tab.consts->splitting != 0;
-    for (int k = tid; k < PMAX; k += kBlock1) {
+    for (int k = tid; k < PMAX; k += BLOCK) {
         L.psimax[k] = k < P ? a.tab.psimax[k] : (T)0;
         const T full = (moving && k < P) ? (T)(vfdt * a.ehat[k]) : (T)0;
         L.drift[k] = strang ? full * (T)0.5 : full;
         L.pdrift[k] = strang ? full * (T)0.5 : (T)0;
     }
-    for (int k = tid; k < kWaves1 * Q * 3; k += kBlock1) L.red[k] = 0.0;
+    for (int k = tid; k < kWaves1 * Q * 3; k += BLOCK) L.red[k] = 0.0;
     if (tid < 16) L.cnt[tid] = 0u;
     __syncthreads();
     // node value of the drift: sum_h drift_h Psi_h(z_q)
-    for (int k = tid; k < Q; k += kBlock1) {
+    for (int k = tid; k < Q; k += BLOCK) {
         L.eps0sq[k] = a.tab.eps0sq[k];
         T d = (T)0;
         for (int h = 0; h < PMAX; ++h) d += L.drift[h] * L.psi[k * PMAX + h];
@@ -387,7 +400,7 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
     // particle (all chunks but the last), so the per-lane guards fold away
     auto tiles = [&](auto full) {
         constexpr bool FULL = decltype(full)::value;
-        for (int64_t base = begin; base < end; base += kBlock1) {
+        for (int64_t base = begin; base < end; base += BLOCK) {
             const int64_t i = base + tid;
             const bool act = FULL || i < end;
             T cx[PMAX], cy[PMAX];
@@ -398,6 +411,7 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
                 auto nodes = [&]() -> T {
                     const bool on = act;
                     T e2max = (T)0;
+                    uint32_t outmask = 0u;
     #pragma unroll
                     for (int q = 0; q < QMAX; ++q) {
                         if (q < Q) {
@@ -411,11 +425,34 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
                                 acc[q][1] += (double)(c.v_f * ky * rs);
                                 acc[q][2] += (double)(e2 * rs);
                             }
-                            k1_bin_fast<T>(a, L, c, q, kx, ky, on);
+                            {
+                                // the node's cell: inside the LDS window (compared in
+                                // floating point, so a NaN fails) one packed increment,
+                                // else its bit in outmask for the general path below
+                                const T fr = floor((kx + c.lk) * c.inv_dk) - (T)a.win_r0;
+                                const T fl = floor((ky + c.lk) * c.inv_dk) - (T)a.win_l0;
+                                const T w = (T)a.win;
+                                const bool in = fr >= (T)0 && fr < w && fl >= (T)0 && fl < w;
+                                if (on && in) {
+                                    const int idx = __mul24(__mul24(q, a.win) + (int)fr, a.win) + (int)fl;
+                                    atomicAdd(&L.hwin[idx >> 1], 1u << ((idx & 1) << 4));
+                                }
+                                outmask |= (on && !in) ? (1u << q) : 0u;
+                            }
                             // after the drift, for the rate bound
                             const T dx = kx - L.shift[q];
                             const T d2 = dx * dx + ky * ky + L.eps0sq[q];
                             e2max = d2 > e2max ? d2 : e2max;
+                        }
+                    }
+                    // nodes outside the window (rare): re-evaluated, general path
+                    if (__ballot(outmask != 0u)) {
+                        for (int q = 0; q < Q; ++q) {
+                            if (outmask & (1u << q)) {
+                                T kx, ky;
+                                eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
+                                k1_bin<T>(a, L, c, q, kx, ky);
+                            }
                         }
                     }
                     return e2max;
@@ -499,7 +536,7 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
         if (nc) {
             if (tid == 0) gbase = atomicAdd(a.qc + 2 * (step & 1), nc);
             __syncthreads();
-            for (uint32_t k = tid; k < nc; k += kBlock1) a.cand[gbase + k] = L.cbuf[k];
+            for (uint32_t k = tid; k < nc; k += BLOCK) a.cand[gbase + k] = L.cbuf[k];
         }
     }
 
@@ -507,13 +544,13 @@ __global__ void __launch_bounds__(kBlock1) k1_stream(const K1Args<T>* __restrict
     {
         uint32_t* slab = a.slabs + (size_t)wg * a.hwin_words;
         const int nv = a.hwin_words >> 2;
-        for (int w = tid; w < nv; w += kBlock1)
+        for (int w = tid; w < nv; w += BLOCK)
             reinterpret_cast<uint4*>(slab)[w] = reinterpret_cast<const uint4*>(L.hwin)[w];
     }
     // this workgroup's moment sums, waves in order
-    for (int k = tid; k < Q * 3; k += kBlock1) {
+    for (int k = tid; k < Q * 3; k += BLOCK) {
         double v = 0.0;
-        for (int wv = 0; wv < kWaves1; ++wv) v += L.red[wv * Q * 3 + k];
+        for (int wv = 0; wv < WAVES; ++wv) v += L.red[wv * Q * 3 + k];
         a.partial[(size_t)wg * Q * 3 + k] = v;
     }
     if (tid < 8 && L.cnt[tid]) atomicAdd(&a.counters[tid], (unsigned long long)L.cnt[tid]);
@@ -1111,7 +1148,7 @@ int qmax_bucket(int Q) {
 template <typename T, int PMAX, int QMAX>
 static int launch_k1_t(const void* args, const uint32_t* wg0, int n_inst, int moving, unsigned grid,
                        size_t lds, void* stream) {
-    hipLaunchKernelGGL((k1_stream<T, PMAX, QMAX>), dim3(grid), dim3(kBlock1), lds,
+    hipLaunchKernelGGL((k1_stream<T, PMAX, QMAX>), dim3(grid), dim3(K1Block<T, PMAX, QMAX>::value), lds,
                        (hipStream_t)stream, static_cast<const K1Args<T>*>(args), wg0, n_inst,
                        moving);
     return (int)hipGetLastError();

@@ -74,7 +74,7 @@ def test_graph_survives_rechunk(sg):
     b.set_graph(3)
     for s in (a, b):
         s.init_particles()
-        s.set_chunk(512)
+        s.set_chunk(1024)
         s.step(7)
     assert_same(snapshot(a), snapshot(b))
 
@@ -180,7 +180,7 @@ def test_autotune_keeps_the_run(sg, batched):
             else:
                 assert np.array_equal(after[k], before[j][k]), (j, k)
         shape = tuned.launch_shape(j)
-        assert shape["chunk"] % 512 == 0 and shape["collider_workgroups"] in (512, 1024, 2048)
+        assert shape["chunk"] % 1024 == 0 and shape["collider_workgroups"] in (512, 1024, 2048)
     for s in (tuned, plain):
         s.step(12)
     for j in range(n):

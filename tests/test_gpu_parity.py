@@ -116,14 +116,14 @@ def test_init_parity(sg, orc, name):
 # ---------------------------------------------------------------- steps
 STEP_CASES = {
     "strang_sg_gap": (small_cfg(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1,
-                                n_particles=20_001, field0=5e6, splitting=1), 120, 512),
+                                n_particles=20_001, field0=5e6, splitting=1), 120, 1024),
     "det_n1e4": (small_cfg(n_particles=10_000), 300, None),
     # a fine grid (0.0083 eV cells): the Fermi disk spans about +-48 cells while the LDS
     # window of eight nodes spans +-31, so much of H^n goes through the overflow grid
     "window_overflow": (small_cfg(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1,
-                                  n_particles=20_001, field0=2e6, lk_eV=1.0), 80, 512),
+                                  n_particles=20_001, field0=2e6, lk_eV=1.0), 80, 1024),
     "sg_gap_ragged": (small_cfg(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1,
-                                n_particles=20_001, field0=2e6), 120, 512),
+                                n_particles=20_001, field0=2e6), 120, 1024),
     "sg_2d_q64": (small_cfg(dim_z=2, degree=4, nodes_1d=8, gap_dim=0, gap0=0.3, gap_rel=0.15,
                             field_dim=1, field0=1.5e6, field_rel=0.2, n_particles=3_000), 25, None),
     # 28 modes: the kernels' largest mode bucket (32)
@@ -134,7 +134,7 @@ STEP_CASES = {
     "sg_2d_q81": (small_cfg(dim_z=2, degree=3, nodes_1d=9, gap_dim=0, gap0=0.3, gap_rel=0.15,
                             field_dim=1, field0=1.5e6, field_rel=0.2, n_particles=2_000), 25, None),
     "hot_field_small_grid": (small_cfg(dim_z=1, degree=2, nodes_1d=3, gap_dim=0, gap_rel=0.2,
-                                       field0=3e7, n_particles=5_000, nk=64, lk_eV=1.2), 120, 512),
+                                       field0=3e7, n_particles=5_000, nk=64, lk_eV=1.2), 120, 1024),
     "pauli_off_literal": (small_cfg(dim_z=1, degree=3, nodes_1d=4, gap_dim=0, gap_rel=0.1,
                                     pauli=0, final_state=1, field0=5e6, n_particles=5_000), 80,
                           None),
@@ -194,7 +194,7 @@ def test_chunk_invariance(sg):
     cfg = small_cfg(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1, n_particles=30_000,
                     field0=2e6)
     states = []
-    for chunk in (512, 1024, 8192):
+    for chunk in (1024, 2048, 8192):
         sim = sg.Simulation(cfg, max_steps=60)
         sim.set_chunk(chunk)
         sim.init_particles()
