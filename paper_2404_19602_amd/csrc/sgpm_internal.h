@@ -85,6 +85,18 @@ struct DevTab {
 
 constexpr int kWaves1 = 16;           // most waves per workgroup of the stream kernel
 constexpr int kBlock1 = 64 * kWaves1; // chunk quantum: a multiple of every stream block size
+
+// Waves per stream workgroup for a precision, mode bucket and node bucket:
+// sixteen (1024 threads, four waves per SIMD, so at most 128 VGPRs) where the
+// kernel fits that with at most a few spilled registers, else eight.  The
+// generic path for more than 12 nodes keeps eight: its per-wave moment sums
+// live in LDS beside a histogram window that is already small.
+constexpr int k1_waves(bool fp32, int pmax, int qmax) {
+    return (qmax == 0 ||
+            (fp32 ? ((pmax >= 16 && qmax == 12) || (pmax == 32 && qmax == 8))
+                  : (qmax == 12 ? pmax > 1 : (qmax == 8 ? pmax > 6 : pmax > 16))))
+               ? 8 : 16;
+}
 constexpr int kMaxStreamWG = 4096;    // cap on stream workgroups of one instance (sizes the slabs)
 constexpr int kMaxChunk = 8192;       // cap on particles per stream workgroup (LDS list)
 constexpr int kK2Grid = 1024;         // persistent collider workgroups of one launch

@@ -231,7 +231,7 @@ size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words, int chunk) {
     off = (off + 15) & ~(size_t)15;
     off += s * ((size_t)Q * PM + 2 * Q + 3 * PM);       // psi, eps0sq, shift, psimax, drift, pdrift
     off = (off + 15) & ~(size_t)15;
-    off += (size_t)kWaves1 * Q * 3 * 8;                  // per-wave moment sums
+    off += (size_t)k1_waves(fp32 != 0, PM, qmax_bucket(Q)) * Q * 3 * 8;   // per-wave moment sums
     off += 16 * 4;                                       // counters
     return off;
 }
@@ -250,7 +250,7 @@ struct K1Lds {
 
 template <typename T>
 __device__ __forceinline__ K1Lds<T> k1_lds(unsigned char* smem, int PM, int Q, int hwin_words,
-                                           int chunk) {
+                                           int chunk, int waves) {
     K1Lds<T> L;
     L.hwin = reinterpret_cast<uint32_t*>(smem);
     L.cbuf = reinterpret_cast<int*>(smem + (size_t)hwin_words * 4);
@@ -268,7 +268,7 @@ __device__ __forceinline__ K1Lds<T> k1_lds(unsigned char* smem, int PM, int Q, i
     off += sizeof(T) * ((size_t)Q * PM + 2 * Q + 3 * PM);
     off = (off + 15) & ~(size_t)15;
     L.red = reinterpret_cast<double*>(smem + off);
-    off += (size_t)kWaves1 * Q * 3 * 8;
+    off += (size_t)waves * Q * 3 * 8;
     L.cnt = reinterpret_cast<uint32_t*>(smem + off);
     return L;
 }
@@ -326,15 +326,11 @@ __device__ __forceinline__ bool k1_candidate(const K1Args<T>& a, const Consts<T>
     return !(-dlog(xi) >= t);
 }
 
-// Threads per stream workgroup of an instantiation: 1024 (sixteen waves, four
-// per SIMD, so at most 128 VGPRs) where the kernel fits that with at most a few
-// spilled registers, else 512.  Both divide the chunk quantum kBlock1.
+// Threads per stream workgroup of an instantiation (k1_waves); 1024 and 512
+// both divide the chunk quantum kBlock1.
 template <typename T, int PMAX, int QMAX>
 struct K1Block {
-    static constexpr bool wide =
-        sizeof(T) == 8 ? (QMAX == 12 ? PMAX > 1 : (QMAX == 8 ? PMAX > 6 : PMAX > 16))
-                       : ((PMAX >= 16 && QMAX == 12) || (PMAX == 32 && QMAX == 8));
-    static constexpr int value = wide ? 512 : 1024;
+    static constexpr int value = 64 * k1_waves(sizeof(T) == 4, PMAX, QMAX);
 };
 
 template <typename T, int PMAX, int QMAX>
@@ -356,7 +352,7 @@ k1_stream(const K1Args<T>* __restrict__ all,
         a.excess[(size_t)(step - a.dyn->rec_base) * a.Q + threadIdx.x] = 0u;
     const T dt = (T)a.dyn->dt;
     const int P = a.P, Q = a.Q;
-    const K1Lds<T> L = k1_lds<T>(smem, PMAX, Q, a.hwin_words, (int)a.chunk);
+    const K1Lds<T> L = k1_lds<T>(smem, PMAX, Q, a.hwin_words, (int)a.chunk, WAVES);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     for (int w = tid; w < (a.hwin_words >> 2); w += BLOCK)        // whole 16-byte rows
@@ -373,7 +369,7 @@ k1_stream(const K1Args<T>* __restrict__ all,
         L.drift[k] = strang ? full * (T)0.5 : full;
         L.pdrift[k] = strang ? full * (T)0.5 : (T)0;
     }
-    for (int k = tid; k < kWaves1 * Q * 3; k += BLOCK) L.red[k] = 0.0;
+    for (int k = tid; k < WAVES * Q * 3; k += BLOCK) L.red[k] = 0.0;
     if (tid < 16) L.cnt[tid] = 0u;
     __syncthreads();
     // node value of the drift: sum_h drift_h Psi_h(z_q)
