@@ -268,9 +268,10 @@ sgpm_status sgpm_set_chunk(sgpm_ctx* ctx, int32_t inst, int32_t chunk);
  * with HIP events on the context's stream) for each candidate shape: every
  * instance's chunk scaled by 1/4, 1/2, 1, 2 or 4 from the automatic one
  * (within the limits of sgpm_set_chunk), times 512, 1024 or 2048 collider
- * workgroups (a grid other than 1024 must be more than 1 % faster).  Between trials and at the end it puts back the particle
- * state, the step counter and the counters; the histogram is rebuilt and the
- * moment record restarts at the current time, as after sgpm_set_state.
+ * workgroups (a grid other than 1024 must be more than 3 % faster).
+ * Between trials and at the end it puts back the particle state, the step
+ * counter and the counters; the histogram is rebuilt and the moment record
+ * restarts at the current time, as after sgpm_set_state.
  * Keeps the fastest shape (results do not depend on it; see sgpm_set_chunk)
  * and returns its device time per step in *best_ms_per_step (may be NULL).
  * Needs trial_steps <= max_steps of every instance (1 <= trial_steps <=
