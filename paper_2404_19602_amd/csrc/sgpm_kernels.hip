@@ -104,6 +104,78 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// gfx950 lane swaps on both 32-bit halves of a pair of doubles: swap32 trades
+// lanes 32..63 of a for lanes 0..31 of b; swap16 trades the odd 16-lane rows of
+// a for the even rows of b.
+__device__ __forceinline__ void swap32_f64(double& a, double& b) {
+    const uint64_t ua = (uint64_t)__double_as_longlong(a), ub = (uint64_t)__double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)ua, (uint32_t)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32),
+                                                     false, false);
+    a = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0]));
+    b = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+}
+__device__ __forceinline__ void swap16_f64(double& a, double& b) {
+    const uint64_t ua = (uint64_t)__double_as_longlong(a), ub = (uint64_t)__double_as_longlong(b);
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)ua, (uint32_t)ub, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(ua >> 32), (uint32_t)(ub >> 32),
+                                                     false, false);
+    a = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0]));
+    b = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+}
+
+// x read from another lane of the same 16-lane row (DPP control CTRL)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF,
+                                                              0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Wave sums of V per-lane values.  V is padded with zeros to VP, a multiple
+// of 4.  Two halving steps (lanes 32 apart, then 16 apart) leave every lane
+// with VP/4 partial sums of four lanes each; the 16 lanes of a row then add
+// theirs (quad swaps, half-row and row mirrors), so that row r holds the sums
+// of values j + (VP/4)(r & 1) + (VP/2)(r >> 1), j < VP/4.  The first lane of
+// each row adds those with index below n_out to out[] (each index owned by
+// one lane).  No LDS, no index arithmetic.
+template <int V>
+__device__ __forceinline__ void wave_sums_add(const double (&v)[V], double* out, int n_out,
+                                              int lane) {
+    constexpr int VP = (V + 3) & ~3, H2 = VP / 2, H4 = VP / 4;
+    double u[H2];
+#pragma unroll
+    for (int j = 0; j < H2; ++j) {
+        double a = v[j], b = j + H2 < V ? v[j + H2] : 0.0;
+        swap32_f64(a, b);
+        u[j] = a + b;
+    }
+    double w[H4];
+#pragma unroll
+    for (int j = 0; j < H4; ++j) {
+        double a = u[j], b = u[j + H4];
+        swap16_f64(a, b);
+        w[j] = a + b;
+    }
+#pragma unroll
+    for (int j = 0; j < H4; ++j) {
+        double x = w[j];
+        x += dpp_f64<0xB1>(x);    // quad_perm [1,0,3,2]
+        x += dpp_f64<0x4E>(x);    // quad_perm [2,3,0,1]
+        x += dpp_f64<0x141>(x);   // row_half_mirror
+        x += dpp_f64<0x140>(x);   // row_mirror
+        w[j] = x;
+    }
+    if ((lane & 15) == 0) {
+        const int r = lane >> 4, base = H4 * (r & 1) + H2 * (r >> 1);
+#pragma unroll
+        for (int j = 0; j < H4; ++j)
+            if (base + j < n_out) out[base + j] += w[j];
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T group_max(T v, int G) {
     for (int m = G >> 1; m >= 1; m >>= 1) {
@@ -458,23 +530,27 @@ k1_stream(const K1Args<T>* __restrict__ all,
                 // margin for the rounding of the shifted evaluation
                 if (act && moving) cand = k1_candidate<T>(a, c, i, sqrt(e2max) * c.b_margin, step, dt);
             } else {
-                for (int q = 0; q < Q; ++q) {
-                    double vx = 0.0, vy = 0.0, en = 0.0;
-                    if (act) {
-                        T kx, ky;
-                        eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
-                        const T e2 = kx * kx + ky * ky + L.eps0sq[q];
-                        const T rs = rsqrt_nr(e2);
-                        vx = (double)(c.v_f * kx * rs);
-                        vy = (double)(c.v_f * ky * rs);
-                        en = (double)(e2 * rs);
-                        k1_bin<T>(a, L, c, q, kx, ky);
+                // blocks of four nodes, their twelve sums reduced over the wave together
+                for (int q0 = 0; q0 < Q; q0 += 4) {
+                    double v[12];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int q = q0 + b;
+                        double vx = 0.0, vy = 0.0, en = 0.0;
+                        if (act && q < Q) {
+                            T kx, ky;
+                            eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
+                            const T e2 = kx * kx + ky * ky + L.eps0sq[q];
+                            const T rs = rsqrt_nr(e2);
+                            vx = (double)(c.v_f * kx * rs);
+                            vy = (double)(c.v_f * ky * rs);
+                            en = (double)(e2 * rs);
+                            k1_bin<T>(a, L, c, q, kx, ky);
+                        }
+                        v[3 * b] = vx; v[3 * b + 1] = vy; v[3 * b + 2] = en;
                     }
-                    vx = wave_sum(vx); vy = wave_sum(vy); en = wave_sum(en);
-                    if (lane == 0) {
-                        double* m = L.red + ((size_t)wave * Q + q) * 3;
-                        m[0] += vx; m[1] += vy; m[2] += en;
-                    }
+                    const int nb = Q - q0 < 4 ? Q - q0 : 4;
+                    wave_sums_add<12>(v, L.red + ((size_t)wave * Q + q0) * 3, 3 * nb, lane);
                 }
                 if (act && moving) {
                     // |k(z_q)| <= sum_h |k_h| max_q |Psi_h(z_q)| per component, after the drift
@@ -511,17 +587,12 @@ k1_stream(const K1Args<T>* __restrict__ all,
     if (end - begin == a.chunk) tiles(std::true_type{});
     else tiles(std::false_type{});
     if constexpr (QMAX > 0) {
+        double v[3 * QMAX];
 #pragma unroll
         for (int q = 0; q < QMAX; ++q) {
-            if (q < Q) {
-                const double vx = wave_sum(acc[q][0]), vy = wave_sum(acc[q][1]),
-                             en = wave_sum(acc[q][2]);
-                if (lane == 0) {
-                    double* m = L.red + ((size_t)wave * Q + q) * 3;
-                    m[0] = vx; m[1] = vy; m[2] = en;
-                }
-            }
+            v[3 * q] = acc[q][0]; v[3 * q + 1] = acc[q][1]; v[3 * q + 2] = acc[q][2];
         }
+        wave_sums_add<3 * QMAX>(v, L.red + (size_t)wave * Q * 3, 3 * Q, lane);
     }
     __syncthreads();
 
