@@ -252,6 +252,24 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ row, const T (&c
     kx = x; ky = y;
 }
 
+// the coefficients of the particles of one tile: base is the tile's first
+// particle (the same for the whole workgroup), t this lane's offset in it, so
+// every mode is one uniform pointer plus a 32-bit lane offset.  Modes past P
+// repeat mode P-1; the padded basis tables are zero there, so they add nothing.
+template <typename T, int PMAX>
+__device__ __forceinline__ void load_tile_coeffs(const T* __restrict__ kxa, const T* __restrict__ kya,
+                                                 int64_t n, int P, int64_t base, uint32_t t,
+                                                 T (&cx)[PMAX], T (&cy)[PMAX]) {
+#pragma unroll
+    for (int h = 0; h < PMAX; ++h) {
+        const int hh = h < P ? h : P - 1;
+        const T* px = kxa + ((size_t)hh * n + base);
+        const T* py = kya + ((size_t)hh * n + base);
+        cx[h] = px[t];
+        cy[h] = py[t];
+    }
+}
+
 // coefficients of particle i (drift applied), zero past P, branch-free loads
 template <typename T, int PMAX>
 __device__ __forceinline__ void load_coeffs(const T* __restrict__ kxa, const T* __restrict__ kya,
@@ -462,7 +480,6 @@ k1_stream(const K1Args<T>* __restrict__ all,
 #pragma unroll
         for (int q = 0; q < QMAX; ++q) { acc[q][0] = 0.0; acc[q][1] = 0.0; acc[q][2] = 0.0; }
     }
-    const T zero[PMAX] = {};
 
     // the tiles of this workgroup's chunk; FULL: every lane of every tile holds a
     // particle (all chunks but the last), so the per-lane guards fold away
@@ -472,7 +489,7 @@ k1_stream(const K1Args<T>* __restrict__ all,
             const int64_t i = base + tid;
             const bool act = FULL || i < end;
             T cx[PMAX], cy[PMAX];
-            load_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, act ? i : begin, zero, cx, cy);
+            load_tile_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, base, act ? (uint32_t)tid : 0u, cx, cy);
             bool cand = false;
             if constexpr (QMAX > 0) {
                 // the nodes of one particle
@@ -568,7 +585,7 @@ k1_stream(const K1Args<T>* __restrict__ all,
     #pragma unroll
                 for (int h = 0; h < PMAX; ++h)
                     if (h < P && L.drift[h] != (T)0)
-                        a.kx[(size_t)h * a.n + i] = (cx[h] - L.drift[h]) - L.pdrift[h];
+                        (a.kx + ((size_t)h * a.n + base))[(uint32_t)tid] = (cx[h] - L.drift[h]) - L.pdrift[h];
             }
             // candidates of this workgroup collected in LDS
             const uint64_t mask = __ballot(cand);
@@ -719,6 +736,19 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
     const double vfdt = a.dyn->vfdt;
     const uint32_t* h_read = a.H + (size_t)(step % 3u) * a.hstride;
     const uint32_t* hmax_read = a.Hmax + (size_t)(step % 3u) * a.hmstride;
+    const int g = tid % G;                // rank in the group = node handled
+    const int grp = tid / G;
+    const uint32_t per_pass = kBlock / G;
+    // the first pass's candidate and its coefficients (drift not yet applied),
+    // fetched while the tables are staged
+    const T zero[PMAX] = {};
+    const uint32_t cid0 = first * per_pass + grp;
+    int64_t i = 0;
+    T cx[PMAX] = {}, cy[PMAX] = {};
+    if (cid0 < total) {
+        i = a.cand[cid0];
+        load_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, i, zero, cx, cy);
+    }
 
     if (tid == 0) *L.c = *a.tab.consts;
     for (int k = tid; k < Q * PMAX; k += kBlock) {
@@ -743,18 +773,18 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
     // the grid of H^n moved with the drift applied before the collisions
     const T dt_grid = strang ? dt * (T)0.5 : dt;
 
-    const int g = tid % G;                // rank in the group = node handled
-    const int grp = tid / G;
-    const uint32_t per_pass = kBlock / G;
     T* nodes = L.scratch + (size_t)grp * (2 * Q + 2 * PMAX);   // [2][Q] new node values
     T* modes = nodes + 2 * Q;                                   // [2][PMAX] new coefficients
 
+#pragma unroll
+    for (int h = 0; h < PMAX; ++h) cx[h] -= L.drift[h];   // zero past P on both sides
     for (uint32_t p0 = first * per_pass; p0 < total; p0 += stride * per_pass) {
         const uint32_t cid = p0 + grp;
         if (cid >= total) continue;
-        const int64_t i = a.cand[cid];
-        T cx[PMAX], cy[PMAX];
-        load_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, i, L.drift, cx, cy);
+        if (cid != cid0) {
+            i = a.cand[cid];
+            load_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, i, L.drift, cx, cy);
+        }
         T tc = (T)0;
         uint32_t coll = 0;
         const uint32_t ctr0 = (uint32_t)i;
@@ -950,6 +980,17 @@ __device__ __forceinline__ void k2_body(const K2Args<T>* __restrict__ all, int n
     typedef const __attribute__((address_space(4))) K2Args<T> CA;
     const uint32_t grid = gridDim.x;
     const int tid = threadIdx.x;
+    if (n_inst == 1) {
+        // one instance: its passes b, b + grid, ... are this workgroup's
+        const K2Args<T> a = load_desc(all, 0);
+        const uint32_t step = a.dyn->step_k2;
+        const uint32_t total = a.qc[2 * (step & 1u)];
+        if (blockIdx.x == 0 && tid == 0) a.dyn->step_k3 = step + 1u;   // the finalize kernel is done
+        const uint32_t per_pass = (uint32_t)(kBlock / a.G);
+        if (blockIdx.x < (total + per_pass - 1) / per_pass)
+            k2_instance<T, PMAX, NPL>(a, smem, step, total, blockIdx.x, grid);
+        return;
+    }
     // every instance's step, list length and pass count, read in parallel
     uint32_t loc[kPer];
     uint32_t sum = 0;
