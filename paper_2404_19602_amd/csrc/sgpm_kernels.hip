@@ -502,12 +502,23 @@ k1_stream(const K1Args<T>* __restrict__ all,
                         if (q < Q) {
                             T kx, ky;
                             eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
+                            // read before the histogram increment, which the compiler
+                            // must otherwise assume may change them
+                            const T e0sq = L.eps0sq[q], sh = L.shift[q];
                             // state at t^n: histogram and moments (Sec. 4.2)
-                            const T e2 = kx * kx + ky * ky + L.eps0sq[q];
+                            const T e2 = kx * kx + ky * ky + e0sq;
                             const T rs = rsqrt_nr(e2);
                             if (on) {
-                                acc[q][0] += (double)(c.v_f * kx * rs);
-                                acc[q][1] += (double)(c.v_f * ky * rs);
+                                if constexpr (sizeof(T) == 8) {
+                                    // v_F applied to the lane's sums at the end
+                                    acc[q][0] += kx * rs;
+                                    acc[q][1] += ky * rs;
+                                } else {
+                                    // FP32 products, summed exactly in FP64: the sums
+                                    // do not depend on how the particles are chunked
+                                    acc[q][0] += (double)(c.v_f * kx * rs);
+                                    acc[q][1] += (double)(c.v_f * ky * rs);
+                                }
                                 acc[q][2] += (double)(e2 * rs);
                             }
                             {
@@ -517,7 +528,7 @@ k1_stream(const K1Args<T>* __restrict__ all,
                                 const T fr = floor((kx + c.lk) * c.inv_dk) - (T)a.win_r0;
                                 const T fl = floor((ky + c.lk) * c.inv_dk) - (T)a.win_l0;
                                 const T w = (T)a.win;
-                                const bool in = fr >= (T)0 && fr < w && fl >= (T)0 && fl < w;
+                                const bool in = (fr >= (T)0) & (fr < w) & (fl >= (T)0) & (fl < w);
                                 if (on && in) {
                                     const int idx = __mul24(__mul24(q, a.win) + (int)fr, a.win) + (int)fl;
                                     atomicAdd(&L.hwin[idx >> 1], 1u << ((idx & 1) << 4));
@@ -525,9 +536,9 @@ k1_stream(const K1Args<T>* __restrict__ all,
                                 outmask |= (on && !in) ? (1u << q) : 0u;
                             }
                             // after the drift, for the rate bound
-                            const T dx = kx - L.shift[q];
-                            const T d2 = dx * dx + ky * ky + L.eps0sq[q];
-                            e2max = d2 > e2max ? d2 : e2max;
+                            const T dx = kx - sh;
+                            const T d2 = dx * dx + ky * ky + e0sq;
+                            e2max = fmax(d2, e2max);   // never NaN: a NaN d2 is passed over
                         }
                     }
                     // nodes outside the window (rare): re-evaluated, general path
@@ -605,9 +616,10 @@ k1_stream(const K1Args<T>* __restrict__ all,
     else tiles(std::false_type{});
     if constexpr (QMAX > 0) {
         double v[3 * QMAX];
+        const double vf = sizeof(T) == 8 ? (double)L.c->v_f : 1.0;
 #pragma unroll
         for (int q = 0; q < QMAX; ++q) {
-            v[3 * q] = acc[q][0]; v[3 * q + 1] = acc[q][1]; v[3 * q + 2] = acc[q][2];
+            v[3 * q] = vf * acc[q][0]; v[3 * q + 1] = vf * acc[q][1]; v[3 * q + 2] = acc[q][2];
         }
         wave_sums_add<3 * QMAX>(v, L.red + (size_t)wave * Q * 3, 3 * Q, lane);
     }
