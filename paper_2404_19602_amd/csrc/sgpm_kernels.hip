@@ -592,11 +592,16 @@ k1_stream(const K1Args<T>* __restrict__ all,
                 }
             }
             if (act && moving && !cand) {
-                // the particle does not collide: its step is the drift alone
+                // the particle does not collide: its step is the drift alone.  The
+                // lane offset is passed through an empty asm statement so that the
+                // per-mode store addresses are formed here, not kept for the whole
+                // loop in registers (which would spill them).
+                uint32_t t = (uint32_t)tid;
+                __asm__ volatile("" : "+v"(t));
     #pragma unroll
                 for (int h = 0; h < PMAX; ++h)
                     if (h < P && L.drift[h] != (T)0)
-                        (a.kx + ((size_t)h * a.n + base))[(uint32_t)tid] = (cx[h] - L.drift[h]) - L.pdrift[h];
+                        (a.kx + ((size_t)h * a.n + base))[t] = (cx[h] - L.drift[h]) - L.pdrift[h];
             }
             // candidates of this workgroup collected in LDS
             const uint64_t mask = __ballot(cand);
