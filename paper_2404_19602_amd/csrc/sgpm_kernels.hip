@@ -1169,6 +1169,22 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
         const int col = tid % (kK3Words / 4);
         const int lane = tid / (kK3Words / 4);
         const int word0 = wb * kK3Words + 4 * col;
+        // the overflow count of the cell this thread settles below, loaded
+        // together with the slabs (each cell is settled by one thread only)
+        size_t g_set = 0;
+        int q_set = -1;
+        uint32_t ex_set = 0u;
+        if (tid < 2 * kK3Words) {
+            const int word = wb * kK3Words + (tid >> 1);
+            const int idx = 2 * word + (tid & 1);
+            if (word < a.hwin_words && idx < a.Q * wcells) {
+                q_set = idx / wcells;
+                const int rem = idx - q_set * wcells;
+                const int r = a.win_r0 + rem / a.win, l = a.win_l0 + rem % a.win;
+                g_set = (size_t)q_set * cells + (size_t)r * a.nk + l;
+                ex_set = a.extra[g_set];
+            }
+        }
         uint32_t lo[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u};
         if (word0 < a.hwin_words) {
             const uint32_t* src = a.slabs + word0;
@@ -1184,23 +1200,15 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
 #pragma unroll
         for (int j = 0; j < 4; ++j) { part[lane][4 * col + j][0] = lo[j]; part[lane][4 * col + j][1] = hi[j]; }
         __syncthreads();
-        if (tid < 2 * kK3Words) {
+        if (q_set >= 0) {
             const int wl = tid >> 1, half = tid & 1;
-            const int word = wb * kK3Words + wl;
-            uint32_t sum = 0u;
+            uint32_t sum = ex_set;
 #pragma unroll
             for (int k = 0; k < kK3Lanes; ++k) sum += part[k][wl][half];
-            const int idx = 2 * word + half;
-            if (word < a.hwin_words && idx < a.Q * wcells) {
-                const int q = idx / wcells, rem = idx - q * wcells;
-                const int r = a.win_r0 + rem / a.win, l = a.win_l0 + rem % a.win;
-                const size_t g = (size_t)q * cells + (size_t)r * a.nk + l;
-                sum += a.extra[g];
-                a.extra[g] = 0u;
-                h_out[g] = sum;
-                if (sum) atomicMax(&smax[q], sum);
-                if (sum > scap[q]) atomicAdd(&sex[q], sum - scap[q]);
-            }
+            a.extra[g_set] = 0u;
+            h_out[g_set] = sum;
+            if (sum) atomicMax(&smax[q_set], sum);
+            if (sum > scap[q_set]) atomicAdd(&sex[q_set], sum - scap[q_set]);
         }
         __syncthreads();   // part[] is rewritten by the next block
     }
