@@ -127,20 +127,26 @@ def roofline_of(cfg, r, P, Q) -> tuple:
             "kernel_ms": per[dom]["avg_ms"], "bytes_per_launch": per[dom]["bytes_per_launch"],
             "timing": "HIP events around each launch on the library's stream, "
                       "in a replay of the timed steps from the same state"}
-    traffic = measured_traffic(dom)
+    shape = r.get("shape") or {}
+    traffic = measured_traffic(dom, shape.get("stream_workgroups"))
     if traffic is not None:
         roof["traffic"] = traffic
     return roof, per
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, stream_workgroups=None):
     """HBM bytes per launch of a kernel from the committed PMC summary, if the
-    kernel source is the one the counters were taken on."""
+    kernel source is the one the counters were taken on and, when both are
+    known, the launch shape (stream workgroups) is the same: the window slabs
+    the stream kernel writes and the finalize kernel reads scale with it."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         rec = json.load(fh)
     if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    taken = rec.get("stream_workgroups")
+    if taken is not None and stream_workgroups is not None and taken != stream_workgroups:
         return None
     k = rec.get("kernels", {}).get(kernel)
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
@@ -253,39 +259,83 @@ def cpu_baseline(cfg: dict):
                       f"same physical and gPC parameters ({dt:.1f} s of CPU work)"}
 
 
-def pmc_summary(fetch_csv: str, write_csv: str, out_path: str = TRAFFIC_FILE) -> dict:
+def pmc_summary(fetch_csv: str, write_csv: str, out_path: str = TRAFFIC_FILE,
+                steps: int = 20) -> dict:
     """The traffic record from two rocprofv3 --pmc runs of this bench with
-    --copy-calibration (FETCH_SIZE, then WRITE_SIZE; csv counter collections):
-    the medians over the headline's dispatches of each step kernel, scaled by
-    what the same counter reads for the 268435456-byte device copies, with the
-    SHA-256 of the kernel sources they were taken on."""
+    --copy-calibration (FETCH_SIZE, then WRITE_SIZE; csv counter collections),
+    scaled by what the same counter reads for the 268435456-byte device copies,
+    with the SHA-256 of the kernel sources they were taken on.
+
+    Per step kernel, the median over the last 2 * steps moving steps of the
+    headline (its timed and its profiled pass, in the final launch shape): a
+    stream launch is a moving step when the collider runs before the next
+    stream launch, and that step's finalize and collide launches are the ones
+    that follow it.  The autotuner's trials and the bins-only passes, whose
+    shapes and traffic differ, are left out.  Without dispatch ids in the files
+    every headline dispatch counts."""
     import csv
     import statistics
 
+    names = {"stream": "k1_stream<double, 6, 8>", "finalize": "k3_finalize",
+             "collide": "k2_collide<double, 6, 1>"}
+
     def load(path, counter):
-        by = {}
+        by, seq = {}, []
         with open(path) as fh:
             for r in csv.DictReader(fh):
-                if r["Counter_Name"] == counter:
-                    by.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        return by
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"])
+                by.setdefault(r["Kernel_Name"], []).append(v)
+                key = next((k for k, pat in names.items() if pat in r["Kernel_Name"]), None)
+                if key is not None and r.get("Dispatch_Id"):
+                    wgs = None
+                    if r.get("Grid_Size") and r.get("Workgroup_Size"):
+                        wgs = int(r["Grid_Size"]) // max(1, int(r["Workgroup_Size"]))
+                    seq.append((int(r["Dispatch_Id"]), key, v, wgs))
+        return by, sorted(seq)
+
+    def moving_steps(seq):
+        """(stream, finalize, collide) rows of the last 2 * steps moving steps."""
+        out = []
+        for k, (_, key, _, _) in enumerate(seq):
+            if key != "stream":
+                continue
+            fin = col = None
+            for row in seq[k + 1:]:
+                if row[1] == "stream":
+                    break
+                if row[1] == "finalize" and fin is None:
+                    fin = row
+                if row[1] == "collide" and col is None:
+                    col = row
+            if fin is not None and col is not None:
+                out.append((seq[k], fin, col))
+        return out[-2 * steps:]
 
     copy = 268435456
-    f, w = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
+    (f, fseq), (w, wseq) = load(fetch_csv, "FETCH_SIZE"), load(write_csv, "WRITE_SIZE")
 
     def factor(by):   # counters are in KiB; the copies are the large copyBuffer dispatches
         vals = [v for k, vs in by.items() if "copyBuffer" in k for v in vs if v > 100000]
         return copy / (statistics.median(vals) * 1024)
 
     cf, cw = factor(f), factor(w)
-    names = {"stream": "k1_stream<double, 6, 8>", "finalize": "k3_finalize",
-             "collide": "k2_collide<double, 6, 1>"}
+    fsteps, wsteps = moving_steps(fseq), moving_steps(wseq)
     out = {"workload": WORKLOAD + " (FP64 state)", "source_sha256": kernel_source_hash(),
            "calibration": {"copy_bytes": copy, "fetch_factor": cf, "write_factor": cw},
            "kernels": {}}
-    for key, pat in names.items():
-        fk = [v for k, vs in f.items() if pat in k for v in vs]
-        wk = [v for k, vs in w.items() if pat in k for v in vs]
+    if fsteps and wsteps:
+        shapes = sorted({s[0][3] for s in fsteps} | {s[0][3] for s in wsteps})
+        out["steps"] = {"fetch_run": len(fsteps), "write_run": len(wsteps)}
+        out["stream_workgroups"] = shapes[0] if len(shapes) == 1 else None
+    for j, (key, pat) in enumerate(names.items()):
+        if fsteps and wsteps:
+            fk = [s[j][2] for s in fsteps]
+            wk = [s[j][2] for s in wsteps]
+        else:
+            fk = [v for k, vs in f.items() if pat in k for v in vs]
+            wk = [v for k, vs in w.items() if pat in k for v in vs]
         out["kernels"][key] = {"dispatches": len(fk),
                                "fetch_bytes": statistics.median(fk) * 1024 * cf,
                                "write_bytes": statistics.median(wk) * 1024 * cw}
@@ -306,14 +356,18 @@ def main():
     ap.add_argument("--no-uq", action="store_true", help="skip the MC-MC / moments-at-z timings")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the timings of the other workloads at full size")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch shape of the headline (counter runs: "
+                         "the traffic record then holds for that shape)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run five plain 256 MiB device copies (calibrates the HBM "
                          "byte counters of a profiler run)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write the traffic record from two counter runs and exit (no GPU)")
+                    help="write the traffic record from two counter runs and exit (no GPU); "
+                         "--steps gives the timed steps of those runs")
     args = ap.parse_args()
     if args.pmc_summary:
-        print(json.dumps(pmc_summary(*args.pmc_summary), indent=1))
+        print(json.dumps(pmc_summary(*args.pmc_summary, steps=args.steps), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py runs the step on one GPU (asked for {args.gpus}); the path is not "
@@ -335,7 +389,7 @@ def main():
 
     cfg = workload(WORKLOAD)
     log(f"{WORKLOAD}: FP64, {args.warmup} warm-up + {args.steps} timed + {args.steps} profiled steps")
-    r64 = run_gpu(dict(cfg, precision="fp64"), args.steps, args.warmup)
+    r64 = run_gpu(dict(cfg, precision="fp64"), args.steps, args.warmup, tune=not args.no_tune)
     P, Q, N = r64["sim"].P, r64["sim"].Q, cfg["n_particles"]
     pn = N * Q * args.steps
     roof, per = roofline_of(dict(cfg, precision="fp64"), r64, P, Q)

@@ -99,3 +99,55 @@ def test_pmc_summary_scales_by_the_copy(tmp_path):
     assert k1["write_bytes"] == pytest.approx(300.0 * 1024)
     assert out["source_sha256"] == bench.kernel_source_hash()
     assert json.loads((tmp_path / "t.json").read_text()) == out
+
+
+def test_pmc_summary_keeps_the_timed_passes(tmp_path):
+    """With dispatch ids, only the last 2 * steps moving steps count: a stream
+    launch followed by the collider before the next stream launch.  Earlier
+    launches (another launch shape, as in the autotuner's trials) and bins-only
+    passes (no collider) are left out, and the stream workgroups are recorded."""
+    head = ("Dispatch_Id,Grid_Size,Workgroup_Size,Kernel_Name,Counter_Name,Counter_Value\n")
+    copy_kib = 268435456 / 1024
+    k1, k3, k2 = ("void sgpm::k1_stream<double, 6, 8>(x)", "sgpm::k3_finalize(x)",
+                  "void sgpm::k2_collide<double, 6, 1>(x)")
+
+    def runs(counter, copy_val):
+        rows, d = [], 0
+        for _ in range(3):
+            d += 1; rows.append((d, 1024, 1024, "__amd_rocclr_copyBuffer", copy_val))
+        # a trial shape: 490 workgroups, large values
+        for _ in range(4):
+            d += 1; rows.append((d, 490 * 1024, 1024, k1, 9000.0))
+            d += 1; rows.append((d, 256, 256, k3, 900.0))
+            d += 1; rows.append((d, 256, 256, k2, 90.0))
+        # a bins-only pass (no collider), then the final shape: 245 workgroups
+        d += 1; rows.append((d, 245 * 1024, 1024, k1, 5.0))
+        d += 1; rows.append((d, 256, 256, k3, 5.0))
+        for s in range(6):
+            d += 1; rows.append((d, 245 * 1024, 1024, k1, 100.0 + s))
+            d += 1; rows.append((d, 256, 256, k3, 10.0))
+            d += 1; rows.append((d, 256, 256, k2, 1.0))
+        return head + "".join(f'{a},{g},{wg},"{k}",{counter},{v}\n' for a, g, wg, k, v in rows)
+
+    fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
+    fp.write_text(runs("FETCH_SIZE", copy_kib / 2))
+    wp.write_text(runs("WRITE_SIZE", copy_kib))
+    out = bench.pmc_summary(str(fp), str(wp), str(tmp_path / "t.json"), steps=2)
+    k = out["kernels"]
+    assert k["stream"]["dispatches"] == 4          # the last 2 * steps moving steps
+    assert k["stream"]["fetch_bytes"] == pytest.approx(103.5 * 1024 * 2.0)   # median of 102..105
+    assert k["finalize"]["write_bytes"] == pytest.approx(10.0 * 1024)
+    assert k["collide"]["write_bytes"] == pytest.approx(1.0 * 1024)
+    assert out["stream_workgroups"] == 245
+
+
+def test_traffic_only_for_the_same_launch_shape(monkeypatch, tmp_path):
+    rec = {"source_sha256": "h", "stream_workgroups": 245,
+           "kernels": {"stream": {"fetch_bytes": 1.0, "write_bytes": 2.0}}}
+    path = tmp_path / "t.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "h")
+    assert bench.measured_traffic("stream", 245) == 3.0
+    assert bench.measured_traffic("stream", 490) is None
+    assert bench.measured_traffic("stream") == 3.0
