@@ -268,7 +268,8 @@ sgpm_status sgpm_set_chunk(sgpm_ctx* ctx, int32_t inst, int32_t chunk);
  * with HIP events on the context's stream) for each candidate shape: every
  * instance's chunk scaled by 1/4, 1/2, 1, 2 or 4 from the automatic one
  * (within the limits of sgpm_set_chunk), times 512, 1024 or 2048 collider
- * workgroups (a grid other than 1024 must be more than 3 % faster).
+ * workgroups.  A grid other than 1024 must be more than 3 % faster, and so
+ * must chunks other than the automatic ones (the two margins multiply).
  * Between trials and at the end it puts back the particle state, the step
  * counter and the counters; the histogram is rebuilt and the moment record
  * restarts at the current time, as after sgpm_set_state.

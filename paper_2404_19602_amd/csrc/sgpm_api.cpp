@@ -994,6 +994,8 @@ sgpm_status sgpm_autotune(sgpm_ctx* c, double dt, int32_t trial_steps, double* b
     double best = 1e300, best_score = 1e300, best_f = 1.0;
     int best_g = c->k2_grid;
     std::vector<std::vector<int64_t>> tried;
+    std::vector<int64_t> auto_shape;
+    for (Instance& I : c->inst) auto_shape.push_back(scaled_chunk(I, 1.0));
     sgpm_status st = SGPM_OK;
     for (double f : kFactors) {
         std::vector<int64_t> shape;
@@ -1010,10 +1012,11 @@ sgpm_status sgpm_autotune(sgpm_ctx* c, double dt, int32_t trial_steps, double* b
             double ms = 0.0;
             if (!st) st = sgpm_last_step_ms(c, &ms);
             if (st) break;
-            // another collider grid than the default must win by more than 3 %:
-            // at the trial's candidate count the grids are often within noise,
-            // and later in a run, with more candidates, the default does best
-            const double score = g == kK2Grid ? ms : ms * 1.03;
+            // another collider grid than the default, and other chunks than the
+            // automatic ones, must each win by more than 3 %: at the trial's
+            // candidate count such neighbours are often within noise, and later
+            // in a run, with more candidates, the default grid does best
+            const double score = ms * (g == kK2Grid ? 1.0 : 1.03) * (shape == auto_shape ? 1.0 : 1.03);
             if (score < best_score) { best_score = score; best = ms; best_f = f; best_g = g; }
         }
         if (st) break;
