@@ -166,7 +166,9 @@ void window_for(int P, int Q, int nk, double lk_eV, bool fp32, int chunk, int bu
                 int* r0, int* l0, int* words) {
     const size_t fixed = k1_lds_bytes(P, Q, fp32 ? 1 : 0, 0, chunk) + 64;
     const double room = fixed < (size_t)budget ? (double)(budget - fixed) : 0.0;
-    int w = (int)std::floor(std::sqrt(room / (2.0 * Q)));
+    // node q counts in half (q & 1) of word (q >> 1) w^2 + r w + l: ceil(Q/2) planes of w^2 words
+    const int planes = (Q + 1) / 2;
+    int w = (int)std::floor(std::sqrt(room / (4.0 * planes)));
     const int cap = 2 * (int)std::ceil(kWinEv / (2.0 * lk_eV / nk));
     if (w > cap) w = cap;
     w &= ~1;
@@ -175,7 +177,7 @@ void window_for(int P, int Q, int nk, double lk_eV, bool fp32, int chunk, int bu
     *win = w;
     *r0 = (nk - w) / 2;
     *l0 = (nk - w) / 2;
-    *words = ((Q * w * w + 1) / 2 + 3) / 4 * 4;   // whole 16-byte slab rows
+    *words = (planes * w * w + 3) / 4 * 4;       // whole 16-byte slab rows
 }
 
 Layout layout_of(const sgpm_instance_desc& d, const HostTables& t, int64_t n_all) {

@@ -363,6 +363,14 @@ __device__ __forceinline__ K1Lds<T> k1_lds(unsigned char* smem, int PM, int Q, i
     return L;
 }
 
+// LDS window layout: node q counts in the 16-bit half (q & 1) of word
+// (q >> 1) W^2 + wr W + wl, (wr, wl) the cell relative to the window's corner,
+// so an even and an odd node share a plane of W^2 words and the increment of
+// a node known at compile time is a constant.
+__device__ __forceinline__ int win_word(int q, int W, int wr, int wl) {
+    return __mul24(q >> 1, W * W) + __mul24(wr, W) + wl;
+}
+
 // one nodal value into H^n: LDS window when inside it, else the overflow grid
 template <typename T>
 __device__ __forceinline__ void k1_bin(const K1Args<T>& a, const K1Lds<T>& L, const Consts<T>& c,
@@ -375,30 +383,9 @@ __device__ __forceinline__ void k1_bin(const K1Args<T>& a, const K1Lds<T>& L, co
     }
     const int wr = r - a.win_r0, wl = l - a.win_l0;
     if ((unsigned)wr < (unsigned)a.win && (unsigned)wl < (unsigned)a.win) {
-        const int idx = (q * a.win + wr) * a.win + wl;
-        atomicAdd(&L.hwin[idx >> 1], (idx & 1) ? 65536u : 1u);
+        atomicAdd(&L.hwin[win_word(q, a.win, wr, wl)], (q & 1) ? 65536u : 1u);
     } else {
         atomicAdd(&a.extra[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l], 1u);
-    }
-}
-
-// Node value into H^n with the common case made cheap: when every active lane
-// of the wave falls inside the LDS window (compared in floating point, so a
-// NaN fails), one packed LDS increment each; otherwise the general path.
-template <typename T>
-__device__ __forceinline__ void k1_bin_fast(const K1Args<T>& a, const K1Lds<T>& L,
-                                            const Consts<T>& c, int q, T kx, T ky, bool act) {
-    const T fr = floor((kx + c.lk) * c.inv_dk) - (T)a.win_r0;
-    const T fl = floor((ky + c.lk) * c.inv_dk) - (T)a.win_l0;
-    const T w = (T)a.win;
-    const bool inwin = fr >= (T)0 && fr < w && fl >= (T)0 && fl < w;
-    if (__ballot(act && !inwin) == 0) {
-        if (act) {
-            const int idx = (q * a.win + (int)fr) * a.win + (int)fl;
-            atomicAdd(&L.hwin[idx >> 1], 1u << ((idx & 1) << 4));
-        }
-    } else if (act) {
-        k1_bin<T>(a, L, c, q, kx, ky);
     }
 }
 
@@ -529,10 +516,9 @@ k1_stream(const K1Args<T>* __restrict__ all,
                                 const T fl = floor((ky + c.lk) * c.inv_dk) - (T)a.win_l0;
                                 const T w = (T)a.win;
                                 const bool in = (fr >= (T)0) & (fr < w) & (fl >= (T)0) & (fl < w);
-                                if (on && in) {
-                                    const int idx = __mul24(__mul24(q, a.win) + (int)fr, a.win) + (int)fl;
-                                    atomicAdd(&L.hwin[idx >> 1], 1u << ((idx & 1) << 4));
-                                }
+                                if (on && in)
+                                    atomicAdd(&L.hwin[win_word(q, a.win, (int)fr, (int)fl)],
+                                              (q & 1) ? 65536u : 1u);
                                 outmask |= (on && !in) ? (1u << q) : 0u;
                             }
                             // after the drift, for the rate bound
@@ -1117,6 +1103,7 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
     const int tid = threadIdx.x;
     const int cells = a.nk * a.nk;
     const int wcells = a.win * a.win;
+    const int wwords = (a.Q + 1) / 2 * wcells;   // window words in use (planes of wcells)
     __shared__ uint32_t part[kK3Lanes][kK3Words][2];
     __shared__ uint32_t smax[kMaxQ];
     __shared__ uint32_t scap[kMaxQ], sex[kMaxQ];
@@ -1142,12 +1129,15 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
             uint32_t ex[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const int idx = 2 * word0 + k;          // cell k of the thread's four words
-                const bool ok = idx < a.Q * wcells;
-                const int q = ok ? idx / wcells : 0, rem = idx - q * wcells;
+                // half k & 1 of word k >> 1 of the thread's four: node 2 p + (k & 1)
+                // of plane p (the window layout of win_word)
+                const int word = word0 + (k >> 1);
+                const int p = word / wcells, rem = word - p * wcells;
+                const int q = 2 * p + (k & 1);
+                const bool ok = word < wwords && q < a.Q;
                 const int r = a.win_r0 + rem / a.win, l = a.win_l0 + rem % a.win;
                 qc[k] = ok ? q : -1;
-                gc[k] = (size_t)q * cells + (size_t)r * a.nk + l;
+                gc[k] = ok ? (size_t)q * cells + (size_t)r * a.nk + l : 0;
                 ex[k] = ok ? a.extra[gc[k]] : 0u;
             }
 #pragma unroll
@@ -1175,11 +1165,12 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
         int q_set = -1;
         uint32_t ex_set = 0u;
         if (tid < 2 * kK3Words) {
+            // half tid & 1 of the block's word tid >> 1 (the window layout of win_word)
             const int word = wb * kK3Words + (tid >> 1);
-            const int idx = 2 * word + (tid & 1);
-            if (word < a.hwin_words && idx < a.Q * wcells) {
-                q_set = idx / wcells;
-                const int rem = idx - q_set * wcells;
+            const int p = word / wcells, rem = word - p * wcells;
+            const int q = 2 * p + (tid & 1);
+            if (word < wwords && q < a.Q) {
+                q_set = q;
                 const int r = a.win_r0 + rem / a.win, l = a.win_l0 + rem % a.win;
                 g_set = (size_t)q_set * cells + (size_t)r * a.nk + l;
                 ex_set = a.extra[g_set];
