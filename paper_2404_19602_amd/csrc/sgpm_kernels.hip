@@ -312,18 +312,22 @@ __device__ __forceinline__ int find_slot(const uint32_t* __restrict__ wg0, int n
 }
 
 // ======================================================= K1: stream kernel
+// LDS of the stream kernel.  The fixed part comes first, at offsets known at
+// compile time for a node bucket (QA: the bucket's node count; the many-node
+// path uses Q), so that every table read is one base register plus an
+// immediate offset: consts, psi, eps0sq, shift, psimax, drift, pdrift, the
+// per-wave moment sums and the counters.  Then the window and the candidate
+// buffer, whose sizes are set at run time.
+__host__ __device__ constexpr size_t k1_fixed_bytes(int PM, int QA, size_t s, int waves) {
+    return ((((((sizeof(Consts<double>) + 15) & ~(size_t)15) +
+               s * ((size_t)QA * PM + 2 * (size_t)QA + 3 * (size_t)PM) + 15) & ~(size_t)15) +
+             (size_t)waves * QA * 3 * 8 + 16 * 4) + 15) & ~(size_t)15;
+}
+
 size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words, int chunk) {
-    const size_t s = fp32 ? 4 : 8;
-    const int PM = pmax_bucket(P);
-    size_t off = (size_t)hwin_words * 4 + (size_t)chunk * 4;   // window, candidate buffer
-    off = (off + 15) & ~(size_t)15;
-    off += sizeof(Consts<double>);                       // consts (either precision fits)
-    off = (off + 15) & ~(size_t)15;
-    off += s * ((size_t)Q * PM + 2 * Q + 3 * PM);       // psi, eps0sq, shift, psimax, drift, pdrift
-    off = (off + 15) & ~(size_t)15;
-    off += (size_t)k1_waves(fp32 != 0, PM, qmax_bucket(Q)) * Q * 3 * 8;   // per-wave moment sums
-    off += 16 * 4;                                       // counters
-    return off;
+    const int PM = pmax_bucket(P), qb = qmax_bucket(Q);
+    return k1_fixed_bytes(PM, qb > 0 ? qb : Q, fp32 ? 4 : 8, k1_waves(fp32 != 0, PM, qb)) +
+           (size_t)hwin_words * 4 + (size_t)chunk * 4;   // window, candidate buffer
 }
 
 template <typename T>
@@ -339,27 +343,26 @@ struct K1Lds {
 };
 
 template <typename T>
-__device__ __forceinline__ K1Lds<T> k1_lds(unsigned char* smem, int PM, int Q, int hwin_words,
-                                           int chunk, int waves) {
+__device__ __forceinline__ K1Lds<T> k1_lds(unsigned char* smem, int PM, int QA, int hwin_words,
+                                           int waves) {
     K1Lds<T> L;
-    L.hwin = reinterpret_cast<uint32_t*>(smem);
-    L.cbuf = reinterpret_cast<int*>(smem + (size_t)hwin_words * 4);
-    size_t off = (size_t)hwin_words * 4 + (size_t)chunk * 4;
-    off = (off + 15) & ~(size_t)15;
-    L.c = reinterpret_cast<Consts<T>*>(smem + off);
-    off += sizeof(Consts<double>);
-    off = (off + 15) & ~(size_t)15;
+    size_t off = 0;
+    L.c = reinterpret_cast<Consts<T>*>(smem);
+    off = (sizeof(Consts<double>) + 15) & ~(size_t)15;
     L.psi = reinterpret_cast<T*>(smem + off);
-    L.eps0sq = L.psi + Q * PM;
-    L.shift = L.eps0sq + Q;
-    L.psimax = L.shift + Q;
+    L.eps0sq = L.psi + QA * PM;
+    L.shift = L.eps0sq + QA;
+    L.psimax = L.shift + QA;
     L.drift = L.psimax + PM;
     L.pdrift = L.drift + PM;
-    off += sizeof(T) * ((size_t)Q * PM + 2 * Q + 3 * PM);
+    off += sizeof(T) * ((size_t)QA * PM + 2 * QA + 3 * PM);
     off = (off + 15) & ~(size_t)15;
     L.red = reinterpret_cast<double*>(smem + off);
-    off += (size_t)waves * Q * 3 * 8;
+    off += (size_t)waves * QA * 3 * 8;
     L.cnt = reinterpret_cast<uint32_t*>(smem + off);
+    off = k1_fixed_bytes(PM, QA, sizeof(T), waves);
+    L.hwin = reinterpret_cast<uint32_t*>(smem + off);
+    L.cbuf = reinterpret_cast<int*>(smem + off + (size_t)hwin_words * 4);
     return L;
 }
 
@@ -429,7 +432,7 @@ k1_stream(const K1Args<T>* __restrict__ all,
         a.excess[(size_t)(step - a.dyn->rec_base) * a.Q + threadIdx.x] = 0u;
     const T dt = (T)a.dyn->dt;
     const int P = a.P, Q = a.Q;
-    const K1Lds<T> L = k1_lds<T>(smem, PMAX, Q, a.hwin_words, (int)a.chunk, WAVES);
+    const K1Lds<T> L = k1_lds<T>(smem, PMAX, QMAX > 0 ? QMAX : Q, a.hwin_words, WAVES);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     for (int w = tid; w < (a.hwin_words >> 2); w += BLOCK)        // whole 16-byte rows
