@@ -398,9 +398,9 @@ __device__ __forceinline__ void k1_bin(const K1Args<T>& a, const K1Lds<T>& L, co
 // xi > 1 - gb dt.
 template <typename T>
 __device__ __forceinline__ bool k1_candidate(const K1Args<T>& a, const Consts<T>& c, int64_t i, T ub,
-                                             uint32_t step, T dt) {
+                                             uint32_t step, T dt, uint32_t seed_lo, uint32_t seed_hi) {
     const T t = rate_bound<T>(c, ub) * dt;
-    const Words wx = philox10((uint32_t)i, step, kPurXi, a.instance, a.seed_lo, a.seed_hi);
+    const Words wx = philox10((uint32_t)i, step, kPurXi, a.instance, seed_lo, seed_hi);
     const T xi = uni<T>(wx.w0, wx.w1);
     if (xi <= (T)1 - t * c.b_margin) return false;
     return !(-dlog(xi) >= t);
@@ -478,6 +478,12 @@ k1_stream(const K1Args<T>* __restrict__ all,
         for (int64_t base = begin; base < end; base += BLOCK) {
             const int64_t i = base + tid;
             const bool act = FULL || i < end;
+            // the node count and the key are re-read (empty asm) on every tile so
+            // that the compiler does not keep the per-node tests and the key
+            // schedule in scalar registers across the loop, which spills them
+            int Qt = Q;
+            uint32_t key_lo = a.seed_lo, key_hi = a.seed_hi;
+            __asm__ volatile("" : "+s"(Qt), "+s"(key_lo), "+s"(key_hi));
             T cx[PMAX], cy[PMAX];
             load_tile_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, base, act ? (uint32_t)tid : 0u, cx, cy);
             bool cand = false;
@@ -489,7 +495,7 @@ k1_stream(const K1Args<T>* __restrict__ all,
                     uint32_t outmask = 0u;
     #pragma unroll
                     for (int q = 0; q < QMAX; ++q) {
-                        if (q < Q) {
+                        if (q < Qt) {
                             T kx, ky;
                             eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
                             // read before the histogram increment, which the compiler
@@ -545,7 +551,8 @@ k1_stream(const K1Args<T>* __restrict__ all,
                 const T e2max = nodes();
                 // the nodal energies after the drift, bounded with a relative
                 // margin for the rounding of the shifted evaluation
-                if (act && moving) cand = k1_candidate<T>(a, c, i, sqrt(e2max) * c.b_margin, step, dt);
+                if (act && moving)
+                    cand = k1_candidate<T>(a, c, i, sqrt(e2max) * c.b_margin, step, dt, key_lo, key_hi);
             } else {
                 // blocks of four nodes, their twelve sums reduced over the wave together
                 for (int q0 = 0; q0 < Q; q0 += 4) {
@@ -577,7 +584,8 @@ k1_stream(const K1Args<T>* __restrict__ all,
                         bx += fabs(cx[h] - L.drift[h]) * L.psimax[h];
                         by += fabs(cy[h]) * L.psimax[h];
                     }
-                    cand = k1_candidate<T>(a, c, i, sqrt(bx * bx + by * by + c.eps0max_sq), step, dt);
+                    cand = k1_candidate<T>(a, c, i, sqrt(bx * bx + by * by + c.eps0max_sq), step, dt,
+                                           key_lo, key_hi);
                 }
             }
             if (act && moving && !cand) {

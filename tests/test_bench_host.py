@@ -56,6 +56,23 @@ def test_roofline_is_the_dominant_kernel():
     r["kernels"]["collide"] = (0.060, 200)
     roof, _ = bench.roofline_of(cfg, r, 6, 8)
     assert roof["kernel"] == "sgpm::k2_collide"
+    assert "close" not in roof            # the stream kernel is 17 % shorter
+
+
+def test_roofline_keeps_the_stream_kernel_within_the_margin():
+    """A collider within 5 % of the stream kernel does not take the roofline; it
+    is listed beside it with its own fraction of peak."""
+    cfg = headline()
+    r = {"n_drift": 1, "cand": (15_696.0,),
+         "kernels": {"stream": (0.050, 200), "finalize": (0.012, 200), "collide": (0.052, 200)}}
+    roof, per = bench.roofline_of(cfg, r, 6, 8)
+    assert roof["kernel"] == "sgpm::k1_stream"
+    assert [c["kernel"] for c in roof["close"]] == ["sgpm::k2_collide"]
+    assert roof["close"][0]["frac"] == pytest.approx(per["collide"]["GBps"] / 8000.0)
+    r["kernels"]["collide"] = (0.0526, 200)       # more than 5 % longer: it dominates
+    roof, _ = bench.roofline_of(cfg, r, 6, 8)
+    assert roof["kernel"] == "sgpm::k2_collide"
+    assert "close" not in roof                   # 0.050 < 0.0526 / 1.05
 
 
 def test_traffic_only_for_the_profiled_sources(monkeypatch):
