@@ -109,7 +109,8 @@ typedef struct {
     int32_t field_dim;      /* component of z driving the field, -1: deterministic */
     double field0, field_rel; /* E_x(z) = field0 (1 + field_rel z), V/m           */
     double fermi_eV;        /* Fermi level of the initial datum [0.4]              */
-    double temp_K;          /* lattice and initial temperature [300]               */
+    double temp_K;          /* lattice temperature: Bose factors, acoustic rate    */
+                            /* [300]                                                */
     double alpha;           /* self-scattering parameter of eq. gamma_tot [0.1]     */
     int32_t nk;             /* histogram cells per axis [240]                       */
     double lk_eV;           /* grid half-width L_k hbar v_F [5]                     */
@@ -126,6 +127,10 @@ typedef struct {
                             /*    collisions, drift dt/2 (higher-order splittings,  */
                             /*    Sec. 3); the Pauli lookup then moves the grid by  */
                             /*    the first half drift                              */
+    double init_temp_K;     /* temperature of the Fermi-Dirac initial datum and of  */
+                            /* the density n(z) of the current J = -e n V; 0 takes */
+                            /* temp_K [0].  A hot start (init_temp_K > temp_K) at  */
+                            /* zero field relaxes toward the lattice temperature    */
 } sgpm_instance_desc;
 
 /* Fill a descriptor with the paper's defaults (Table 1 and Sec. 5). */

@@ -46,19 +46,27 @@ class _Params(C.Structure):
         ("pauli", C.c_int), ("final_state", C.c_int),
         ("rate_scale", C.c_double * 6),
         ("seed", C.c_uint64), ("instance", C.c_uint32), ("c_max", C.c_int),
-        ("splitting", C.c_int),
+        ("splitting", C.c_int), ("init_temp_K", C.c_double),
     ]
 
 
 _lib = None
 
 
+def lib_path() -> str:
+    """The shared object to load: the built oracle, or a copy named by
+    SGPM_ORACLE_LIB (the mutation tests load deliberately broken builds
+    of this source that way, in a process of their own)."""
+    return os.environ.get("SGPM_ORACLE_LIB") or _LIB
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = lib_path()
+        if path == _LIB and not os.path.exists(_LIB):
             build()
-        L = C.CDLL(_LIB)
+        L = C.CDLL(path)
         P = C.c_void_p
         dp = C.POINTER(C.c_double)
         up = C.POINTER(C.c_uint32)
@@ -119,7 +127,8 @@ def _up(a):
 DEFAULTS = dict(dim_z=0, degree=0, nodes_1d=1, n_particles=1000, gap_mode=0, gap_dim=-1,
                 gap0=0.2, gap_rel=0.0, field_dim=-1, field0=1e6, field_rel=0.0,
                 fermi_eV=0.4, temp_K=300.0, alpha=0.1, nk=240, lk_eV=5.0, pauli=1,
-                final_state=0, rate_scale=(1.0,) * 6, seed=1, instance=0, c_max=32, splitting=0)
+                final_state=0, rate_scale=(1.0,) * 6, seed=1, instance=0, c_max=32, splitting=0,
+                init_temp_K=0.0)
 
 
 def _params(cfg: dict) -> _Params:

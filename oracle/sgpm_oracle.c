@@ -196,7 +196,7 @@ int orc_num_modes(int dim_z, int degree)
 /* ------------------------------------------------------------------------ */
 static double fd_weight(const orc_sim *s, double e)
 {
-    return e / (1.0 + exp((e - s->p.fermi_eV) / s->kT_eV));
+    return e / (1.0 + exp((e - s->p.fermi_eV) / s->kT0_eV));
 }
 
 /* integral of eps f_FD over [a, b] by 10-point Gauss-Legendre */
@@ -207,7 +207,8 @@ static double fd_integral(const orc_sim *s, double a, double b)
     return acc * h;
 }
 
-/* Per node: panels of width kT/2 from eps0 to max(eps_F, eps0) + 80 kT,
+/* Per node: panels of width kT/2 from eps0 to max(eps_F, eps0) + 80 kT
+ * (T the temperature of the initial datum),
  * with cumulative integrals from below (lo) and from above (hi).  The
  * neglected tail is about e^-80 of the total, below 1e-18 of the smallest
  * upper-tail probability a 52-bit uniform can ask for (2^-53 ~ e^-36.7). */
@@ -220,8 +221,8 @@ static void build_cdf_tables(orc_sim *s)
     s->cdf_hi = (double **)calloc((size_t)Q, sizeof(double *));
     for (int q = 0; q < Q; ++q) {
         double a = s->eps0[q];
-        double top = (s->p.fermi_eV > a ? s->p.fermi_eV : a) + 80.0 * s->kT_eV;
-        double hpan = 0.5 * s->kT_eV;
+        double top = (s->p.fermi_eV > a ? s->p.fermi_eV : a) + 80.0 * s->kT0_eV;
+        double hpan = 0.5 * s->kT0_eV;
         int np = (int)ceil((top - a) / hpan);
         s->cdf_np[q] = np;
         s->cdf_x[q] = (double *)malloc(sizeof(double) * (size_t)(np + 1));
@@ -302,6 +303,7 @@ orc_sim *orc_create(const orc_params *p)
     if (p->degree < 0 || p->nodes_1d < 1) return NULL;
     if (p->n_particles < 1) return NULL;
     if (p->temp_K <= 0 || p->nk < 1 || p->lk_eV <= 0 || p->alpha < 0) return NULL;
+    if (!(p->init_temp_K >= 0)) return NULL;
     if (p->gap_dim >= p->dim_z || p->field_dim >= p->dim_z) return NULL;
     if (p->c_max < 1 || p->c_max > 255) return NULL;
 
@@ -309,6 +311,7 @@ orc_sim *orc_create(const orc_params *p)
     s->p = *p;
     s->hbar = H_PLANCK / (2.0 * PI_D);
     s->kT_eV = K_B * p->temp_K / Q_E;
+    s->kT0_eV = K_B * (p->init_temp_K > 0 ? p->init_temp_K : p->temp_K) / Q_E;
     s->P = orc_num_modes(p->dim_z, p->degree);
     int n1 = p->nodes_1d;
     s->Q = (p->dim_z == 0) ? 1 : (p->dim_z == 1 ? n1 : n1 * n1);
@@ -952,8 +955,7 @@ void orc_moments_at(const orc_sim *s, int nz, const double *z, double *out)
             vy += V_F * ay / eps;
             en += eps;
         }
-        double kT = K_B * s->p.temp_K / Q_E;
-        double n = orc_density_closed(e0, s->p.fermi_eV, kT, s->hbar);
+        double n = orc_density_closed(e0, s->p.fermi_eV, s->kT0_eV, s->hbar);
         out[j * 4 + 0] = vx / (double)N;
         out[j * 4 + 1] = vy / (double)N;
         out[j * 4 + 2] = en / (double)N;

@@ -34,6 +34,8 @@ typedef struct {
     int splitting;      /* 0: drift dt then collisions (the paper's first-order
                            splitting); 1: Strang, drift dt/2, collisions, drift
                            dt/2 (Sec. 3 mentions higher-order splittings)      */
+    double init_temp_K; /* temperature of the Fermi-Dirac initial datum (and of
+                           the density n used for J); 0 = temp_K              */
 } orc_params;
 
 typedef struct {
@@ -43,7 +45,8 @@ typedef struct {
 typedef struct {
     orc_params p;
     int P, Q;
-    double hbar, kT_eV;
+    double hbar, kT_eV;     /* lattice k_B T: Bose factors, acoustic rate       */
+    double kT0_eV;          /* k_B T of the Fermi-Dirac initial datum           */
     double *z, *w, *psi, *Ehat, *eps0, *width, *field, *density;
     double C_ac, C_O, C_K, n_O, n_K, hw_O, hw_K, edge_kappa_coef;
     double *C_edge;

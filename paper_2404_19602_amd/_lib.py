@@ -31,6 +31,7 @@ class Desc(C.Structure):
         ("rate_scale", C.c_double * 6),
         ("seed", C.c_uint64), ("instance_id", C.c_uint32), ("c_max", C.c_int32),
         ("max_steps", C.c_int32), ("splitting", C.c_int32),
+        ("init_temp_K", C.c_double),
     ]
 
 
@@ -98,7 +99,8 @@ def check(status: int, ctx, what: str):
 _DEFAULTS = dict(dim_z=0, degree=0, nodes_1d=1, n_particles=10000, gap_mode=0, gap_dim=-1,
                  gap0=0.2, gap_rel=0.0, field_dim=-1, field0=1e6, field_rel=0.0, fermi_eV=0.4,
                  temp_K=300.0, alpha=0.1, nk=240, lk_eV=5.0, pauli=1, final_state=0,
-                 rate_scale=(1.0,) * 6, seed=1, instance=0, c_max=32, splitting=0)
+                 rate_scale=(1.0,) * 6, seed=1, instance=0, c_max=32, splitting=0,
+                 init_temp_K=0.0)
 
 
 def desc_from_cfg(cfg: dict, max_steps: int | None = None) -> Desc:

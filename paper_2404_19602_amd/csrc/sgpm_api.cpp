@@ -673,6 +673,7 @@ void sgpm_default_desc(sgpm_instance_desc* d) {
     d->nk = 240; d->lk_eV = 5.0; d->pauli = 1; d->final_state = 0;
     for (int m = 0; m < 6; ++m) d->rate_scale[m] = 1.0;
     d->seed = 1; d->instance_id = 0; d->c_max = 32; d->max_steps = 1000; d->splitting = 0;
+    d->init_temp_K = 0.0;
 }
 
 const char* sgpm_status_string(sgpm_status s) {
@@ -1056,7 +1057,7 @@ sgpm_status sgpm_init_particles(sgpm_ctx* c) {
         a.n = I.n; a.P = I.P; a.Q = I.Q;
         a.wpsi = I.d_wpsi; a.eps0 = I.d_eps0; a.cdf_lo = I.d_cdf_lo; a.cdf_hi = I.d_cdf_hi;
         a.gl = I.d_gl; a.cdf_np = I.t.cdf_np; a.cdf_h = I.t.cdf_h;
-        a.mu = I.d.fermi_eV; a.kT = I.t.kT;
+        a.mu = I.d.fermi_eV; a.kT = I.t.kT_init;
         a.seed_lo = (uint32_t)(I.d.seed & 0xFFFFFFFFu);
         a.seed_hi = (uint32_t)(I.d.seed >> 32);
         a.instance = I.d.instance_id;
@@ -1390,7 +1391,7 @@ sgpm_status sgpm_moments_at(sgpm_ctx* c, int32_t inst, int32_t n_z, const double
             const double e0 = eps0_at(I, zz);
             if (!(e0 > 0)) return fail(c, SGPM_EINVAL, "gap not positive at a requested z");
             host[(size_t)j * (P + 1) + P] = e0;
-            dens[j] = density_at(e0, I.d.fermi_eV, I.t.kT);
+            dens[j] = density_at(e0, I.d.fermi_eV, I.t.kT_init);
         }
         HIPCHK(c, hipMemcpyAsync(I.zpsi, host.data(), (size_t)nz * (P + 1) * 8,
                                  hipMemcpyHostToDevice, c->stream));

@@ -33,7 +33,9 @@ struct HostTables {
     std::vector<double> density;// [Q] electrons per m^2
     std::vector<double> cedge;  // [Q] edge prefactor, 1/(s eV), per unit angular integral
     double c_ac = 0, c_o = 0, c_k = 0;   // 1/(s eV)
-    double n_o = 0, n_k = 0, hw_o = 0, hw_k = 0, kT = 0;
+    double n_o = 0, n_k = 0, hw_o = 0, hw_k = 0;
+    double kT = 0;              // lattice k_B T (eV): Bose factors, acoustic rate
+    double kT_init = 0;         // k_B T (eV) of the Fermi-Dirac initial datum and density
     double edge_kap = 0;        // 2 a^2 / (hbar v_F)^2 in 1/eV^2
     double v_f = 0;             // m/s
     double gl10_x[10], gl10_w[10];

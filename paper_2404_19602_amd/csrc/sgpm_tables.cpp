@@ -125,6 +125,7 @@ const char* build_tables(const sgpm_instance_desc& d, HostTables& t) {
     if (d.n_particles < 1) return "n_particles must be >= 1";
     if (d.n_particles > (int64_t)2000000000) return "n_particles above 2e9";
     if (!(d.temp_K > 0) || !std::isfinite(d.temp_K)) return "temp_K must be > 0";
+    if (!(d.init_temp_K >= 0) || !std::isfinite(d.init_temp_K)) return "init_temp_K must be >= 0";
     if (d.nk < 2 || d.nk > 4096) return "nk must be in [2, 4096]";
     if (!(d.lk_eV > 0)) return "lk_eV must be > 0";
     if (!(d.alpha >= 0) || !std::isfinite(d.alpha)) return "alpha must be >= 0";
@@ -177,6 +178,7 @@ const char* build_tables(const sgpm_instance_desc& d, HostTables& t) {
     const double hvf_eVm = hbar * kVF / kE;      // hbar v_F in eV m
     t.v_f = kVF;
     t.kT = kKB * d.temp_K / kE;
+    t.kT_init = kKB * (d.init_temp_K > 0 ? d.init_temp_K : d.temp_K) / kE;
     t.eps0.assign(Q, 0.0);
     t.width.assign(Q, 0.0);
     t.field.assign(Q, 0.0);
@@ -231,15 +233,16 @@ const char* build_tables(const sgpm_instance_desc& d, HostTables& t) {
 
     gauss_legendre(10, t.gl10_x, t.gl10_w);
 
-    // Fermi-Dirac energy CDF per node (density eps f_FD on [eps0, inf)):
-    // panels of kT/2 up to max(mu, eps0) + 80 kT, 10-point Gauss per panel.
+    // Fermi-Dirac energy CDF per node (density eps f_FD on [eps0, inf)) at the
+    // temperature of the initial datum: panels of kT/2 up to max(mu, eps0) +
+    // 80 kT, 10-point Gauss per panel.
     double e0min = t.eps0[0], e0max = t.eps0[0];
     for (int q = 1; q < Q; ++q) {
         e0min = std::fmin(e0min, t.eps0[q]);
         e0max = std::fmax(e0max, t.eps0[q]);
     }
-    t.cdf_h = 0.5 * t.kT;
-    double top = std::fmax(d.fermi_eV, e0max) + 80.0 * t.kT;
+    t.cdf_h = 0.5 * t.kT_init;
+    double top = std::fmax(d.fermi_eV, e0max) + 80.0 * t.kT_init;
     t.cdf_np = (int)std::ceil((top - e0min) / t.cdf_h);
     if (t.cdf_np < 4) t.cdf_np = 4;
     const int np = t.cdf_np;
@@ -252,7 +255,7 @@ const char* build_tables(const sgpm_instance_desc& d, HostTables& t) {
             double a = t.eps0[q] + j * t.cdf_h, b = a + t.cdf_h;
             double c = 0.5 * (a + b), hw = 0.5 * (b - a), s = 0.0;
             for (int k = 0; k < 10; ++k)
-                s += t.gl10_w[k] * fd_density(c + hw * t.gl10_x[k], d.fermi_eV, t.kT);
+                s += t.gl10_w[k] * fd_density(c + hw * t.gl10_x[k], d.fermi_eV, t.kT_init);
             pan[j] = s * hw;
         }
         double* lo = &t.cdf_lo[(size_t)q * (np + 1)];
