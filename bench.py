@@ -1,21 +1,25 @@
 """Benchmark of the sG-PM hot path on one MI355X.
 
-Headline workload: sg_gap_m5_q8_n1e6 -- 1e6 particles, uncertain band gap
-Delta(z) = 0.2 eV (1 + 0.1 z), Legendre order M = 5 (6 modes), 8 Gauss nodes,
-E = 20 kV/cm, dt = 2 fs, FP64 particle state (the plain form), the paper's
-rates and the Pauli acceptance on a 240 x 240 grid.  A step is one pass of
-the whole hot path (drift, node evaluation, histogram, moments, collision
-decision, nodal collisions, projection) over every particle, launched the
-library's default way (captured HIP graphs of 16 steps).
+Headline workload: sg_gap_m8_q12_n3e7 -- the largest single-GPU workload:
+3e7 particles, uncertain band gap Delta(z) = 0.25 eV (1 + 0.2 z), Legendre
+order M = 8 (9 modes), 12 Gauss nodes, E = 40 kV/cm, dt = 2 fs, FP64
+particle state (the plain form), the paper's rates and the Pauli acceptance
+on a 256 x 256 grid rebuilt every step.  A step is one pass of the whole hot
+path (drift, node evaluation, histogram, moments, collision decision, nodal
+collisions, projection) over every particle, launched the library's default
+way (captured HIP graphs of 16 steps).
 
 The same K steps are then run once more with a HIP event after every kernel
-launch (on the library's stream) to time each kernel; the roofline is that
-of the kernel with the largest mean time, from its algorithmic bytes per
-launch.  The same workload with FP32 particle state is run beside it and
-compared against the Monte Carlo standard error, and the 64-instance batched
-FP32 sweep is timed in one shared launch per kernel and step.  The CPU
-baseline is the plain FP64 oracle on a bounded sample of the headline
-workload, on the host cores.
+launch (on the library's stream) to time each kernel.  ``roofline`` is that
+of the longest kernel, from its algorithmic bytes per launch;
+``roofline_step`` is the whole step's, from the algorithmic bytes of one
+step over the wall time per step.  Beside the headline: the same workload
+with FP32 particle state (compared per observable against the Monte Carlo
+standard error), the 8-node workload (1e6 particles) in FP64, and the
+64-instance sweep in FP32 batched (one launch per kernel and step), in FP64
+batched and in FP64 plain (each instance alone), compared per instance and
+observable.  The CPU baseline is the plain FP64 oracle on a bounded sample of
+the headline workload, on the host cores.
 
 Prints one JSON line.  Throughput is particle-node updates per second with
 the state resident in HBM.
@@ -33,11 +37,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-DOMINANCE_MARGIN = 1.05
-WORKLOAD = "sg_gap_m5_q8_n1e6"
+WORKLOAD = "sg_gap_m8_q12_n3e7"
+SECONDARY = "sg_gap_m5_q8_n1e6"
 KERNEL_SYMBOLS = {"stream": "sgpm::k1_stream", "finalize": "sgpm::k3_finalize",
                   "collide": "sgpm::k2_collide"}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_sg_gap_m5_q8_n1e6.json")
+# kernel-name patterns of the headline's FP64 launches in a profiler's output
+HEADLINE_KERNELS = {"stream": "k1_stream<double", "finalize": "k3_finalize",
+                    "collide": "k2_collide"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_sg_gap_m8_q12_n3e7.json")
+OBSERVABLES = ("E_vx", "Var_vx", "E_jx", "Var_jx", "E_energy")
 
 
 def log(msg: str):
@@ -70,7 +78,7 @@ def kernel_bytes(cfg: dict, P: int, Q: int, n_drift: int, cand: float) -> dict:
 
 def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True, tune: bool = True):
     """Warm-up, the autotuned launch shape (trials from the warmed-up state,
-    which is put back; the moment record restarts there), K timed steps in
+    which is put back), K timed steps in
     the default launch mode, then the same K steps once more from the same
     state and step (the random streams are keyed by the step, so the run is
     replayed exactly) with a HIP event around every kernel: the per-kernel
@@ -98,10 +106,14 @@ def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True, tune: bool = Tr
     wall = time.perf_counter() - t0
     dev_ms = sim.last_step_ms()
     c1 = [sim.counters(j) for j in range(sim.n_inst)]
-    out = dict(sim=sim, wall=wall, dev_ms=dev_ms, shape=shape, tuned_ms=tuned_ms,
+    out = dict(sim=sim, wall=wall, steps=steps, dev_ms=dev_ms, shape=shape, tuned_ms=tuned_ms,
                cand=[(b["candidates"] - a["candidates"]) / steps for a, b in zip(c0, c1)])
+    # the record of the timed steps: their last steps + 1 recorded times (the
+    # autotuner may have restarted the record at the tuned time)
+    out["moments_all"] = [sim.moments(sim.record_length(j) - steps - 1, steps + 1, inst=j)
+                          for j in range(sim.n_inst)]
     if not many:
-        out["moments"] = sim.moments(0, steps + 1)
+        out["moments"] = out["moments_all"][0]
         t = sim.tables()
         out["n_drift"] = int(np.count_nonzero(t["ehat"]))
     if profile:
@@ -115,35 +127,32 @@ def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True, tune: bool = Tr
 
 
 def roofline_of(cfg, r, P, Q) -> tuple:
-    """Per-kernel achieved GB/s and the roofline object of the dominant kernel."""
+    """Per-kernel achieved GB/s, the roofline object of the dominant kernel (the
+    one with the largest mean launch time) and that of the whole step (the
+    algorithmic bytes of the three launches of a step over the wall time per
+    graph-replayed step)."""
     b = kernel_bytes(cfg, P, Q, r["n_drift"], r["cand"][0])
     per = {}
     for k, (ms, n) in r["kernels"].items():
         per[k] = {"avg_ms": ms, "launches": n, "bytes_per_launch": b[k],
                   "GBps": b[k] / (ms * 1e-3) / 1e9 if ms > 0 else None}
-    # The dominant kernel is the longest, except that the stream kernel (the one
-    # HBM bounds) is kept unless another takes more than DOMINANCE_MARGIN longer:
-    # within that margin the event timings do not order them run to run, and the
-    # collider is latency-bound.  Kernels within the margin are listed in "close".
     dom = max(per, key=lambda k: per[k]["avg_ms"])
-    if dom != "stream" and per[dom]["avg_ms"] <= DOMINANCE_MARGIN * per["stream"]["avg_ms"]:
-        dom = "stream"
     ach = per[dom]["GBps"]
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": KERNEL_SYMBOLS[dom],
             "kernel_ms": per[dom]["avg_ms"], "bytes_per_launch": per[dom]["bytes_per_launch"],
             "timing": "HIP events around each launch on the library's stream, "
                       "in a replay of the timed steps from the same state"}
-    close = [{"kernel": KERNEL_SYMBOLS[k], "kernel_ms": per[k]["avg_ms"],
-              "achieved_GBps": per[k]["GBps"], "frac": per[k]["GBps"] / HBM_PEAK_GBS}
-             for k in per if k != dom and per[k]["avg_ms"] >= per[dom]["avg_ms"] / DOMINANCE_MARGIN]
-    if close:
-        roof["close"] = close
     shape = r.get("shape") or {}
     traffic = measured_traffic(dom, shape.get("stream_workgroups"))
     if traffic is not None:
         roof["traffic"] = traffic
-    return roof, per
+    step_bytes = sum(b.values())
+    step_ms = r["wall"] * 1e3 / r["steps"]
+    step = {"bound": "hbm", "achieved": step_bytes / (step_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "bytes_per_step": step_bytes, "ms_per_step": step_ms}
+    step["frac"] = step["achieved"] / HBM_PEAK_GBS
+    return roof, per, step
 
 
 def measured_traffic(kernel: str, stream_workgroups=None):
@@ -176,11 +185,9 @@ def uq_timings(cfg: dict, steps: int = 100, n: int = 50_000, samples: int = 256)
 
     log(f"uq: MC-MC with {samples} samples x {n} particles vs MC-sG, {steps} steps")
     z = uq.sample_z(samples, 1, 7)
-    cfgs = []
-    for k in range(samples):
-        c = uq.deterministic_at(cfg, z[k])
+    cfgs = uq.deterministic_at(cfg, z)
+    for k, c in enumerate(cfgs):
         c.update(instance=k, n_particles=n)
-        cfgs.append(c)
     res = {}
     for name, cf in (("mc_mc", cfgs), ("mc_sg", dict(cfg, n_particles=n))):
         sim = sg.Simulation(cf, max_steps=steps + 30)
@@ -211,8 +218,7 @@ def uq_timings(cfg: dict, steps: int = 100, n: int = 50_000, samples: int = 256)
 
 
 OTHER_CONFIGS = (("gnr_det_n1e4", ("fp64",)),
-                 ("sg_gap_field_td4_q64_n4e6", ("fp64", "fp32")),
-                 ("sg_gap_m8_q12_n3e7", ("fp64", "fp32")))
+                 ("sg_gap_field_td4_q64_n4e6", ("fp64", "fp32")))
 
 
 def other_configs(steps: int = 50) -> dict:
@@ -248,8 +254,8 @@ def other_configs(steps: int = 50) -> dict:
     return res
 
 
-def cpu_baseline(cfg: dict):
-    """The FP64 oracle on a bounded sample: 200 000 of the particles for 200
+def cpu_baseline(cfg: dict, n_s: int = 100_000, steps_s: int = 250):
+    """The FP64 oracle on a bounded sample: n_s of the particles for steps_s
     steps (about ten seconds), every host thread this process may use."""
     import oracle
     try:
@@ -257,7 +263,6 @@ def cpu_baseline(cfg: dict):
     except AttributeError:
         threads = os.cpu_count() or 1
     threads = max(1, min(threads, int(os.environ.get("OMP_NUM_THREADS", threads))))
-    n_s, steps_s = 200_000, 200
     scfg = dict(cfg, n_particles=n_s)
     sim = oracle.OracleSim(scfg, threads=threads)
     sim.init()
@@ -274,7 +279,8 @@ def cpu_baseline(cfg: dict):
 def pmc_summary(fetch_csv: str, write_csv: str, out_path: str = TRAFFIC_FILE,
                 steps: int = 20) -> dict:
     """The traffic record from two rocprofv3 --pmc runs of this bench with
-    --copy-calibration (FETCH_SIZE, then WRITE_SIZE; csv counter collections),
+    --copy-calibration --headline-only (FETCH_SIZE, then WRITE_SIZE; csv
+    counter collections),
     scaled by what the same counter reads for the 268435456-byte device copies,
     with the SHA-256 of the kernel sources they were taken on.
 
@@ -288,8 +294,7 @@ def pmc_summary(fetch_csv: str, write_csv: str, out_path: str = TRAFFIC_FILE,
     import csv
     import statistics
 
-    names = {"stream": "k1_stream<double, 6, 8>", "finalize": "k3_finalize",
-             "collide": "k2_collide<double, 6, 1>"}
+    names = HEADLINE_KERNELS
 
     def load(path, counter):
         by, seq = {}, []
@@ -356,6 +361,96 @@ def pmc_summary(fetch_csv: str, write_csv: str, out_path: str = TRAFFIC_FILE,
     return out
 
 
+def max_dev_over_se(ref: dict, other: dict) -> dict:
+    """max over the recorded times t >= 1 of |other - ref| / SE(ref), per observable"""
+    import numpy as np
+    out = {}
+    for obs in OBSERVABLES:
+        se = np.maximum(ref["SE_" + obs][1:], 1e-300)
+        out[obs] = float(np.max(np.abs(ref[obs][1:] - other[obs][1:]) / se))
+    return out
+
+
+def sweep_forms(steps: int, warmup: int = 10) -> dict:
+    """The 64-instance sweep three ways, the same steps from the same initial
+    data and random streams: FP32 batched and FP64 batched (one launch of each
+    kernel per step for every instance of a shape group, graph-replayed), and
+    FP64 plain (each instance in a context of its own, one after another; its
+    time is the sum).  Every instance's observables of the FP32-batched run
+    are compared with its FP64-plain run against the Monte Carlo SE."""
+    import numpy as np
+    import torch
+    import paper_2404_19602_amd as sg
+    from workloads import batched_sweep
+
+    cfgs = batched_sweep(steps=steps)
+    pn = sum(c["n_particles"] * (c["degree"] + 3) for c in cfgs) * steps
+    res = {"workload": "batched_sweep_64 (E 1-50 kV/cm, gap 0.1-0.5 eV +-10 %, M in {2,4,6}, "
+                       "Q = M + 3, N log-uniform 1e5-2e6)",
+           "instances": len(cfgs), "n_particles": sum(c["n_particles"] for c in cfgs),
+           "steps": steps, "unit": "particle-node updates/s"}
+    mom = {}
+    for form, prec in (("fp32_batched", "fp32"), ("fp64_batched", "fp64")):
+        log(f"sweep {form}: {len(cfgs)} instances, {warmup} warm-up + {steps} timed steps")
+        r = run_gpu([dict(c, precision=prec) for c in cfgs], steps, warmup, profile=(prec == "fp32"))
+        sim = r["sim"]
+        mom[form] = r["moments_all"]
+        res[form] = {"ms_per_step": r["wall"] * 1e3 / steps, "value": pn / r["wall"],
+                     "launch_shape_inst0": r["shape"], "candidates_per_step": sum(r["cand"])}
+        if "kernels" in r:
+            res[form]["kernels"] = {k: {"avg_ms": ms, "launches": n}
+                                    for k, (ms, n) in r["kernels"].items()}
+        del r, sim
+        torch.cuda.empty_cache()
+    log(f"sweep fp64_plain: {len(cfgs)} contexts one after another")
+    wall, plain = 0.0, []
+    for c in cfgs:
+        sim = sg.Simulation(dict(c, precision="fp64"), max_steps=warmup + steps)
+        sim.init_particles()
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+        plain.append(sim.moments(warmup, steps + 1))
+        del sim
+    res["fp64_plain"] = {"ms_per_step": wall * 1e3 / steps, "value": pn / wall}
+    worst = {obs: 0.0 for obs in OBSERVABLES}
+    for j in range(len(cfgs)):
+        for obs, v in max_dev_over_se(plain[j], mom["fp32_batched"][j]).items():
+            worst[obs] = max(worst[obs], v)
+        # the batched FP64 instance is the plain one, bit for bit
+        if not np.array_equal(plain[j]["E_vx"], mom["fp64_batched"][j]["E_vx"]):
+            res["fp64_batched_differs_from_plain"] = True
+    res["max_abs_dev_over_mc_se"] = worst
+    res["matched_error"] = all(v < 3.0 for v in worst.values())
+    res["speedup_fp32_batched_vs_fp64_plain"] = res["fp64_plain"]["ms_per_step"] / \
+        res["fp32_batched"]["ms_per_step"]
+    res["speedup_fp32_batched_vs_fp64_batched"] = res["fp64_batched"]["ms_per_step"] / \
+        res["fp32_batched"]["ms_per_step"]
+    return res
+
+
+def secondary_line(steps: int, warmup: int) -> dict:
+    """The 8-node workload (1e6 particles, M = 5) in FP64: per-step rate and
+    the rooflines of its dominant kernel and of its whole step."""
+    from workloads import workload
+    cfg = workload(SECONDARY, precision="fp64")
+    log(f"{SECONDARY}: FP64, {warmup} warm-up + {steps} timed + {steps} profiled steps")
+    r = run_gpu(cfg, steps, warmup)
+    P, Q = r["sim"].P, r["sim"].Q
+    roof, per, step = roofline_of(cfg, r, P, Q)
+    roof["traffic"] = None      # the traffic record is the headline's
+    out = {"workload": SECONDARY, "dtype": "f64", "n_particles": cfg["n_particles"],
+           "gpc_modes": P, "nodes": Q, "ms_per_step": r["wall"] * 1e3 / steps,
+           "value": cfg["n_particles"] * Q * steps / r["wall"], "unit": "particle-node updates/s",
+           "roofline": roof, "roofline_step": step, "kernels": per,
+           "candidates_per_step": r["cand"][0], "launch_shape": r["shape"]}
+    del r
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,9 +460,13 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison run")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance sweep")
     ap.add_argument("--batched-steps", type=int, default=100)
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 8-node, 1e6-particle FP64 line")
     ap.add_argument("--no-uq", action="store_true", help="skip the MC-MC / moments-at-z timings")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the timings of the other workloads at full size")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="the headline FP64 run alone (counter runs)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch shape of the headline (counter runs: "
                          "the traffic record then holds for that shape)")
@@ -385,9 +484,11 @@ def main():
         print(f"bench.py runs the step on one GPU (asked for {args.gpus}); the path is not "
               "sharded over several GPUs", file=sys.stderr)
         sys.exit(2)
+    if args.headline_only:
+        args.no_cpu = args.no_fp32 = args.no_batched = args.no_secondary = True
+        args.no_uq = args.no_configs = True
 
-    import numpy as np
-    from workloads import batched_sweep, workload
+    from workloads import workload
 
     if args.copy_calibration:
         import torch
@@ -399,12 +500,12 @@ def main():
         log("copy calibration: 5 copies of 268435456 bytes")
         del src, dst
 
-    cfg = workload(WORKLOAD)
+    cfg = workload(WORKLOAD, precision="fp64")
     log(f"{WORKLOAD}: FP64, {args.warmup} warm-up + {args.steps} timed + {args.steps} profiled steps")
-    r64 = run_gpu(dict(cfg, precision="fp64"), args.steps, args.warmup, tune=not args.no_tune)
+    r64 = run_gpu(cfg, args.steps, args.warmup, tune=not args.no_tune)
     P, Q, N = r64["sim"].P, r64["sim"].Q, cfg["n_particles"]
     pn = N * Q * args.steps
-    roof, per = roofline_of(dict(cfg, precision="fp64"), r64, P, Q)
+    roof, per, step = roofline_of(cfg, r64, P, Q)
     log(f"FP64 {r64['wall'] * 1e3 / args.steps:.4f} ms/step; kernels " +
         ", ".join(f"{k} {v['avg_ms'] * 1e3:.1f} us" for k, v in per.items()))
 
@@ -427,51 +528,41 @@ def main():
                    "launch": "hip graphs of 16 steps", "chunk": r64["shape"]["chunk"],
                    "collider_workgroups": r64["shape"]["collider_workgroups"]},
         "roofline": roof,
+        "roofline_step": step,
         "kernels": per,
         "device_ms_per_step": r64["dev_ms"],
         "candidates_per_step": r64["cand"][0],
     }
-    del r64["sim"]
+    m64 = r64["moments"]
+    del r64
+    import torch
+    torch.cuda.empty_cache()
 
     if not args.no_fp32:
         log("FP32 run of the same steps")
         r32 = run_gpu(dict(cfg, precision="fp32"), args.steps, args.warmup)
-        m64, m32 = r64["moments"], r32["moments"]
-        dev = {}
-        for obs in ("E_vx", "Var_vx", "E_jx", "Var_jx", "E_energy"):
-            se = np.maximum(m64["SE_" + obs][1:], 1e-300)
-            dev[obs] = float(np.max(np.abs(m64[obs][1:] - m32[obs][1:]) / se))
-        _, per32 = roofline_of(dict(cfg, precision="fp32"), r32, P, Q)
+        dev = max_dev_over_se(m64, r32["moments"])
+        _, per32, step32 = roofline_of(dict(cfg, precision="fp32"), r32, P, Q)
         out["fp32"] = {
             "value": pn / r32["wall"], "ms_per_step": r32["wall"] * 1e3 / args.steps,
-            "kernels": per32,
-            "speedup_vs_fp64": r64["wall"] / r32["wall"],
+            "kernels": per32, "roofline_step": step32,
+            "speedup_vs_fp64": out["ms_per_step"] / (r32["wall"] * 1e3 / args.steps),
             "max_abs_dev_over_mc_se": dev,
             "matched_error": all(v < 3.0 for v in dev.values()),
         }
         del r32
+        torch.cuda.empty_cache()
+
+    if not args.no_secondary:
+        out["secondary"] = secondary_line(args.steps, args.warmup)
+        torch.cuda.empty_cache()
 
     if not args.no_batched:
-        cfgs = batched_sweep()
-        nb = args.batched_steps
-        log(f"batched sweep: {len(cfgs)} instances, FP32, {sum(c['n_particles'] for c in cfgs)} "
-            f"particles, 10 warm-up + {nb} timed steps")
-        rb = run_gpu(cfgs, nb, 10)
-        pn_b = sum(c["n_particles"] * (c["degree"] + 3) for c in cfgs) * nb
-        out["batched"] = {
-            "workload": "batched_sweep_64 (E 1-50 kV/cm, gap 0.1-0.5 eV +-10 %, M in {2,4,6}, "
-                        "Q = M + 3, N log-uniform 1e5-2e6)",
-            "instances": len(cfgs), "n_particles": sum(c["n_particles"] for c in cfgs),
-            "value": pn_b / rb["wall"], "unit": "particle-node updates/s",
-            "ms_per_step": rb["wall"] * 1e3 / nb, "steps": nb, "dtype": "f32",
-            "launch_shape_inst0": rb["shape"],
-            "candidates_per_step": sum(rb["cand"]),
-            "kernels": {k: {"avg_ms": ms, "launches": n} for k, (ms, n) in rb["kernels"].items()},
-        }
-        del rb
+        out["batched"] = sweep_forms(args.batched_steps)
+        torch.cuda.empty_cache()
 
     if not args.no_uq:
-        out["uq"] = uq_timings(cfg)
+        out["uq"] = uq_timings(workload(SECONDARY))
 
     if not args.no_configs:
         out["other_configs"] = other_configs()

@@ -219,6 +219,16 @@ sgpm_status sgpm_reconstruct_f(sgpm_ctx* ctx, int32_t inst, int32_t nbins, doubl
 sgpm_status sgpm_moments_at(sgpm_ctx* ctx, int32_t inst, int32_t n_z, const double* z,
                             double* out);
 
+/* The uncertain inputs of instance inst at points z (Sec. 4: the band of
+ * width W(z) and the field E(z) of the problem statement): z is
+ * [n_z][dim_z] (ignored for dim_z = 0); out is [n_z][4]: band gap 2 eps0(z)
+ * (eV), band minimum eps0(z) = hbar v_F pi / W(z) (eV), width W(z) (m) and
+ * field E_x(z) (V/m).  A gap that is not positive gives zeros in the first
+ * three.  Host only, no device work.  For deterministic runs at sampled z
+ * (Monte Carlo sampling of the uncertain inputs). */
+sgpm_status sgpm_inputs_at(const sgpm_ctx* ctx, int32_t inst, int32_t n_z, const double* z,
+                           double* out);
+
 /* Energy distribution of the particles reconstructed at arbitrary points z
  * (k_i(z) = sum_h k_h Psi_h(z)); z[n_z][dim_z], out[n_z][nbins].  Positive
  * by construction.  Synchronises. */
@@ -276,12 +286,15 @@ sgpm_status sgpm_set_chunk(sgpm_ctx* ctx, int32_t inst, int32_t chunk);
  * workgroups.  A grid other than 1024 must be more than 3 % faster, and so
  * must chunks other than the automatic ones (the two margins multiply).
  * Between trials and at the end it puts back the particle state, the step
- * counter and the counters; the histogram is rebuilt and the moment record
- * restarts at the current time, as after sgpm_set_state.
+ * counter and the counters, and rebuilds the histogram.
  * Keeps the fastest shape (results do not depend on it; see sgpm_set_chunk)
  * and returns its device time per step in *best_ms_per_step (may be NULL).
  * Needs trial_steps <= max_steps of every instance (1 <= trial_steps <=
- * 1000).  Synchronises the stream; host copies of the state are made. */
+ * 1000).  The maximum occupation number (sgpm_occupancy_excess) is kept.
+ * The moment record continues when every record has room for the trials
+ * after the current time and the chunks are unchanged; otherwise it restarts
+ * at the current time.  Synchronises the stream; host copies of the state
+ * are made. */
 sgpm_status sgpm_autotune(sgpm_ctx* ctx, double dt_s, int32_t trial_steps,
                           double* best_ms_per_step);
 

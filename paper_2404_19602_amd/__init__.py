@@ -235,6 +235,18 @@ class Simulation:
                                     out.ctypes.data_as(C.c_void_p)), self._ctx, "moments_at")
         return {"V_x": out[:, 0], "V_y": out[:, 1], "energy": out[:, 2], "J_x": out[:, 3]}
 
+    def inputs_at(self, z, inst: int = 0) -> dict:
+        """The uncertain inputs at points z: band gap and band minimum (eV),
+        ribbon width (m) and field (V/m)."""
+        dz = int(self.cfgs[inst].get("dim_z", 0))
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.float64).reshape(-1, max(dz, 1)))
+        nz = z.shape[0]
+        out = np.zeros((nz, 4))
+        check(lib().sgpm_inputs_at(self._ctx, inst, nz, z.ctypes.data_as(C.c_void_p),
+                                   out.ctypes.data_as(C.c_void_p)), self._ctx, "inputs_at")
+        return {"gap_eV": out[:, 0], "eps0_eV": out[:, 1], "width_m": out[:, 2],
+                "field": out[:, 3]}
+
     def synchronize(self):
         self.stream.synchronize()
 

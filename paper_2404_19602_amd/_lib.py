@@ -58,6 +58,7 @@ def lib():
             "sgpm_reconstruct_f": (i32, [vp, i32, i32, dbl, dbl, vp, vp]),
             "sgpm_reconstruct_f_at": (i32, [vp, i32, i32, vp, i32, dbl, dbl, vp]),
             "sgpm_moments_at": (i32, [vp, i32, i32, vp, vp]),
+            "sgpm_inputs_at": (i32, [vp, i32, i32, vp, vp]),
             "sgpm_occupancy_excess": (i32, [vp, i32, i64, i64, vp]),
             "sgpm_set_state": (i32, [vp, i32, vp, i64]),
             "sgpm_get_state": (i32, [vp, i32, vp]),

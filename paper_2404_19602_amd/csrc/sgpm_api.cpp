@@ -598,19 +598,23 @@ void set_chunk(Instance& I, int64_t chunk) {
                &I.hwin_words);
 }
 
-// histogram, its maximum and record index 0 for the current state
-sgpm_status rebuild(sgpm_ctx* c, Instance& I) {
+// Histogram and its maximum for the current state.  restart: the moment
+// record restarts here (record index 0) and the maximum occupation number is
+// taken from this state; otherwise both continue and the current time's
+// record slot is rewritten from the same state.
+sgpm_status rebuild(sgpm_ctx* c, Instance& I, bool restart = true) {
     HIPCHK(c, hipMemsetAsync(I.H, 0, (size_t)3 * I.hstride * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(I.extra, 0, (size_t)I.hstride * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(I.Hmax, 0, (size_t)3 * I.hmstride * 4, c->stream));
     HIPCHK(c, hipMemsetAsync(I.qc, 0, 64, c->stream));
     HIPCHK(c, hipMemsetAsync(I.counters, 0, SGPM_N_COUNTERS * 8, c->stream));
-    I.rec_base = I.step;
+    if (restart) I.rec_base = I.step;
     int e = launch_set_dyn(c->dyn + I.pos, 1, 1, (uint32_t)I.step, (uint32_t)I.rec_base, 0, 0.0,
                            c->stream);
     if (e) return dev_fail(c, (hipError_t)e, "step state launch");
     sgpm_status st = state_pass_one(c, I);
     if (st) return st;
+    if (!restart) return SGPM_OK;
     // maximum occupation number: the largest cell count of this state, per node
     HIPCHK(c, hipMemcpyAsync(I.cap, I.Hmax + (size_t)(I.step % 3) * I.hmstride, (size_t)I.Q * 4,
                              hipMemcpyDeviceToDevice, c->stream));
@@ -618,10 +622,12 @@ sgpm_status rebuild(sgpm_ctx* c, Instance& I) {
     return SGPM_OK;
 }
 
-// Raw copy of an instance's state, step and counters (autotuner trials).
+// Raw copy of an instance's state, step, counters and launch shape
+// (autotuner trials).
 struct Saved {
     std::vector<unsigned char> state;
     int64_t step = 0;
+    int64_t chunk = 0;
     unsigned long long counters[SGPM_N_COUNTERS];
 };
 
@@ -634,17 +640,25 @@ sgpm_status save_instance(sgpm_ctx* c, Instance& I, Saved& S) {
                              c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     S.step = I.step;
+    S.chunk = I.chunk;
     return SGPM_OK;
 }
 
-// the saved state back in place, its histogram and time rebuilt (the record
-// restarts there, as after sgpm_set_state), the counters as they were
-sgpm_status restore_instance(sgpm_ctx* c, Instance& I, const Saved& S) {
+// The saved state back in place and its histogram rebuilt, the counters as
+// they were.  The maximum occupation number is kept.  The moment record
+// continues (a trial writes the slots after the current time, which the run
+// overwrites) unless restart is set, when it restarts at the current time.
+sgpm_status restore_instance(sgpm_ctx* c, Instance& I, const Saved& S, bool restart) {
     const size_t b = S.state.size() / 2;
     HIPCHK(c, hipMemcpyAsync(I.kx, S.state.data(), b, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(I.ky, S.state.data() + b, b, hipMemcpyHostToDevice, c->stream));
     I.step = S.step;
-    sgpm_status st = rebuild(c, I);
+    if (restart) {
+        // the record restarts: its slot 0 holds this time, no excess yet
+        I.rec_base = I.step;
+        HIPCHK(c, hipMemsetAsync(I.excess, 0, (size_t)I.Q * 4, c->stream));
+    }
+    sgpm_status st = rebuild(c, I, false);
     if (st) return st;
     HIPCHK(c, hipMemcpyAsync(I.counters, S.counters, sizeof(S.counters), hipMemcpyHostToDevice,
                              c->stream));
@@ -983,6 +997,11 @@ sgpm_status sgpm_autotune(sgpm_ctx* c, double dt, int32_t trial_steps, double* b
         if (I.step + trial_steps >= (int64_t)0xFFFFFFFFll)
             return fail(c, SGPM_EINVAL, "step counter would reach the initialisation stream");
     }
+    // the trials write the record slots after the current time when every
+    // record has room for them; otherwise the record restarts now
+    bool room = true;
+    for (Instance& I : c->inst)
+        room = room && I.step - I.rec_base + trial_steps <= I.d.max_steps;
     std::vector<Saved> saved(c->inst.size());
     for (size_t k = 0; k < c->inst.size(); ++k) {
         sgpm_status s = save_instance(c, c->inst[k], saved[k]);
@@ -1010,7 +1029,7 @@ sgpm_status sgpm_autotune(sgpm_ctx* c, double dt, int32_t trial_steps, double* b
             c->k2_grid = g;
             st = upload_args(c);
             for (size_t k = 0; k < c->inst.size() && !st; ++k)
-                st = restore_instance(c, c->inst[k], saved[k]);
+                st = restore_instance(c, c->inst[k], saved[k], !room);
             if (!st) st = sgpm_step(c, dt, trial_steps);
             double ms = 0.0;
             if (!st) st = sgpm_last_step_ms(c, &ms);
@@ -1030,7 +1049,12 @@ sgpm_status sgpm_autotune(sgpm_ctx* c, double dt, int32_t trial_steps, double* b
     for (Instance& I : c->inst) set_chunk(I, scaled_chunk(I, best_f));
     c->k2_grid = best_g;
     st = upload_args(c);
-    for (size_t k = 0; k < c->inst.size() && !st; ++k) st = restore_instance(c, c->inst[k], saved[k]);
+    // the record continues if no chunk changed (its batches are the chunk's
+    // workgroups), else it restarts at the current time
+    bool same = room;
+    for (size_t k = 0; k < c->inst.size(); ++k) same = same && c->inst[k].chunk == saved[k].chunk;
+    for (size_t k = 0; k < c->inst.size() && !st; ++k)
+        st = restore_instance(c, c->inst[k], saved[k], !same);
     if (st) return st;
     if (best_ms) *best_ms = best;
     return SGPM_OK;
@@ -1159,7 +1183,7 @@ sgpm_status sgpm_moments(sgpm_ctx* c, int32_t inst, int64_t first, int64_t count
         return fail(c, SGPM_EINVAL, "requested times outside the record");
     if (count == 0) return SGPM_OK;
     const int Q = I.Q, NB = I.nb;
-    const size_t per = (size_t)NB * Q * 3;
+    const size_t per = (size_t)kNumBatches * Q * 3;   // record slot of one time
     std::vector<double> rec;
     try { rec.resize(per * count); } catch (...) { return SGPM_ENOMEM; }
     HIPCHK(c, hipMemcpyAsync(rec.data(), I.record + per * first, per * count * 8,
@@ -1200,8 +1224,9 @@ sgpm_status sgpm_moments(sgpm_ctx* c, int32_t inst, int64_t first, int64_t count
         g[SGPM_AGG_E_VX] = ez(vx.data()); g[SGPM_AGG_VAR_VX] = varz(vx.data(), g[SGPM_AGG_E_VX]);
         g[SGPM_AGG_E_JX] = ez(jx.data()); g[SGPM_AGG_VAR_JX] = varz(jx.data(), g[SGPM_AGG_E_JX]);
         g[SGPM_AGG_E_EN] = ez(en.data()); g[SGPM_AGG_VAR_EN] = varz(en.data(), g[SGPM_AGG_E_EN]);
-        // batch means: the same aggregates from each batch's particles
-        double acc[6] = {0, 0, 0, 0, 0, 0}, acc2[6] = {0, 0, 0, 0, 0, 0};
+        // batch means: the same aggregates from each batch's particles; the
+        // standard error of their mean from the two-pass sample variance
+        double bv[kNumBatches][6];
         int used = 0;
         std::vector<double> bx(Q), bj(Q), be(Q);
         for (int b = 0; b < NB; ++b) {
@@ -1211,19 +1236,20 @@ sgpm_status sgpm_moments(sgpm_ctx* c, int32_t inst, int64_t first, int64_t count
                 be[q] = r[((size_t)b * Q + q) * 3 + 2] / bn[b];
                 bj[q] = -kECharge * dens[q] * bx[q];
             }
-            double v[6];
+            double* v = bv[used++];
             v[0] = ez(bx.data()); v[1] = varz(bx.data(), v[0]);
             v[2] = ez(bj.data()); v[3] = varz(bj.data(), v[2]);
             v[4] = ez(be.data()); v[5] = varz(be.data(), v[4]);
-            for (int k = 0; k < 6; ++k) { acc[k] += v[k]; acc2[k] += v[k] * v[k]; }
-            ++used;
         }
         for (int k = 0; k < 6; ++k) {
             double se = 0.0;
             if (used > 1) {
-                const double m = acc[k] / used;
-                const double var = std::fmax(acc2[k] / used - m * m, 0.0) * used / (used - 1.0);
-                se = std::sqrt(var / used);
+                double m = 0.0;
+                for (int b = 0; b < used; ++b) m += bv[b][k];
+                m /= used;
+                double ss = 0.0;
+                for (int b = 0; b < used; ++b) ss += (bv[b][k] - m) * (bv[b][k] - m);
+                se = std::sqrt(ss / (used - 1.0) / used);
             }
             g[SGPM_AGG_SE_E_VX + k] = se;
         }
@@ -1367,6 +1393,33 @@ static double eps0_at(const Instance& I, const double* zz) {
     const double g = I.d.gap0 * (1.0 + I.d.gap_rel * zg);
     if (!(g > 0)) return 0.0;
     return I.d.gap_mode == 0 ? 0.5 * g : 3.14159265358979323846 * hvf_eVm / (g * 1e-9);
+}
+
+sgpm_status sgpm_inputs_at(const sgpm_ctx* c, int32_t inst, int32_t n_z, const double* z,
+                           double* out) {
+    if (!c || inst < 0 || inst >= (int32_t)c->inst.size()) return SGPM_EINVAL;
+    const Instance& I = c->inst[inst];
+    const int dz = I.t.dim_z;
+    if (n_z < 0 || (n_z > 0 && (!out || (dz > 0 && !z)))) return SGPM_EINVAL;
+    const double hvf_eVm = 6.62607015e-34 / (2 * 3.14159265358979323846) * I.t.v_f / kECharge;
+    for (int k = 0; k < n_z; ++k) {
+        double zz[2] = {0.0, 0.0};
+        for (int d = 0; d < dz; ++d) {
+            zz[d] = z[(size_t)k * dz + d];
+            if (!std::isfinite(zz[d])) return SGPM_EINVAL;
+        }
+        const double e0 = eps0_at(I, zz);
+        const double zf = I.d.field_dim >= 0 ? zz[I.d.field_dim] : 0.0;
+        double* o = out + (size_t)k * 4;
+        o[0] = 2.0 * e0;
+        o[1] = e0;
+        const double zg = I.d.gap_dim >= 0 ? zz[I.d.gap_dim] : 0.0;
+        const double g = I.d.gap0 * (1.0 + I.d.gap_rel * zg);
+        o[2] = !(e0 > 0) ? 0.0
+               : (I.d.gap_mode == 1 ? g * 1e-9 : 3.14159265358979323846 * hvf_eVm / e0);
+        o[3] = I.d.field0 * (1.0 + I.d.field_rel * zf);
+    }
+    return SGPM_OK;
 }
 
 sgpm_status sgpm_moments_at(sgpm_ctx* c, int32_t inst, int32_t n_z, const double* z, double* out) {

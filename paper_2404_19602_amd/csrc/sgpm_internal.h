@@ -193,7 +193,7 @@ struct K3Args {
     int nwg, nb;            // stream workgroups and moment batches
     int fold;               // window blocks of kK3Words words per workgroup
     const double* partial;  // [nwg][Q][3]
-    double* record;         // [max_steps + 1][nb][Q][3]
+    double* record;         // [max_steps + 1][kNumBatches][Q][3], batches b < nb used
     Dyn* dyn;
     const uint32_t* cap;    // [Q] maximum occupation number per node
     uint32_t* excess;       // [max_steps + 1][Q] particles above it, per time

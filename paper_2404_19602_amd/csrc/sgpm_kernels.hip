@@ -1121,7 +1121,9 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
     if (moving && wg == 0 && threadIdx.x == 0) a.dyn->step_k1 = step + 1u;
     const int nwg = a.nwg, nb = a.nb;
     const double* partial = a.partial;
-    double* record = a.record + (size_t)(step - a.dyn->rec_base) * nb * a.Q * 3;
+    // one record slot per time, kNumBatches batches wide whatever the launch
+    // shape, so a change of shape never moves the slots of other times
+    double* record = a.record + (size_t)(step - a.dyn->rec_base) * kNumBatches * a.Q * 3;
     uint32_t* h_out = a.H + (size_t)(step % 3u) * a.hstride;
     uint32_t* hmax_out = a.Hmax + (size_t)(step % 3u) * a.hmstride;
     const int tid = threadIdx.x;

@@ -29,16 +29,23 @@ def sample_z(n: int, dim_z: int, seed: int) -> np.ndarray:
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=(n, dim_z))
 
 
-def deterministic_at(cfg: dict, z) -> dict:
-    """The deterministic problem of an uncertain workload at one point z: the
-    band gap (or width) and field take their values at z."""
-    z = np.atleast_1d(np.asarray(z, dtype=np.float64))
-    out = dict(cfg)
-    zg = z[cfg["gap_dim"]] if cfg.get("gap_dim", -1) >= 0 else 0.0
-    zf = z[cfg["field_dim"]] if cfg.get("field_dim", -1) >= 0 else 0.0
-    out.update(_DET)
-    out["gap0"] = cfg["gap0"] * (1.0 + cfg.get("gap_rel", 0.0) * zg)
-    out["field0"] = cfg["field0"] * (1.0 + cfg.get("field_rel", 0.0) * zf)
+def deterministic_at(cfg: dict, z) -> list:
+    """The deterministic problems of an uncertain workload at points z
+    ([n][dim_z]): the band gap (or width) and the field take the values the
+    library evaluates at each z (``sgpm_inputs_at``)."""
+    probe = Simulation(dict(cfg, n_particles=1), max_steps=0)
+    vals = probe.inputs_at(z)
+    del probe
+    out = []
+    for k in range(len(vals["field"])):
+        c = dict(cfg)
+        c.update(_DET)
+        if int(cfg.get("gap_mode", 0)) == 1:
+            c["gap0"] = float(vals["width_m"][k] * 1e9)
+        else:
+            c["gap0"] = float(vals["gap_eV"][k])
+        c["field0"] = float(vals["field"][k])
+        out.append(c)
     return out
 
 
@@ -50,13 +57,11 @@ def mc_sampling(cfg: dict, n_samples: int, steps: int, seed: int = 7,
     random streams)."""
     dt = cfg.get("dt", 2e-15) if dt is None else dt
     z = sample_z(n_samples, int(cfg.get("dim_z", 0)), seed)
-    cfgs = []
-    for k in range(n_samples):
-        c = deterministic_at(cfg, z[k])
+    cfgs = deterministic_at(cfg, z)
+    for k, c in enumerate(cfgs):
         c["instance"] = k
         if n_particles is not None:
             c["n_particles"] = int(n_particles)
-        cfgs.append(c)
     sim = Simulation(cfgs, max_steps=steps)
     sim.init_particles()
     sim.step(steps, dt)

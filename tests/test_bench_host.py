@@ -1,7 +1,7 @@
 """Host logic of bench.py (no GPU): the one-GPU contract, the algorithmic
-byte model of each step kernel, the choice of the dominant kernel for the
-roofline, and the rule that measured traffic is reported only for the kernel
-sources it was taken on."""
+byte model of each step kernel, the rooflines of the dominant kernel and of
+the whole step, and the rule that measured traffic is reported only for the
+kernel sources it was taken on."""
 import json
 import os
 import subprocess
@@ -17,7 +17,7 @@ import bench  # noqa: E402
 
 def headline():
     from workloads import workload
-    return workload("sg_gap_m5_q8_n1e6")
+    return workload("sg_gap_m8_q12_n3e7", precision="fp64")
 
 
 def test_more_than_one_gpu_is_refused():
@@ -30,8 +30,9 @@ def test_more_than_one_gpu_is_refused():
 
 def test_kernel_bytes_of_the_headline_workload():
     cfg = headline()
-    N, P, Q, nk = cfg["n_particles"], 6, 8, cfg.get("nk", 240)
-    cand = 15_696
+    N, P, Q, nk = cfg["n_particles"], 9, 12, cfg["nk"]
+    assert (N, nk) == (30_000_000, 256)
+    cand = 350_000
     b = bench.kernel_bytes(cfg, P, Q, n_drift=1, cand=cand)
     # every coefficient read once; the drifted mode written for the non-candidates
     assert b["stream"] == 2 * P * 8 * N + (N - cand) * 1 * 8
@@ -43,41 +44,58 @@ def test_kernel_bytes_of_the_headline_workload():
     assert b32["stream"] * 2 == b["stream"] and b32["collide"] * 2 == b["collide"]
 
 
-def test_roofline_is_the_dominant_kernel():
+def _run(kernels, wall=2.0, steps=1000):
+    return {"n_drift": 1, "cand": (350_000.0,), "kernels": kernels, "wall": wall, "steps": steps}
+
+
+def test_roofline_is_the_longest_kernel():
     cfg = headline()
-    r = {"n_drift": 1, "cand": (15_696.0,),
-         "kernels": {"stream": (0.050, 200), "finalize": (0.012, 200), "collide": (0.045, 200)}}
-    roof, per = bench.roofline_of(cfg, r, 6, 8)
+    r = _run({"stream": (1.50, 1000), "finalize": (0.05, 1000), "collide": (1.00, 1000)})
+    roof, per, step = bench.roofline_of(cfg, r, 9, 12)
     assert roof["kernel"] == "sgpm::k1_stream"
     assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
-    want = per["stream"]["bytes_per_launch"] / 50e-6 / 1e9
+    want = per["stream"]["bytes_per_launch"] / 1.5e-3 / 1e9
     assert roof["achieved"] == pytest.approx(want)
     assert roof["frac"] == pytest.approx(want / 8000.0)
-    r["kernels"]["collide"] = (0.060, 200)
-    roof, _ = bench.roofline_of(cfg, r, 6, 8)
+    # no margin in favour of any kernel: a collider 1 % longer takes the roofline
+    r["kernels"]["collide"] = (1.515, 1000)
+    roof, _, _ = bench.roofline_of(cfg, r, 9, 12)
     assert roof["kernel"] == "sgpm::k2_collide"
-    assert "close" not in roof            # the stream kernel is 17 % shorter
 
 
-def test_roofline_keeps_the_stream_kernel_within_the_margin():
-    """A collider within 5 % of the stream kernel does not take the roofline; it
-    is listed beside it with its own fraction of peak."""
+def test_roofline_of_the_whole_step():
+    """The step's algorithmic bytes (the three launches) over the wall time
+    per step."""
     cfg = headline()
-    r = {"n_drift": 1, "cand": (15_696.0,),
-         "kernels": {"stream": (0.050, 200), "finalize": (0.012, 200), "collide": (0.052, 200)}}
-    roof, per = bench.roofline_of(cfg, r, 6, 8)
-    assert roof["kernel"] == "sgpm::k1_stream"
-    assert [c["kernel"] for c in roof["close"]] == ["sgpm::k2_collide"]
-    assert roof["close"][0]["frac"] == pytest.approx(per["collide"]["GBps"] / 8000.0)
-    r["kernels"]["collide"] = (0.0526, 200)       # more than 5 % longer: it dominates
-    roof, _ = bench.roofline_of(cfg, r, 6, 8)
-    assert roof["kernel"] == "sgpm::k2_collide"
-    assert "close" not in roof                   # 0.050 < 0.0526 / 1.05
+    r = _run({"stream": (1.50, 1000), "finalize": (0.05, 1000), "collide": (1.00, 1000)},
+             wall=2.4, steps=1000)
+    _, per, step = bench.roofline_of(cfg, r, 9, 12)
+    total = sum(v["bytes_per_launch"] for v in per.values())
+    assert step["bytes_per_step"] == total
+    assert step["ms_per_step"] == pytest.approx(2.4)
+    assert step["achieved"] == pytest.approx(total / 2.4e-3 / 1e9)
+    assert step["frac"] == pytest.approx(step["achieved"] / 8000.0)
 
 
-def test_traffic_only_for_the_profiled_sources(monkeypatch):
-    with open(bench.TRAFFIC_FILE) as fh:
-        rec = json.load(fh)
+def test_matched_error_is_per_observable():
+    import numpy as np
+    t = 5
+    ref = {o: np.linspace(1.0, 2.0, t) for o in bench.OBSERVABLES}
+    ref.update({"SE_" + o: np.full(t, 0.1) for o in bench.OBSERVABLES})
+    other = {o: ref[o].copy() for o in bench.OBSERVABLES}
+    other["E_vx"][3] += 0.25          # 2.5 SE at one time
+    other["Var_vx"][0] += 9.0         # time 0 (the shared initial datum) is not compared
+    dev = bench.max_dev_over_se(ref, other)
+    assert dev["E_vx"] == pytest.approx(2.5) and dev["Var_vx"] == 0.0
+
+
+def test_traffic_only_for_the_profiled_sources(monkeypatch, tmp_path):
+    rec = {"source_sha256": "the profiled sources", "calibration": {"fetch_factor": 2.0,
+                                                                      "write_factor": 1.0},
+           "kernels": {"stream": {"fetch_bytes": 4.3e9, "write_bytes": 0.4e9}}}
+    path = tmp_path / "t.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "not the profiled sources")
     assert bench.measured_traffic("stream") is None
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: rec["source_sha256"])
@@ -98,12 +116,12 @@ def test_pmc_summary_scales_by_the_copy(tmp_path):
     head = "Kernel_Name,Counter_Name,Counter_Value\n"
     copy_kib = 268435456 / 1024
     fetch = [("__amd_rocclr_copyBuffer", copy_kib / 2)] * 5 + [
-        ("void sgpm::k1_stream<double, 6, 8>(x)", v) for v in (1000.0, 1100.0, 900.0)] + [
-        ("sgpm::k3_finalize(x)", 50.0), ("void sgpm::k2_collide<double, 6, 1>(x)", 20.0),
-        ("void sgpm::k1_stream<float, 6, 8>(x)", 1e9)]   # another instantiation: ignored
+        ("void sgpm::k1_stream<double, 9, 12>(x)", v) for v in (1000.0, 1100.0, 900.0)] + [
+        ("sgpm::k3_finalize(x)", 50.0), ("void sgpm::k2_collide_wide<double, 9, 1>(x)", 20.0),
+        ("void sgpm::k1_stream<float, 9, 12>(x)", 1e9)]   # another precision: ignored
     write = [("__amd_rocclr_copyBuffer", copy_kib)] * 5 + [
-        ("void sgpm::k1_stream<double, 6, 8>(x)", 300.0), ("sgpm::k3_finalize(x)", 4.0),
-        ("void sgpm::k2_collide<double, 6, 1>(x)", 6.0)]
+        ("void sgpm::k1_stream<double, 9, 12>(x)", 300.0), ("sgpm::k3_finalize(x)", 4.0),
+        ("void sgpm::k2_collide_wide<double, 9, 1>(x)", 6.0)]
     fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
     fp.write_text(head + "".join(f'"{k}",FETCH_SIZE,{v}\n' for k, v in fetch))
     wp.write_text(head + "".join(f'"{k}",WRITE_SIZE,{v}\n' for k, v in write))
@@ -125,8 +143,8 @@ def test_pmc_summary_keeps_the_timed_passes(tmp_path):
     passes (no collider) are left out, and the stream workgroups are recorded."""
     head = ("Dispatch_Id,Grid_Size,Workgroup_Size,Kernel_Name,Counter_Name,Counter_Value\n")
     copy_kib = 268435456 / 1024
-    k1, k3, k2 = ("void sgpm::k1_stream<double, 6, 8>(x)", "sgpm::k3_finalize(x)",
-                  "void sgpm::k2_collide<double, 6, 1>(x)")
+    k1, k3, k2 = ("void sgpm::k1_stream<double, 9, 12>(x)", "sgpm::k3_finalize(x)",
+                  "void sgpm::k2_collide_wide<double, 9, 1>(x)")
 
     def runs(counter, copy_val):
         rows, d = [], 0

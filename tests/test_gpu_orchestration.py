@@ -190,3 +190,13 @@ def test_autotune_keeps_the_run(sg, batched):
                 assert a[k] == b[k], (j, k)
             else:
                 assert np.array_equal(a[k], b[k]), (j, k)
+        # the maximum occupation number of the initial datum is kept, and the
+        # record continues through the tuning unless the chunk changed
+        ea, eb = tuned.occupancy_excess(inst=j), plain.occupancy_excess(inst=j)
+        assert np.array_equal(ea[-12:], eb[-12:]), j
+        if tuned.launch_shape(j)["chunk"] == plain.launch_shape(j)["chunk"]:
+            assert tuned.record_length(j) == plain.record_length(j) == 18
+            ma, mb = tuned.moments(inst=j), plain.moments(inst=j)
+            for k in ("E_vx", "E_energy", "SE_E_vx"):
+                assert np.array_equal(ma[k], mb[k]), (j, k)
+            assert np.array_equal(ea, eb), j

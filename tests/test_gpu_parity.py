@@ -89,6 +89,9 @@ INIT_CASES = {
                        field_dim=1, field0=1.5e6, field_rel=0.2, n_particles=3_000),
     "width": small_cfg(dim_z=1, degree=3, nodes_1d=5, gap_mode=1, gap0=7.0, gap_rel=1 / 14,
                        gap_dim=0, n_particles=4_097),
+    # a Fermi-Dirac datum hotter than the lattice
+    "hot_start": small_cfg(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1,
+                           n_particles=6_000, init_temp_K=900.0),
 }
 
 
@@ -139,6 +142,10 @@ STEP_CASES = {
                                     pauli=0, final_state=1, field0=5e6, n_particles=5_000), 80,
                           None),
     "single_particle": (small_cfg(n_particles=1, rate_scale=(30.0,) * 6), 200, None),
+    # hot start at zero field relaxing toward the lattice temperature
+    "hot_start_relaxation": (small_cfg(dim_z=1, degree=3, nodes_1d=4, gap_dim=0, gap_rel=0.2,
+                                       field0=0.0, init_temp_K=900.0, n_particles=8_000), 150,
+                             None),
     "field_uncertain_m8": (small_cfg(dim_z=1, degree=8, nodes_1d=12, field_dim=0, field0=4e6,
                                      field_rel=0.5, gap_dim=0, gap0=0.25, gap_rel=0.2,
                                      nk=256, n_particles=6_000), 60, None),
