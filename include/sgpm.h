@@ -319,6 +319,25 @@ const char* sgpm_status_string(sgpm_status s);
 sgpm_status sgpm_philox_device(const uint32_t* d_ctr, const uint32_t* d_key, uint32_t* d_out,
                                int64_t n, void* hip_stream);
 
+/* Allocation-free energy distribution, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same reconstruction as sgpm_reconstruct_f's
+ * nodes output, out[q][b] = fraction of the n particles whose energy at node
+ * q lies in bin b, per eV, but from caller device arrays and without a
+ * context.  kx, ky: device coefficients [P][n] each (double for SGPM_FP64,
+ * float for SGPM_FP32); psi: device [Q][P] basis values Psi_h(z_q); eps0:
+ * device [Q] band minima (eV); out: device [Q][nbins] doubles.  Bins split
+ * [emin, emax) uniformly.  Asynchronous on hip_stream; no hipMalloc, hipFree
+ * or allocating library call.  The bin counts live in a fixed device array
+ * of 2^19 counts (4 MiB) per GPU, held until the process ends: Q * nbins
+ * above 2^19 returns SGPM_EUNSUPPORTED.  Every call on one GPU shares that
+ * array (cleared by the call itself), so calls that overlap on one GPU --
+ * on different streams or host threads -- race. */
+sgpm_status sgpm_energy_density_noalloc(const void* kx, const void* ky, int32_t precision,
+                                        int64_t n, int32_t P, int32_t Q, const double* psi,
+                                        const double* eps0, int32_t nbins, double emin_eV,
+                                        double emax_eV, double* out, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,8 @@ def lib():
             "sgpm_last_error": (C.c_char_p, [vp]),
             "sgpm_status_string": (C.c_char_p, [i32]),
             "sgpm_philox_device": (i32, [vp, vp, vp, i64, vp]),
+            "sgpm_energy_density_noalloc": (i32, [vp, vp, i32, i64, i32, i32, vp, vp, i32, dbl,
+                                                  dbl, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)

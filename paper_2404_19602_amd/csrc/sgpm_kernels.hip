@@ -26,6 +26,8 @@
 // advances the copy of the kernel that runs after it (struct Dyn).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+#include <mutex>
 #include <type_traits>
 #include <stdint.h>
 
@@ -1522,6 +1524,27 @@ int launch_energy_hist(const EnergyHistArgs& a, void* stream) {
     return (int)hipGetLastError();
 }
 
+// ---------------------------------- energy distribution without allocation
+// For callers that cannot allocate device memory: the bin counts live in a
+// file-scope device array (one copy per GPU, held until the process ends)
+// instead of a caller-provided workspace.  Host code never passes the
+// array's name to a kernel: it takes the array's device address per device
+// with hipGetSymbolAddress once and passes that.
+constexpr int kNoAllocCounts = 1 << 19;     // Q * nbins limit: 4 MiB of counts
+static __device__ __align__(256) unsigned long long scratch[kNoAllocCounts];
+
+__global__ void __launch_bounds__(kBlock) fill_u64_kernel(unsigned long long* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+__global__ void __launch_bounds__(kBlock) counts_to_density_kernel(const unsigned long long* c,
+                                                                   double* out, int64_t n,
+                                                                   double scale) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = (double)c[i] / scale;
+}
+
 // ------------------------------------------------- moments at given z
 // Each particle's expansion evaluated at up to kMomZ points z (Sec. 4.2: the
 // particle reconstruction at arbitrary z): sums of v_x, v_y and eps per point
@@ -1609,3 +1632,55 @@ int launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64
 }
 
 }  // namespace sgpm
+
+namespace {
+
+// device address of the scratch array on each device, taken once per device
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_ptr[64] = {};
+
+}  // namespace
+
+extern "C" sgpm_status sgpm_energy_density_noalloc(const void* kx, const void* ky,
+                                                   int32_t precision, int64_t n, int32_t P,
+                                                   int32_t Q, const double* psi,
+                                                   const double* eps0, int32_t nbins,
+                                                   double emin_eV, double emax_eV, double* out,
+                                                   void* hip_stream) {
+    using namespace sgpm;
+    if (!kx || !ky || !psi || !eps0 || !out) return SGPM_EINVAL;
+    if (precision != SGPM_FP64 && precision != SGPM_FP32) return SGPM_EINVAL;
+    if (n < 1 || n > (int64_t)2000000000 || P < 1 || P > kMaxP || Q < 1 || Q > kMaxQ)
+        return SGPM_EINVAL;
+    if (nbins < 1 || !(emax_eV > emin_eV) || !std::isfinite(emin_eV) || !std::isfinite(emax_eV))
+        return SGPM_EINVAL;
+    if ((int64_t)Q * nbins > kNoAllocCounts) return SGPM_EUNSUPPORTED;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return SGPM_EDEVICE;
+    unsigned long long* counts = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            void* p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+                return SGPM_EDEVICE;
+            g_scratch_ptr[dev] = static_cast<unsigned long long*>(p);
+        }
+        counts = g_scratch_ptr[dev];
+    }
+    const hipStream_t st = (hipStream_t)hip_stream;
+    const int64_t m = (int64_t)Q * nbins;
+    const unsigned blocks = (unsigned)((m + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks), dim3(kBlock), 0, st, counts, m);
+    if (hipGetLastError() != hipSuccess) return SGPM_EDEVICE;
+    EnergyHistArgs a;
+    a.kx = kx; a.ky = ky; a.fp32 = precision == SGPM_FP32 ? 1 : 0; a.n = n; a.P = P; a.Q = Q;
+    a.psi = psi; a.eps0 = eps0; a.nbins = nbins; a.emin = emin_eV;
+    a.width = (emax_eV - emin_eV) / nbins;
+    a.bins = counts;
+    if (launch_energy_hist(a, hip_stream) != 0) return SGPM_EDEVICE;
+    hipLaunchKernelGGL(counts_to_density_kernel, dim3(blocks), dim3(kBlock), 0, st, counts, out, m,
+                       (double)n * a.width);
+    if (hipGetLastError() != hipSuccess) return SGPM_EDEVICE;
+    return SGPM_OK;
+}

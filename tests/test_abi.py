@@ -136,3 +136,23 @@ def test_product_never_imports_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.lower().replace("the oracle", ""), f
+
+
+def test_noalloc_validation_without_device_work():
+    """sgpm_energy_density_noalloc refuses bad arguments before touching a
+    device: null pointers, a bad precision, and more bins than its fixed
+    scratch holds (Q * nbins > 2^19)."""
+    L = _lib()
+    lib = L.lib()
+    f = lib.sgpm_energy_density_noalloc
+    one = C.c_void_p(1)
+    args = lambda **kw: dict(dict(kx=one, ky=one, prec=0, n=C.c_int64(10), P=6, Q=8, psi=one,
+                                  eps0=one, nbins=256, emin=C.c_double(0.0),
+                                  emax=C.c_double(2.0), out=one, stream=None), **kw)
+    call = lambda a: f(a["kx"], a["ky"], a["prec"], a["n"], a["P"], a["Q"], a["psi"], a["eps0"],
+                       a["nbins"], a["emin"], a["emax"], a["out"], a["stream"])
+    assert call(args(kx=None)) == 1
+    assert call(args(out=None)) == 1
+    assert call(args(prec=3)) == 1
+    assert call(args(emax=C.c_double(0.0))) == 1
+    assert call(args(Q=128, nbins=4097)) == 6
