@@ -164,6 +164,40 @@ sgpm_status sgpm_init_particles(sgpm_ctx* ctx);
  * (sgpm_set_graph); results do not depend on how they are launched. */
 sgpm_status sgpm_step(sgpm_ctx* ctx, double dt_s, int64_t n_steps);
 
+/* LDS bytes of a stream workgroup of instance inst, which size its histogram
+ * window (the square of cells around the grid centre counted in LDS; counts
+ * outside go through device atomics): 0 = the default (80 KiB for the
+ * generic kernel, 150 KiB or the device's limit for the mirror-pair kernel),
+ * else 16 KiB to 150 KiB (clamped to the default's maximum).  Results do not
+ * depend on it.  Allowed right after init/set_state. */
+sgpm_status sgpm_set_stream_lds(sgpm_ctx* ctx, int32_t inst, int32_t bytes);
+
+/* Histogram window of instance inst: its side in cells and the LDS bytes of a
+ * stream workgroup (either pointer may be NULL). */
+sgpm_status sgpm_window(const sgpm_ctx* ctx, int32_t inst, int32_t* win, int32_t* lds_bytes);
+
+/* Stream kernel of the instances with one uncertain input and 2 to 12 nodes:
+ * on > 0 the mirror-pair kernel, which evaluates the nodes z_q and -z_q of
+ * the symmetric Gauss-Legendre rule together from the even and odd modes;
+ * 0 the generic kernel, one node at a time; on < 0 (the default) the pair
+ * kernel for shape groups (instances launched together) of 2^22 particles
+ * or more, the generic one below.  Results agree to rounding (the node
+ * values are summed in another order).  Resets every instance's chunk to
+ * the automatic one; allowed right after init/set_state (the current time
+ * is re-recorded). */
+sgpm_status sgpm_set_node_pairs(sgpm_ctx* ctx, int32_t on);
+
+/* Collider of the instances with at most 12 nodes: on > 0 a lane per
+ * candidate, which loops over the candidate's nodes; 0 a group of lanes per
+ * candidate, a node per lane (the form used beyond 12 nodes); on < 0 (the
+ * default) the lane form for shape groups of 2^22 particles or more.  The
+ * two compute every quantity by the same expressions in the same order:
+ * results are identical.  Allowed at any time. */
+sgpm_status sgpm_set_collider_lanes(sgpm_ctx* ctx, int32_t on);
+
+/* *paired = 1 if instance inst is stepped by the mirror-pair stream kernel. */
+sgpm_status sgpm_node_pairs(const sgpm_ctx* ctx, int32_t inst, int32_t* paired);
+
 /* Launch mode of sgpm_step: 0 = every kernel launched on the stream; B >= 1
  * = blocks of B steps captured once as a HIP graph (on a private stream) and
  * replayed on the context's stream, remainders from a graph of their own
@@ -270,8 +304,9 @@ sgpm_status sgpm_tables(const sgpm_ctx* ctx, int32_t inst, double* z, double* w,
                         double* density_m2);
 
 /* Launch shape: particles per workgroup chunk (a multiple of 1024, at most
- * 8192, at least a quarter of the automatic choice of about N/256, and large
- * enough for at most 4096 workgroups) of the step kernels of instance inst;
+ * 8192 -- 2^24 with the mirror-pair stream kernel --, at least a quarter of
+ * the automatic choice of about N/256, and large enough for at most 4096
+ * workgroups) of the step kernels of instance inst;
  * 0 restores the automatic
  * choice.  Particle trajectories, histograms and counters do not depend on
  * it; the FP64 moment sums only through their order.  Allowed right after

@@ -97,6 +97,37 @@ class Simulation:
     def set_chunk(self, chunk: int, inst: int = 0):
         check(lib().sgpm_set_chunk(self._ctx, inst, chunk), self._ctx, "set_chunk")
 
+    @staticmethod
+    def _mode(on) -> int:
+        return -1 if on is None else (1 if on else 0)
+
+    def set_node_pairs(self, on):
+        """The mirror-pair stream kernel (True), the generic one (False) or
+        the automatic choice by particle count (None, the default) for the
+        instances with one uncertain input; right after init/set_state."""
+        check(lib().sgpm_set_node_pairs(self._ctx, self._mode(on)), self._ctx, "set_node_pairs")
+
+    def set_collider_lanes(self, on):
+        """A lane per candidate (True), a group of lanes per candidate (False)
+        or the automatic choice by particle count (None, the default) in the
+        collider of the instances with at most 12 nodes."""
+        check(lib().sgpm_set_collider_lanes(self._ctx, self._mode(on)), self._ctx,
+              "set_collider_lanes")
+
+    def set_stream_lds(self, nbytes: int, inst: int = 0):
+        """LDS bytes of a stream workgroup (sizes the histogram window); 0 = default."""
+        check(lib().sgpm_set_stream_lds(self._ctx, inst, int(nbytes)), self._ctx, "set_stream_lds")
+
+    def window(self, inst: int = 0) -> dict:
+        w = C.c_int32(0); b = C.c_int32(0)
+        check(lib().sgpm_window(self._ctx, inst, C.byref(w), C.byref(b)), self._ctx, "window")
+        return {"cells": w.value, "lds_bytes": b.value}
+
+    def node_pairs(self, inst: int = 0) -> bool:
+        v = C.c_int32(0)
+        check(lib().sgpm_node_pairs(self._ctx, inst, C.byref(v)), self._ctx, "node_pairs")
+        return bool(v.value)
+
     def set_graph(self, steps_per_graph: int):
         """0: launch every kernel; B >= 1: replay captured graphs of B steps."""
         check(lib().sgpm_set_graph(self._ctx, steps_per_graph), self._ctx, "set_graph")

@@ -69,6 +69,11 @@ def lib():
             "sgpm_set_chunk": (i32, [vp, i32, i32]),
             "sgpm_last_step_ms": (i32, [vp, C.POINTER(dbl)]),
             "sgpm_set_graph": (i32, [vp, i32]),
+            "sgpm_set_node_pairs": (i32, [vp, i32]),
+            "sgpm_set_collider_lanes": (i32, [vp, i32]),
+            "sgpm_set_stream_lds": (i32, [vp, i32, i32]),
+            "sgpm_window": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32)]),
+            "sgpm_node_pairs": (i32, [vp, i32, C.POINTER(i32)]),
             "sgpm_set_profiling": (i32, [vp, i32]),
             "sgpm_kernel_times": (i32, [vp, vp, vp]),
             "sgpm_autotune": (i32, [vp, dbl, i32, C.POINTER(dbl)]),

@@ -14,6 +14,10 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only inside one source expression, so two
+    # kernels that compute a quantity by the same expressions round it the
+    # same way (the collider variants agree bit for bit)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 

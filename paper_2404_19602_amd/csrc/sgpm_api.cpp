@@ -41,10 +41,14 @@ struct Instance {
     int64_t n = 0;
     int64_t n_all = 0;         // particles of all instances of the context
     bool fp32 = false;
+    bool pair_capable = false; // mirror-symmetric nodes in a bucket of the pair kernel
+    bool paired = false;       // stepped by the mirror-pair stream kernel
     int64_t chunk = kBlock1;
     int nwg = 1, nb = 1;
     int win = 0, win_r0 = 0, win_l0 = 0, hwin_words = 0;
     int lds_budget = kLdsK1Bytes;   // LDS bytes of a stream workgroup (sizes the window)
+    int lds_cap = kLdsPairBudget;   // the device's LDS per workgroup, less a margin
+    int lds_req = 0;                // requested stream LDS bytes (sgpm_set_stream_lds), 0: default
     int64_t hstride = 0;       // words per histogram buffer (padded)
     int64_t hmstride = 0;      // words per maximum buffer
     int64_t step = 0;          // global step counter (random streams)
@@ -85,11 +89,14 @@ struct Instance {
 struct Group {
     bool fp32 = false;
     int pmax = 1, qmax = 1;
+    bool pair_capable = false; // every member has mirror-symmetric nodes
+    bool paired = false;       // launched as the mirror-pair stream kernel
     std::vector<int> members;  // instance indices, in slot order
     int pos0 = 0;              // first slot
     unsigned k1_grid = 0, k3_grid = 0;
     size_t k1_lds = 0, k2_lds = 0;
     int npl = 1;               // collider nodes per lane (2 beyond 64 nodes)
+    bool lanes = false;        // collider with a lane per candidate (every member <= 12 nodes)
 };
 
 // Bytes of every device region of one instance, in carving order.
@@ -134,23 +141,46 @@ int64_t wg_cap_chunk(int64_t n) {
 }
 
 // n: the instance's particles; n_all: all particles of the context.  About
-// one stream workgroup (sixteen or eight waves) per compute unit for the whole context
-// (a batch of small instances fills the device once, not once per instance),
-// whole sub-tiles.
-int64_t auto_chunk(int64_t n, int64_t n_all) {
+// one stream workgroup per compute unit for the whole context (a batch of
+// small instances fills the device once, not once per instance), whole
+// multiples of 1024 particles.  The generic stream kernel keeps its
+// candidates of a chunk in LDS, so its chunk is at most kMaxChunk; the
+// mirror-pair kernel flushes them as they come and takes any chunk.
+int64_t auto_chunk(int64_t n, int64_t n_all, bool paired) {
     int64_t c = (n_all + 255) / 256;
     c = (c + kBlock1 - 1) / kBlock1 * kBlock1;
     if (c < wg_cap_chunk(n)) c = wg_cap_chunk(n);
-    if (c > kMaxChunk) c = kMaxChunk;
+    const int64_t cap = paired ? kMaxPairChunk : kMaxChunk;
+    if (c > cap) c = cap;
     return c;
 }
 
 // smallest chunk a launch shape may use: a quarter of the automatic one
 // (bounds the slab region, one window slab per stream workgroup)
-int64_t min_chunk(int64_t n, int64_t n_all) {
-    int64_t c = auto_chunk(n, n_all) / 4 / kBlock1 * kBlock1;
+int64_t min_chunk(int64_t n, int64_t n_all, bool paired) {
+    int64_t c = auto_chunk(n, n_all, paired) / 4 / kBlock1 * kBlock1;
     if (c < wg_cap_chunk(n)) c = wg_cap_chunk(n);
     return c < kBlock1 ? kBlock1 : c;
+}
+
+// One uncertain input with at least two nodes whose tables have the exact
+// mirror symmetry the pair kernel relies on: z_{Q-1-q} = -z_q and
+// Psi_h(z_{Q-1-q}) = (-1)^h Psi_h(z_q), bit for bit.
+bool mirror_symmetric(const HostTables& t) {
+    if (t.dim_z != 1 || t.Q < 2) return false;
+    for (int q = 0; q < t.Q / 2; ++q) {
+        const int m = t.Q - 1 - q;
+        if (t.z[2 * m] != -t.z[2 * q]) return false;
+        for (int h = 0; h < t.P; ++h) {
+            const double a = t.psi[q * t.P + h], b = t.psi[m * t.P + h];
+            if (b != ((h & 1) ? -a : a)) return false;
+        }
+    }
+    return true;
+}
+
+bool pair_capable(const HostTables& t) {
+    return mirror_symmetric(t) && k1p_buckets(pmax_bucket(t.P), qmax_bucket(t.Q));
 }
 
 // LDS histogram window of the stream kernel: the largest even square of
@@ -162,9 +192,9 @@ int64_t min_chunk(int64_t n, int64_t n_all) {
 // binds only with one or two nodes, where the budget alone would cover much
 // more of the grid than the distribution occupies (every workgroup zeroes and
 // flushes its whole window).
-void window_for(int P, int Q, int nk, double lk_eV, bool fp32, int chunk, int budget, int* win,
-                int* r0, int* l0, int* words) {
-    const size_t fixed = k1_lds_bytes(P, Q, fp32 ? 1 : 0, 0, chunk) + 64;
+void window_for(int P, int Q, int nk, double lk_eV, bool fp32, bool paired, int64_t chunk,
+                int budget, int* win, int* r0, int* l0, int* words) {
+    const size_t fixed = k1_lds_bytes(P, Q, fp32 ? 1 : 0, paired ? 1 : 0, 0, chunk) + 64;
     const double room = fixed < (size_t)budget ? (double)(budget - fixed) : 0.0;
     // node q counts in half (q & 1) of word (q >> 1) w^2 + r w + l: ceil(Q/2) planes of w^2 words
     const int planes = (Q + 1) / 2;
@@ -213,14 +243,21 @@ Layout layout_of(const sgpm_instance_desc& d, const HostTables& t, int64_t n_all
     L.add(64);                                         // 33 (spare)
     L.add(hstride * 4);                                // 34 overflow grid
     {
-        // the smallest chunk has both the most workgroups and the largest window
+        // the smallest chunk has both the most workgroups and the largest window;
+        // room for the generic kernel's slabs and, where the nodes allow it,
+        // for the mirror-pair kernel's
+        const bool f32 = d.precision == SGPM_FP32;
         int w, r0, l0, words;
-        const int64_t mc = min_chunk(d.n_particles, n_all);
-        window_for(t.P, t.Q, d.nk, d.lk_eV, d.precision == SGPM_FP32, (int)mc, kMaxLdsBudget, &w,
-                   &r0, &l0,
-                   &words);
-        const size_t nwg_slab = (size_t)((d.n_particles + mc - 1) / mc);
-        L.add(nwg_slab * (size_t)words * 4);          // 35 slabs
+        int64_t mc = min_chunk(d.n_particles, n_all, false);
+        window_for(t.P, t.Q, d.nk, d.lk_eV, f32, false, mc, kMaxLdsBudget, &w, &r0, &l0, &words);
+        size_t slab_words = (size_t)((d.n_particles + mc - 1) / mc) * (size_t)words;
+        if (pair_capable(t)) {
+            mc = min_chunk(d.n_particles, n_all, true);
+            window_for(t.P, t.Q, d.nk, d.lk_eV, f32, true, mc, kLdsPairBudget, &w, &r0, &l0,
+                       &words);
+            slab_words = std::max(slab_words, (size_t)((d.n_particles + mc - 1) / mc) * words);
+        }
+        L.add(slab_words * 4);                         // 35 slabs
     }
     L.add((size_t)kMomWG * kMomZ * 3 * 8);             // 36 partials of the moments at z
     L.add(Q * 4);                                      // 37 maximum occupation per node
@@ -263,6 +300,11 @@ struct sgpm_ctx {
     int k2_grid = kK2Grid;         // collider workgroups per launch
     std::vector<std::pair<int, hipGraphExec_t>> graphs;
     bool profiling = false;
+    // mirror-pair stream kernel / collider with a lane per candidate where
+    // they apply: 1 always, 0 never, -1 for shape groups of kLargeGroup
+    // particles or more
+    int pairs_mode = -1;
+    int lanes_mode = -1;
     Prof prof;
 };
 
@@ -271,6 +313,27 @@ namespace {
 sgpm_status fail(sgpm_ctx* c, sgpm_status s, const std::string& msg) {
     if (c) c->err = msg;
     return s;
+}
+
+// Shape groups of at least this many particles take the mirror-pair stream
+// kernel and the lane-per-candidate collider in the automatic mode.  Both
+// trade fewer instructions per particle for fewer, larger workgroups: a
+// smaller group (about 2.5e4 collision candidates a step at 1e6 particles)
+// leaves compute units idle and runs faster with the generic forms.
+constexpr int64_t kLargeGroup = (int64_t)1 << 22;
+
+bool large_group(const sgpm_ctx* c, const Group& G) {
+    int64_t n = 0;
+    for (int k : G.members) n += c->inst[k].d.n_particles;
+    return n >= kLargeGroup;
+}
+
+void choose_pairs(sgpm_ctx* c) {
+    for (Group& G : c->groups) {
+        G.paired = G.pair_capable &&
+                   (c->pairs_mode > 0 || (c->pairs_mode < 0 && large_group(c, G)));
+        for (int k : G.members) c->inst[k].paired = G.paired;
+    }
 }
 
 sgpm_status dev_fail(sgpm_ctx* c, hipError_t e, const char* where) {
@@ -382,7 +445,7 @@ K2Args<T> make_k2(const sgpm_ctx* cx, const Instance& I) {
     a.n = I.n; a.P = I.P; a.Q = I.Q;
     int G = 1;
     while (G < I.Q && G < 64) G <<= 1;
-    a.G = G;
+    a.G = cx->groups[I.grp].lanes ? 1 : G;
     a.tab = dev_tab<T>(I);
     a.ehat = I.d_ehat;
     a.dyn = cx->dyn + I.pos;
@@ -429,6 +492,7 @@ K3Args make_k3(const sgpm_ctx* cx, const Instance& I) {
     a.dyn = cx->dyn + I.pos;
     a.cap = I.cap;
     a.excess = I.excess;
+    a.mirror = I.paired ? 1 : 0;
     return a;
 }
 
@@ -460,12 +524,16 @@ sgpm_status upload_args(sgpm_ctx* c) {
         uint32_t *t1 = tab(kTabK1, off), *t3 = tab(kTabK3, off);
         t1[0] = t3[0] = 0u;
         G.k1_lds = 0; G.k2_lds = 0; G.npl = 1;
+        G.lanes = G.qmax >= 1 && G.qmax <= 12 &&
+                  (c->lanes_mode > 0 || (c->lanes_mode < 0 && large_group(c, G)));
         for (size_t m = 0; m < G.members.size(); ++m) {
             Instance& I = c->inst[G.members[m]];
             t1[m + 1] = t1[m] + (uint32_t)I.nwg;
             t3[m + 1] = t3[m] + (uint32_t)k3_grid(I);
-            G.k1_lds = std::max(G.k1_lds, k1_lds_bytes(I.P, I.Q, I.fp32, I.hwin_words, (int)I.chunk));
-            G.k2_lds = std::max(G.k2_lds, k2_lds_bytes(I.P, I.Q, I.fp32));
+            G.k1_lds = std::max(G.k1_lds, k1_lds_bytes(I.P, I.Q, I.fp32, I.paired, I.hwin_words,
+                                                       I.chunk));
+            G.k2_lds = std::max(G.k2_lds, G.lanes ? k2l_lds_bytes(I.P, I.Q, I.fp32)
+                                                  : k2_lds_bytes(I.P, I.Q, I.fp32));
             if (I.Q > 64) G.npl = 2;
             uint32_t* s1 = tab(kTabK1One, 2 * I.pos);
             uint32_t* s3 = tab(kTabK3One, 2 * I.pos);
@@ -523,15 +591,15 @@ sgpm_status enqueue_step(sgpm_ctx* c, hipStream_t s, bool prof) {
     for (size_t g = 0; g < c->groups.size(); ++g) {
         const Group& G = c->groups[g];
         const int m = (int)G.members.size(), off = G.pos0 + (int)g;
-        int e = launch_k1(G.fp32, G.pmax, G.qmax, k1_args(c, G.fp32, G.pos0),
+        int e = launch_k1(G.fp32, G.pmax, G.qmax, G.paired, k1_args(c, G.fp32, G.pos0),
                           wg_table(c, kTabK1, off), m, 1, G.k1_grid, G.k1_lds, s);
         if (e) return dev_fail(c, (hipError_t)e, "stream kernel launch");
         if (prof) { sgpm_status r = prof_mark(c, s, SGPM_KERNEL_STREAM); if (r) return r; }
         e = launch_k3(c->k3 + G.pos0, wg_table(c, kTabK3, off), m, 1, G.k3_grid, s);
         if (e) return dev_fail(c, (hipError_t)e, "finalize kernel launch");
         if (prof) { sgpm_status r = prof_mark(c, s, SGPM_KERNEL_FINALIZE); if (r) return r; }
-        e = launch_k2(G.fp32, G.pmax, G.npl, k2_args(c, G.fp32, G.pos0), m, (unsigned)c->k2_grid,
-                      G.k2_lds, s);
+        e = launch_k2(G.fp32, G.pmax, G.npl, G.lanes, k2_args(c, G.fp32, G.pos0), m,
+                      (unsigned)c->k2_grid, G.k2_lds, s);
         if (e) return dev_fail(c, (hipError_t)e, "collider launch");
         if (prof) { sgpm_status r = prof_mark(c, s, SGPM_KERNEL_COLLIDE); if (r) return r; }
     }
@@ -543,7 +611,7 @@ sgpm_status enqueue_state_pass(sgpm_ctx* c, hipStream_t s) {
     for (size_t g = 0; g < c->groups.size(); ++g) {
         const Group& G = c->groups[g];
         const int m = (int)G.members.size(), off = G.pos0 + (int)g;
-        int e = launch_k1(G.fp32, G.pmax, G.qmax, k1_args(c, G.fp32, G.pos0),
+        int e = launch_k1(G.fp32, G.pmax, G.qmax, G.paired, k1_args(c, G.fp32, G.pos0),
                           wg_table(c, kTabK1, off), m, 0, G.k1_grid, G.k1_lds, s);
         if (!e) e = launch_k3(c->k3 + G.pos0, wg_table(c, kTabK3, off), m, 0, G.k3_grid, s);
         if (e) return dev_fail(c, (hipError_t)e, "state pass launch");
@@ -554,9 +622,10 @@ sgpm_status enqueue_state_pass(sgpm_ctx* c, hipStream_t s) {
 // the same for one instance
 sgpm_status state_pass_one(sgpm_ctx* c, const Instance& I) {
     const Group& G = c->groups[I.grp];
-    int e = launch_k1(I.fp32, G.pmax, G.qmax, k1_args(c, I.fp32, I.pos),
+    int e = launch_k1(I.fp32, G.pmax, G.qmax, G.paired, k1_args(c, I.fp32, I.pos),
                       wg_table(c, kTabK1One, 2 * I.pos), 1, 0, (unsigned)I.nwg,
-                      k1_lds_bytes(I.P, I.Q, I.fp32, I.hwin_words, (int)I.chunk), c->stream);
+                      k1_lds_bytes(I.P, I.Q, I.fp32, I.paired, I.hwin_words, I.chunk),
+                      c->stream);
     if (!e)
         e = launch_k3(c->k3 + I.pos, wg_table(c, kTabK3One, 2 * I.pos), 1, 0,
                       (unsigned)k3_grid(I), c->stream);
@@ -590,12 +659,15 @@ sgpm_status graph_for(sgpm_ctx* c, int steps, hipGraphExec_t* out) {
 // launch shape of the stream kernel: chunk, workgroups, batches and the LDS
 // window that fits beside the chunk's candidate list
 void set_chunk(Instance& I, int64_t chunk) {
-    I.chunk = chunk > 0 ? chunk : auto_chunk(I.n, I.n_all);
+    // the slab region is sized for the largest window of either kernel
+    const int most = I.paired ? std::min(kLdsPairBudget, I.lds_cap) : kMaxLdsBudget;
+    I.lds_budget = I.lds_req > 0 ? std::min(I.lds_req, most)
+                                 : (I.paired ? most : kLdsK1Bytes);
+    I.chunk = chunk > 0 ? chunk : auto_chunk(I.n, I.n_all, I.paired);
     I.nwg = (int)((I.n + I.chunk - 1) / I.chunk);
     I.nb = I.nwg < kNumBatches ? I.nwg : kNumBatches;
-    window_for(I.P, I.Q, I.nk, I.d.lk_eV, I.fp32, (int)I.chunk, I.lds_budget, &I.win, &I.win_r0,
-               &I.win_l0,
-               &I.hwin_words);
+    window_for(I.P, I.Q, I.nk, I.d.lk_eV, I.fp32, I.paired, I.chunk, I.lds_budget, &I.win,
+               &I.win_r0, &I.win_l0, &I.hwin_words);
 }
 
 // Histogram and its maximum for the current state.  restart: the moment
@@ -667,9 +739,9 @@ sgpm_status restore_instance(sgpm_ctx* c, Instance& I, const Saved& S, bool rest
 }
 
 int64_t scaled_chunk(const Instance& I, double f) {
-    int64_t ch = (int64_t)std::llround(auto_chunk(I.n, I.n_all) * f / kBlock1) * kBlock1;
-    ch = std::max<int64_t>(ch, min_chunk(I.n, I.n_all));
-    return std::min<int64_t>(ch, kMaxChunk);
+    int64_t ch = (int64_t)std::llround(auto_chunk(I.n, I.n_all, I.paired) * f / kBlock1) * kBlock1;
+    ch = std::max<int64_t>(ch, min_chunk(I.n, I.n_all, I.paired));
+    return std::min<int64_t>(ch, I.paired ? kMaxPairChunk : kMaxChunk);
 }
 
 }  // namespace
@@ -761,13 +833,16 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         Instance& I = c->inst[k];
         const bool f32 = I.d.precision == SGPM_FP32;
         const int pm = pmax_bucket(I.t.P), qm = qmax_bucket(I.t.Q);
+        I.pair_capable = pair_capable(I.t);
         size_t g = 0;
         while (g < c->groups.size() &&
-               !(c->groups[g].fp32 == f32 && c->groups[g].pmax == pm && c->groups[g].qmax == qm))
+               !(c->groups[g].fp32 == f32 && c->groups[g].pmax == pm && c->groups[g].qmax == qm &&
+                 c->groups[g].pair_capable == I.pair_capable))
             ++g;
         if (g == c->groups.size()) {
             Group G;
             G.fp32 = f32; G.pmax = pm; G.qmax = qm;
+            G.pair_capable = I.pair_capable;
             c->groups.push_back(G);
         }
         c->groups[g].members.push_back(k);
@@ -779,6 +854,15 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
             G.pos0 = pos;
             for (int k : G.members) c->inst[k].pos = pos++;
         }
+    }
+    choose_pairs(c);
+    int lds_cap = kLdsPairBudget;
+    {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) ==
+                hipSuccess && v > 0)
+            lds_cap = std::min(lds_cap, v - 1024);
     }
     unsigned char* base = static_cast<unsigned char*>(ws);
     c->dyn = (Dyn*)(base + CL.dyn);
@@ -820,6 +904,7 @@ sgpm_status sgpm_create(const sgpm_instance_desc* descs, int32_t n_inst, void* w
         I.cap = (uint32_t*)at(37);
         I.excess = (uint32_t*)at(38);
         base += L.total;
+        I.lds_cap = lds_cap;
         set_chunk(I, 0);
         std::memset(&dyn0[I.pos], 0, sizeof(Dyn));
         dyn0[I.pos].v_f = t.v_f;
@@ -930,13 +1015,22 @@ sgpm_status sgpm_tables(const sgpm_ctx* c, int32_t inst, double* z, double* w, d
     return SGPM_OK;
 }
 
+sgpm_status sgpm_window(const sgpm_ctx* c, int32_t inst, int32_t* win, int32_t* lds_bytes) {
+    if (!c || inst < 0 || inst >= (int32_t)c->inst.size()) return SGPM_EINVAL;
+    const Instance& I = c->inst[inst];
+    if (win) *win = I.win;
+    if (lds_bytes) *lds_bytes = I.lds_budget;
+    return SGPM_OK;
+}
+
 sgpm_status sgpm_set_chunk(sgpm_ctx* c, int32_t inst, int32_t chunk) {
     sgpm_status s = check_ctx(c, inst);
     if (s) return s;
-    if (chunk < 0 || chunk % kBlock1 != 0 || chunk > kMaxChunk)
-        return fail(c, SGPM_EINVAL, "chunk must be a multiple of 1024 up to 8192 (0 = automatic)");
     Instance& I = c->inst[inst];
-    if (chunk > 0 && chunk < min_chunk(I.n, I.n_all))
+    if (chunk < 0 || chunk % kBlock1 != 0 || chunk > (I.paired ? kMaxPairChunk : kMaxChunk))
+        return fail(c, SGPM_EINVAL, "chunk must be a multiple of 1024 up to 8192, or up to 2^24 "
+                                    "for the mirror-pair stream kernel (0 = automatic)");
+    if (chunk > 0 && chunk < min_chunk(I.n, I.n_all, I.paired))
         return fail(c, SGPM_EINVAL,
                     "chunk too small: at least a quarter of the automatic chunk and at most "
                     "4096 stream workgroups");
@@ -946,6 +1040,50 @@ sgpm_status sgpm_set_chunk(sgpm_ctx* c, int32_t inst, int32_t chunk) {
     s = upload_args(c);
     if (s) return s;
     if (I.initialised) return rebuild(c, I);
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_set_stream_lds(sgpm_ctx* c, int32_t inst, int32_t bytes) {
+    sgpm_status s = check_ctx(c, inst);
+    if (s) return s;
+    if (bytes != 0 && (bytes < 16 * 1024 || bytes > kLdsPairBudget))
+        return fail(c, SGPM_EINVAL, "stream LDS bytes must be 0 or in [16 KiB, 150 KiB]");
+    Instance& I = c->inst[inst];
+    if (I.initialised && I.step != I.rec_base)
+        return fail(c, SGPM_ESTATE, "the launch shape can only change right after init/set_state");
+    I.lds_req = bytes;
+    set_chunk(I, I.chunk);
+    s = upload_args(c);
+    if (s) return s;
+    if (I.initialised) return rebuild(c, I);
+    return SGPM_OK;
+}
+
+sgpm_status sgpm_set_collider_lanes(sgpm_ctx* c, int32_t on) {
+    if (!c) return SGPM_EINVAL;
+    if (c->poisoned) return fail(c, SGPM_ESTATE, "context poisoned");
+    c->lanes_mode = on < 0 ? -1 : on != 0;
+    return upload_args(c);
+}
+
+sgpm_status sgpm_set_node_pairs(sgpm_ctx* c, int32_t on) {
+    if (!c) return SGPM_EINVAL;
+    if (c->poisoned) return fail(c, SGPM_ESTATE, "context poisoned");
+    for (Instance& I : c->inst)
+        if (I.initialised && I.step != I.rec_base)
+            return fail(c, SGPM_ESTATE, "the stream kernel can only change right after init/set_state");
+    c->pairs_mode = on < 0 ? -1 : on != 0;
+    choose_pairs(c);
+    for (Instance& I : c->inst) set_chunk(I, 0);
+    sgpm_status s = upload_args(c);
+    for (size_t k = 0; k < c->inst.size() && !s; ++k)
+        if (c->inst[k].initialised) s = rebuild(c, c->inst[k]);
+    return s;
+}
+
+sgpm_status sgpm_node_pairs(const sgpm_ctx* c, int32_t inst, int32_t* paired) {
+    if (!c || inst < 0 || inst >= (int32_t)c->inst.size() || !paired) return SGPM_EINVAL;
+    *paired = c->inst[inst].paired ? 1 : 0;
     return SGPM_OK;
 }
 

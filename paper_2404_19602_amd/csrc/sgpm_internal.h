@@ -99,6 +99,16 @@ constexpr int k1_waves(bool fp32, int pmax, int qmax) {
                   : (qmax == 12 ? pmax > 1 : (qmax == 8 ? pmax > 6 : pmax > 16))))
                ? 8 : 16;
 }
+// Threads per workgroup of the stream kernel with mirror node pairs for a
+// precision and bucket (1024, 768 or 512: four, three or two waves per SIMD,
+// one workgroup per compute unit).
+int k1p_block(int fp32, int pmax, int qmax);
+constexpr int kLdsPairBudget = 150 * 1024;   // LDS bytes of a mirror-pair stream workgroup
+constexpr int64_t kMaxPairChunk = (int64_t)1 << 24;   // its largest chunk
+// Mode and node buckets the mirror-pair stream kernel is built for.
+constexpr bool k1p_buckets(int pmax, int qmax) {
+    return (qmax == 8 || qmax == 12) && (pmax == 3 || pmax == 6 || pmax == 9 || pmax == 16);
+}
 constexpr int kMaxStreamWG = 4096;    // cap on stream workgroups of one instance (sizes the slabs)
 constexpr int kMaxChunk = 8192;       // cap on particles per stream workgroup (LDS list)
 constexpr int kK2Grid = 1024;         // persistent collider workgroups of one launch
@@ -197,6 +207,9 @@ struct K3Args {
     Dyn* dyn;
     const uint32_t* cap;    // [Q] maximum occupation number per node
     uint32_t* excess;       // [max_steps + 1][Q] particles above it, per time
+    int mirror;             // window layout: 0 node q in half q & 1 of plane q >> 1;
+                            // 1 (mirror pairs) pair p in plane p, node p low, Q-1-p high
+    int pad_;
 };
 
 struct InitArgs {
@@ -242,10 +255,10 @@ struct MomAtArgs {
 // Kernel launchers (sgpm_kernels.hip).  Return hipError_t as int.  The
 // batched launchers take device arrays of descriptors of n_inst instances of
 // one shape group and wg0[n_inst + 1], the first workgroup of each instance.
-int launch_k1(int fp32, int pmax, int qmax, const void* args, const uint32_t* wg0, int n_inst,
-              int moving, unsigned grid, size_t lds, void* stream);
-int launch_k2(int fp32, int pmax, int npl, const void* args, int n_inst, unsigned grid,
-              size_t lds, void* stream);
+int launch_k1(int fp32, int pmax, int qmax, int paired, const void* args, const uint32_t* wg0,
+              int n_inst, int moving, unsigned grid, size_t lds, void* stream);
+int launch_k2(int fp32, int pmax, int npl, int lanes, const void* args, int n_inst,
+              unsigned grid, size_t lds, void* stream);
 int launch_k3(const K3Args* args, const uint32_t* wg0, int n_inst, int moving, unsigned grid,
               void* stream);
 int launch_set_dyn(Dyn* d, int n, int set_step, uint32_t step, uint32_t rec_base, int set_dt,
@@ -258,8 +271,9 @@ int launch_moments_at(const MomAtArgs& a, int nwg, void* stream);
 double density_at(double eps0, double mu, double kT);   // electrons per m^2
 int launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n,
                   void* stream);
-size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words, int chunk);
+size_t k1_lds_bytes(int P, int Q, int fp32, int paired, int hwin_words, int64_t chunk);
 size_t k2_lds_bytes(int P, int Q, int fp32);
+size_t k2l_lds_bytes(int P, int Q, int fp32);   // the collider with a lane per candidate
 int k3_grid_of(int Q, int nk, int n_win_wg, int nb);
 
 }  // namespace sgpm

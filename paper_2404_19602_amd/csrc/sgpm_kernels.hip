@@ -191,6 +191,12 @@ __device__ __forceinline__ void wave_sums_add(const double (&v)[V], double* out,
     }
 }
 
+// Cross-lane exchange through LDS inside one wave: a wave's LDS operations
+// are performed in order, so only the compiler must keep them in order.
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 template <typename T>
 __device__ __forceinline__ T group_max(T v, int G) {
     for (int m = G >> 1; m >= 1; m >>= 1) {
@@ -339,8 +345,15 @@ __host__ __device__ constexpr size_t k1_fixed_bytes(int PM, int QA, size_t s, in
              (size_t)waves * QA * 3 * 8 + 16 * 4) + 15) & ~(size_t)15;
 }
 
-size_t k1_lds_bytes(int P, int Q, int fp32, int hwin_words, int chunk) {
+constexpr int kK1PSeg = 256;      // candidate list entries per wave of the mirror-pair kernel
+
+size_t k1_lds_bytes(int P, int Q, int fp32, int paired, int hwin_words, int64_t chunk) {
     const int PM = pmax_bucket(P), qb = qmax_bucket(Q);
+    if (paired) {
+        const int waves = k1p_block(fp32, PM, qb) / 64;
+        return k1_fixed_bytes(PM, qb, fp32 ? 4 : 8, waves) + (size_t)hwin_words * 4 +
+               (size_t)waves * kK1PSeg * 4;   // window, candidate lists of the waves
+    }
     return k1_fixed_bytes(PM, qb > 0 ? qb : Q, fp32 ? 4 : 8, k1_waves(fp32 != 0, PM, qb)) +
            (size_t)hwin_words * 4 + (size_t)chunk * 4;   // window, candidate buffer
 }
@@ -669,6 +682,319 @@ k1_stream(const K1Args<T>* __restrict__ all,
     if (tid < 8 && L.cnt[tid]) atomicAdd(&a.counters[tid], (unsigned long long)L.cnt[tid]);
 }
 
+// ============================================ K1 with mirror node pairs
+// For one uncertain input the Gauss-Legendre nodes are symmetric,
+// z_{Q-1-q} = -z_q, and the orthonormal Legendre basis has the parity
+// Psi_h(-z) = (-1)^h Psi_h(z), exactly in the tables.  With E and O the sums
+// of the even and of the odd modes at z_q, k(z_q) = E + O and
+// k(z_{Q-1-q}) = E - O: the two nodes of a pair cost the products of one
+// (eq. gPC evaluated at both nodes).  A lane per particle, as in k1_stream,
+// but with fewer instructions per node: the pairs, the collision bound from
+// the nodal energies before the drift plus the largest nodal drift
+// (|k - d| <= |k| + |d|), and candidate lists flushed to the global list by
+// each wave as they fill, so that a workgroup's chunk is not limited by its
+// LDS.  The workgroup owns a whole compute unit (three or four waves per
+// SIMD), and with it nearly all of the LDS for the histogram window.
+//
+// LDS window of this kernel: pair p in plane p, node p in the low and node
+// Q-1-p in the high 16 bits of a word, the middle node of an odd Q in the low
+// bits of plane (Q-1)/2.  The finalize kernel decodes it by the instance's
+// mirror flag.
+// VGPRs of the kernel, estimated: FP64 moment sums of every node, the
+// coefficients and the temporaries (measured on the compiler's output)
+__host__ __device__ constexpr int k1p_regs(int fp32, int pmax, int qmax) {
+    return 2 * (3 * qmax + 3) + 2 * pmax * (fp32 ? 1 : 2) + (fp32 ? 44 : 52);
+}
+int k1p_block(int fp32, int pmax, int qmax) {
+    const int r = k1p_regs(fp32, pmax, qmax);
+    return r <= 128 ? 1024 : (r <= 168 ? 768 : 512);
+}
+template <typename T, int PMAX, int QMAX>
+struct K1PBlock {
+    static constexpr int r = k1p_regs(sizeof(T) == 4, PMAX, QMAX);
+    static constexpr int value = r <= 128 ? 1024 : (r <= 168 ? 768 : 512);
+};
+
+// Wave sums of V per-lane values; store(k, s) receives the sum s of v[k] over
+// the wave, from one lane per k (the scheme of wave_sums_add).
+template <int V, typename F>
+__device__ __forceinline__ void wave_sums_map(const double (&v)[V], int lane, F&& store) {
+    constexpr int VP = (V + 3) & ~3, H2 = VP / 2, H4 = VP / 4;
+    double u[H2];
+#pragma unroll
+    for (int j = 0; j < H2; ++j) {
+        double a = v[j], b = j + H2 < V ? v[j + H2] : 0.0;
+        swap32_f64(a, b);
+        u[j] = a + b;
+    }
+    double w[H4];
+#pragma unroll
+    for (int j = 0; j < H4; ++j) {
+        double a = u[j], b = u[j + H4];
+        swap16_f64(a, b);
+        w[j] = a + b;
+    }
+#pragma unroll
+    for (int j = 0; j < H4; ++j) {
+        double x = w[j];
+        x += dpp_f64<0xB1>(x);
+        x += dpp_f64<0x4E>(x);
+        x += dpp_f64<0x141>(x);
+        x += dpp_f64<0x140>(x);
+        w[j] = x;
+    }
+    if ((lane & 15) == 0) {
+        const int r = lane >> 4, base = H4 * (r & 1) + H2 * (r >> 1);
+#pragma unroll
+        for (int j = 0; j < H4; ++j)
+            if (base + j < V) store(base + j, w[j]);
+    }
+}
+
+template <typename T, int PMAX, int QMAX>
+__global__ void __launch_bounds__((K1PBlock<T, PMAX, QMAX>::value))
+k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, int n_inst,
+         int moving) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    constexpr int BLOCK = K1PBlock<T, PMAX, QMAX>::value, WAVES = BLOCK / 64;
+    constexpr int NP = QMAX / 2;            // pair slots
+    __shared__ T s_shmax;
+    const int slot = find_slot(wg0, n_inst, blockIdx.x);
+    const K1Args<T> a = load_desc(all, slot);
+    const uint32_t wg = blockIdx.x - wg0[slot];
+    const uint32_t step = a.dyn->step_k1;
+    const double vfdt = a.dyn->vfdt;
+    if (moving && wg == 0 && threadIdx.x == 0) a.dyn->step_k2 = step;
+    if (wg == 0 && (int)threadIdx.x < a.Q)
+        a.excess[(size_t)(step - a.dyn->rec_base) * a.Q + threadIdx.x] = 0u;
+    const T dt = (T)a.dyn->dt;
+    const int P = a.P, Q = a.Q;
+    const K1Lds<T> L = k1_lds<T>(smem, PMAX, QMAX, a.hwin_words, WAVES);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    for (int w = tid; w < (a.hwin_words >> 2); w += BLOCK)
+        reinterpret_cast<uint4*>(L.hwin)[w] = make_uint4(0u, 0u, 0u, 0u);
+    if (tid == 0) *L.c = *a.tab.consts;
+    for (int k = tid; k < Q * PMAX; k += BLOCK) {
+        const int q = k / PMAX, h = k - q * PMAX;
+        L.psi[k] = h < P ? a.tab.psi[q * P + h] : (T)0;
+    }
+    const bool strang = a.tab.consts->splitting != 0;
+    for (int k = tid; k < PMAX; k += BLOCK) {
+        L.psimax[k] = k < P ? a.tab.psimax[k] : (T)0;
+        const T full = (moving && k < P) ? (T)(vfdt * a.ehat[k]) : (T)0;
+        L.drift[k] = strang ? full * (T)0.5 : full;
+        L.pdrift[k] = strang ? full * (T)0.5 : (T)0;
+    }
+    for (int k = tid; k < WAVES * Q * 3; k += BLOCK) L.red[k] = 0.0;
+    if (tid < 16) L.cnt[tid] = 0u;
+    __syncthreads();
+    for (int k = tid; k < Q; k += BLOCK) {
+        L.eps0sq[k] = a.tab.eps0sq[k];
+        T d = (T)0;
+        for (int h = 0; h < PMAX; ++h) d += L.drift[h] * L.psi[k * PMAX + h];
+        L.shift[k] = d;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        T m = (T)0;
+        for (int q = 0; q < Q; ++q) m = fmax(m, fabs(L.shift[q]));
+        s_shmax = m;
+    }
+    __syncthreads();
+    const Consts<T>& c = *L.c;
+    const T shmax = s_shmax;
+    const int64_t begin = (int64_t)wg * a.chunk;
+    const int64_t end = begin + a.chunk < a.n ? begin + a.chunk : a.n;
+    const int W = a.win;
+    int* seg = L.cbuf + wave * kK1PSeg;      // this wave's candidates
+    uint32_t nseg = 0;                       // wave-uniform
+
+    double acc[NP][2][3], accm[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) { acc[p][j][0] = 0.0; acc[p][j][1] = 0.0; acc[p][j][2] = 0.0; }
+
+    // this wave's list into the global one (one reservation)
+    auto flush = [&]() {
+        uint32_t gb = 0;
+        if (lane == 0) gb = atomicAdd(a.qc + 2 * (step & 1), nseg);
+        gb = __shfl(gb, 0, 64);
+        wave_lds_fence();
+        for (uint32_t k = lane; k < nseg; k += 64) a.cand[gb + k] = seg[k];
+        wave_lds_fence();
+        nseg = 0;
+    };
+
+    auto tile = [&](int64_t base, auto full) {
+        constexpr bool FULL = decltype(full)::value;
+        const int64_t i = base + tid;
+        const bool act = FULL || i < end;
+        // re-read on every tile (empty asm): see k1_stream
+        int Qt = Q;
+        uint32_t key_lo = a.seed_lo, key_hi = a.seed_hi;
+        __asm__ volatile("" : "+s"(Qt), "+s"(key_lo), "+s"(key_hi));
+        const int npairs = Qt >> 1;
+        T cx[PMAX], cy[PMAX];
+        load_tile_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, base, act ? (uint32_t)tid : 0u, cx, cy);
+        T e2max = (T)0;
+        uint32_t outmask = 0u;
+        // one nodal value of the state at t^n: window and moment sums
+        auto node = [&](int q, int plane, int j, T kx, T ky, double (&m)[3], int bit) {
+            const T e0sq = L.eps0sq[q];
+            const T e2 = kx * kx + ky * ky + e0sq;
+            const T rs = rsqrt_nr(e2);
+            if (act) {
+                if constexpr (sizeof(T) == 8) {
+                    m[0] += kx * rs;          // v_F applied to the lane's sums at the end
+                    m[1] += ky * rs;
+                } else {
+                    m[0] += (double)(c.v_f * kx * rs);
+                    m[1] += (double)(c.v_f * ky * rs);
+                }
+                m[2] += (double)(e2 * rs);
+            }
+            const T fr = floor((kx + c.lk) * c.inv_dk) - (T)a.win_r0;
+            const T fl = floor((ky + c.lk) * c.inv_dk) - (T)a.win_l0;
+            const T w = (T)W;
+            const bool in = (fr >= (T)0) & (fr < w) & (fl >= (T)0) & (fl < w);
+            if (act && in)
+                atomicAdd(&L.hwin[__mul24(plane, W * W) + __mul24((int)fr, W) + (int)fl],
+                          j ? 65536u : 1u);
+            outmask |= (act && !in) ? (1u << bit) : 0u;
+            e2max = fmax(e2, e2max);    // a NaN e2 is passed over
+        };
+        // the even and odd sums of pair p
+        auto eo = [&](int p, T& ex, T& ox, T& ey, T& oy) {
+            const T* row = L.psi + p * PMAX;
+            ex = (T)0; ox = (T)0; ey = (T)0; oy = (T)0;
+#pragma unroll
+            for (int h = 0; h < PMAX; h += 2) { ex += cx[h] * row[h]; ey += cy[h] * row[h]; }
+#pragma unroll
+            for (int h = 1; h < PMAX; h += 2) { ox += cx[h] * row[h]; oy += cy[h] * row[h]; }
+        };
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (p < npairs) {
+                T ex, ox, ey, oy;
+                eo(p, ex, ox, ey, oy);
+                node(p, p, 0, ex + ox, ey + oy, acc[p][0], 2 * p);
+                node(Qt - 1 - p, p, 1, ex - ox, ey - oy, acc[p][1], 2 * p + 1);
+            }
+            // one pair after the other: overlapping them buys little with three
+            // or four waves per SIMD and costs the registers of another wave
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (Qt & 1) {
+            T ex, ox, ey, oy;
+            eo(npairs, ex, ox, ey, oy);
+            node(npairs, npairs, 0, ex + ox, ey + oy, accm, 2 * NP);
+        }
+        // nodes outside the window (rare): the same values again, into the
+        // overflow grid or counted outside the grid
+        if (__ballot(outmask != 0u)) {
+            for (int b = 0; b <= 2 * NP; ++b) {
+                if (!(outmask & (1u << b))) continue;
+                const int p = b < 2 * NP ? (b >> 1) : npairs;
+                const int j = b < 2 * NP ? (b & 1) : 0;
+                T ex, ox, ey, oy;
+                eo(p, ex, ox, ey, oy);
+                const T kx = j ? ex - ox : ex + ox, ky = j ? ey - oy : ey + oy;
+                const int q = j ? Qt - 1 - p : p;
+                const int r = cell_coord<T>(kx, c.lk, c.inv_dk);
+                const int l = cell_coord<T>(ky, c.lk, c.inv_dk);
+                if (r < 0 || l < 0 || r >= c.nk || l >= c.nk)
+                    atomicAdd(&L.cnt[SGPM_CNT_OUT_OF_GRID], 1u);
+                else
+                    atomicAdd(&a.extra[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l], 1u);
+            }
+        }
+        // after the drift every nodal wave-vector moves by at most shmax, so
+        // sqrt(max e2) + shmax bounds every nodal energy (|k - d| <= |k| + |d|)
+        bool cand = false;
+        if (act && moving)
+            cand = k1_candidate<T>(a, c, i, (sqrt(e2max) + shmax) * c.b_margin, step, dt,
+                                   key_lo, key_hi);
+        if (act && moving && !cand) {
+            uint32_t tt = (uint32_t)tid;
+            __asm__ volatile("" : "+v"(tt));
+#pragma unroll
+            for (int h = 0; h < PMAX; ++h)
+                if (h < P && L.drift[h] != (T)0)
+                    (a.kx + ((size_t)h * a.n + base))[tt] = (cx[h] - L.drift[h]) - L.pdrift[h];
+        }
+        const uint64_t mask = __ballot(cand);
+        if (mask) {
+            const uint32_t nnew = (uint32_t)__popcll(mask);
+            if (lane == 0) atomicAdd(&L.cnt[SGPM_CNT_CANDIDATES], nnew);
+            if (cand) {
+                const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                seg[nseg + pos] = (int)i;
+            }
+            nseg += nnew;
+            if (nseg > (uint32_t)(kK1PSeg - 64)) flush();
+        }
+    };
+    int64_t base = begin;
+    for (; base + BLOCK <= end; base += BLOCK) tile(base, std::true_type{});
+    if (base < end) tile(base, std::false_type{});
+    // the waves' remaining candidates with one reservation for the workgroup
+    // (waves ending together would otherwise queue on the list's counter)
+    {
+        __shared__ uint32_t s_n[WAVES + 1];
+        if (lane == 0) s_n[wave] = nseg;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t tot = 0;
+            for (int w = 0; w < WAVES; ++w) { const uint32_t v = s_n[w]; s_n[w] = tot; tot += v; }
+            s_n[WAVES] = tot ? atomicAdd(a.qc + 2 * (step & 1), tot) : 0u;
+        }
+        __syncthreads();
+        const uint32_t gb = s_n[WAVES] + s_n[wave];
+        for (uint32_t k = lane; k < nseg; k += 64) a.cand[gb + k] = seg[k];
+    }
+    {
+        constexpr int V = 6 * NP + 3;
+        double v[V];
+        const double vf = sizeof(T) == 8 ? (double)c.v_f : 1.0;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                v[(2 * p + j) * 3] = vf * acc[p][j][0];
+                v[(2 * p + j) * 3 + 1] = vf * acc[p][j][1];
+                v[(2 * p + j) * 3 + 2] = acc[p][j][2];
+            }
+        v[6 * NP] = vf * accm[0]; v[6 * NP + 1] = vf * accm[1]; v[6 * NP + 2] = accm[2];
+        const int npairs = Q >> 1;
+        double* red = L.red + (size_t)wave * Q * 3;
+        wave_sums_map<V>(v, lane, [&](int k, double sum) {
+            const int m = k % 3, b = k / 3;
+            if (b < 2 * NP) {
+                const int p = b >> 1;
+                if (p < npairs) red[((b & 1) ? Q - 1 - p : p) * 3 + m] = sum;
+            } else if (Q & 1) {
+                red[npairs * 3 + m] = sum;
+            }
+        });
+    }
+    __syncthreads();
+    {
+        uint32_t* slab = a.slabs + (size_t)wg * a.hwin_words;
+        const int nv = a.hwin_words >> 2;
+        for (int w = tid; w < nv; w += BLOCK)
+            reinterpret_cast<uint4*>(slab)[w] = reinterpret_cast<const uint4*>(L.hwin)[w];
+    }
+    for (int k = tid; k < Q * 3; k += BLOCK) {
+        double v = 0.0;
+        for (int wv = 0; wv < WAVES; ++wv) v += L.red[wv * Q * 3 + k];
+        a.partial[(size_t)wg * Q * 3 + k] = v;
+    }
+    if (tid < 8 && L.cnt[tid]) atomicAdd(&a.counters[tid], (unsigned long long)L.cnt[tid]);
+}
+
 // ===================================================== K2: collider kernel
 // lanes per candidate of the collider: one node per lane, at most a wave
 __host__ __device__ __forceinline__ int k2_group_width(int Q) {
@@ -742,11 +1068,6 @@ __device__ __forceinline__ T pauli_f(const uint32_t* __restrict__ h_read,
     return (T)h / (T)mx;
 }
 
-// Cross-lane exchange through LDS inside one wave: a wave's LDS operations
-// are performed in order, so only the compiler must keep them in order.
-__device__ __forceinline__ void wave_lds_fence() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-}
 
 // The candidates of one instance in passes of kBlock / G candidates: this
 // workgroup takes the passes first, first + stride, ... below the instance's
@@ -993,10 +1314,270 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
     __syncthreads();
 }
 
+// ------------------------------------------ K2 with a lane per candidate
+// For at most 12 nodes a lane takes a whole candidate and loops over its
+// nodes, and a wave serves 64 candidates at once.  The draws, logarithm and
+// angles of a collision are then computed once per candidate instead of on
+// every lane of a node group, no lane idles for want of a node, and many more
+// candidates are in flight to hide the latency of their loads.  Every
+// quantity is computed by the same expressions as in k2_instance, sums over
+// the modes and the projection's sums over the nodes in the same order, and
+// the node maxima are exact, so the results are the same bit for bit.  The
+// exact edge rates of a collision wait in LDS (a column per lane) between the
+// pass that takes their maximum and the pass that selects the mechanisms.
+// The first edge proposal of a collision, shared by all of its nodes, is
+// drawn once and kept.
+// the lanes' edge rates [Q][kBlock] in the layout of k2_lds: as many of its
+// per-group scratch blocks (2 Q + 2 PMAX values each) as they take
+__host__ __device__ constexpr int k2l_groups(int Q, int PM) {
+    return Q * kBlock / (2 * Q + 2 * PM) + 1;
+}
+size_t k2l_lds_bytes(int P, int Q, int fp32) {
+    const size_t s = fp32 ? 4 : 8;
+    const int PM = pmax_bucket(P);
+    size_t off = sizeof(Consts<double>);
+    off = (off + 15) & ~(size_t)15;
+    off += s * (2 * (size_t)Q * PM + 4 * (size_t)Q + 32 + 2 * PM);
+    off = (off + 15) & ~(size_t)15;
+    off += s * (size_t)k2l_groups(Q, PM) * (2 * (size_t)Q + 2 * PM);
+    off = (off + 15) & ~(size_t)15;
+    off += 16 * 4;                                 // counters
+    return off;
+}
+
+template <typename T, int PMAX>
+__device__ __forceinline__ void k2_lanes_instance(const K2Args<T>& a, unsigned char* smem,
+                                                  uint32_t step, uint32_t total, uint32_t first,
+                                                  uint32_t stride) {
+    const int P = a.P, Q = a.Q;
+    // tables as in k2_instance; the per-group scratch holds the edge rates
+    const K2Lds<T> L = k2_lds<T>(smem, PMAX, Q, k2l_groups(Q, PMAX));
+    T* edge = L.scratch;                           // [Q][kBlock]
+    const int tid = threadIdx.x;
+    const T dt = (T)a.dyn->dt;
+    const double vfdt = a.dyn->vfdt;
+    const uint32_t* h_read = a.H + (size_t)(step % 3u) * a.hstride;
+    const uint32_t* hmax_read = a.Hmax + (size_t)(step % 3u) * a.hmstride;
+    if (tid == 0) *L.c = *a.tab.consts;
+    for (int k = tid; k < Q * PMAX; k += kBlock) {
+        const int q = k / PMAX, h = k - q * PMAX;
+        L.psi[k] = h < P ? a.tab.psi[q * P + h] : (T)0;
+        L.wpsi[k] = h < P ? a.tab.wpsi[q * P + h] : (T)0;
+    }
+    for (int k = tid; k < Q; k += kBlock) {
+        L.eps0[k] = a.tab.eps0[k]; L.eps0sq[k] = a.tab.eps0sq[k];
+        L.cedge[k] = a.tab.cedge[k]; L.vfield[k] = a.tab.vfield[k];
+    }
+    for (int k = tid; k <= kEdgePts / 2; k += kBlock) L.ecos[k] = a.tab.edge_cos[k];
+    const bool strang = a.tab.consts->splitting != 0;
+    for (int k = tid; k < PMAX; k += kBlock) {
+        const T full = k < P ? (T)(vfdt * a.ehat[k]) : (T)0;
+        L.drift[k] = strang ? full * (T)0.5 : full;
+        L.pdrift[k] = strang ? full * (T)0.5 : (T)0;
+    }
+    if (tid < 16) L.cnt[tid] = 0u;
+    __syncthreads();
+    const Consts<T>& c = *L.c;
+    const T dt_grid = strang ? dt * (T)0.5 : dt;
+    uint32_t n_coll = 0, n_ev = 0, n_rej = 0, n_exh = 0, n_cmax = 0;
+
+    for (uint32_t p0 = first * kBlock; p0 < total; p0 += stride * kBlock) {
+        const uint32_t cid = p0 + tid;
+        bool live = cid < total;
+        int64_t i = 0;
+        T cx[PMAX], cy[PMAX];
+#pragma unroll
+        for (int h = 0; h < PMAX; ++h) { cx[h] = (T)0; cy[h] = (T)0; }
+        if (live) {
+            i = a.cand[cid];
+            load_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, i, L.drift, cx, cy);
+        }
+        T tc = (T)0;
+        uint32_t coll = 0;
+        const uint32_t ctr0 = (uint32_t)i;
+        // one collision iteration of this lane's candidate; false ends it
+        auto iterate = [&]() -> bool {
+            // node values, phonon rates and a bound of Gamma~ (the edge
+            // integral is at most 2 pi), as in k2_instance
+            T sb = (T)0;
+            for (int q = 0; q < Q; ++q) {
+                T kx, ky;
+                eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
+                const T ne = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
+                T r[5];
+                phonon_rates<T>(c, ne, L.eps0[q], r);
+                T run = (T)0;
+#pragma unroll
+                for (int m = 0; m < 5; ++m) run += r[m];
+                run += (ne - L.eps0[q] >= (T)0)
+                           ? L.cedge[q] * ne * ((T)kEdgePts * Num<T>::trap) : (T)0;
+                sb = run > sb ? run : sb;
+            }
+            const Words wx = k2_draw<T>(ctr0, step, (coll << 8) | kPurXi, a.instance, a.seed_lo,
+                                        a.seed_hi);
+            const T lxi = -dlog(uni<T>(wx.w0, wx.w1));
+            if (!(tc + lxi / (c.alpha1 * sb * ((T)1 + (T)16 * Num<T>::eps)) < dt)) return false;
+            // exact rates: the edge integral of every node
+            T smax = (T)0;
+            for (int q = 0; q < Q; ++q) {
+                T kx, ky;
+                eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
+                const T ne = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
+                T r[5];
+                phonon_rates<T>(c, ne, L.eps0[q], r);
+                T run = (T)0;
+#pragma unroll
+                for (int m = 0; m < 5; ++m) run += r[m];
+                const T e = edge_rate<T>(c, L.ecos, L.cedge[q], L.eps0[q], kx, ky, ne);
+                edge[q * kBlock + tid] = e;
+                run = run + e;
+                smax = run > smax ? run : smax;
+            }
+            const T Gt = c.alpha1 * smax;
+            const T dtc = lxi / Gt;   // eq. dt, node maximum
+            if (!(tc + dtc < dt)) return false;
+            ++n_coll;
+            const Words ws = k2_draw<T>(ctr0, step, (coll << 8) | kPurSel, a.instance, a.seed_lo,
+                                        a.seed_hi);
+            const T su = uni<T>(ws.w0, ws.w1), eta = uni<T>(ws.w2, ws.w3);
+            const Words wa = k2_draw<T>(ctr0, step, (coll << 8) | kPurAng, a.instance, a.seed_lo,
+                                        a.seed_hi);
+            const T u1 = uni<T>(wa.w0, wa.w1), u2 = uni<T>(wa.w2, wa.w3);
+            T s_phi, c_phi;
+            dsincospi((T)2 * u2, &s_phi, &c_phi);
+            const T rr = sqrt(u1);
+            const T dx = (T)1 + rr * c_phi, dy = rr * s_phi;
+            const T n2 = dx * dx + dy * dy;
+            const T cac = (dx * dx - dy * dy) / n2, sac = ((T)2 * dx * dy) / n2;
+            T sop, cop;
+            dsincospi((T)2 * u1, &sop, &cop);    // OP angle 2 pi u1
+            bool have0 = false;                   // the first edge proposal, drawn once
+            T st0 = (T)0, ct0 = (T)0, v0 = (T)0;
+            T ax[PMAX], ay[PMAX];
+#pragma unroll
+            for (int h = 0; h < PMAX; ++h) { ax[h] = (T)0; ay[h] = (T)0; }
+            for (int q = 0; q < Q; ++q) {
+                T kx, ky;
+                eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
+                const T e = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
+                const T e0 = L.eps0[q];
+                T r[5], cum[6];
+                phonon_rates<T>(c, e, e0, r);
+                T run = (T)0;
+#pragma unroll
+                for (int m = 0; m < 5; ++m) { run += r[m]; cum[m] = run; }
+                cum[5] = cum[4] + edge[q * kBlock + tid];
+                int ell = 7;
+#pragma unroll
+                for (int m = 5; m >= 0; --m)
+                    if (su < cum[m] / Gt) ell = m + 1;
+                T nx = kx, ny = ky;
+                if (ell != 7) {
+                    const T kabs = sqrt(kx * kx + ky * ky);
+                    const T cin = kabs > (T)0 ? kx / kabs : (T)1;
+                    const T sin_ = kabs > (T)0 ? ky / kabs : (T)0;
+                    T px = kx, py = ky;
+                    bool ok = true;
+                    if (ell == 6) {
+                        const T kap = c.edge_kap * (kx * kx + ky * ky);
+                        if (!have0) {
+                            const Words we = k2_draw<T>(ctr0, step, (coll << 8) | kPurEdge0,
+                                                        a.instance, a.seed_lo, a.seed_hi);
+                            const T ut = uni<T>(we.w0, we.w1);
+                            v0 = uni<T>(we.w2, we.w3);
+                            dsincospi((T)2 * ut, &st0, &ct0);
+                            have0 = true;
+                        }
+                        const T d0 = ct0 - cin;
+                        ok = v0 < dexp(-kap * d0 * d0);
+                        if (ok) { px = kabs * ct0; py = kabs * st0; }
+                        for (uint32_t jt = 1; !ok && jt < (uint32_t)kEdgeTries; ++jt) {
+                            const Words we = k2_draw<T>(ctr0, step, (coll << 8) | (kPurEdge0 + jt),
+                                                        a.instance, a.seed_lo, a.seed_hi);
+                            const T ut = uni<T>(we.w0, we.w1), v = uni<T>(we.w2, we.w3);
+                            T st, ct;
+                            dsincospi((T)2 * ut, &st, &ct);
+                            const T d = ct - cin;
+                            if (v < dexp(-kap * d * d)) {
+                                px = kabs * ct; py = kabs * st;
+                                ok = true;
+                            }
+                        }
+                        if (!ok) ++n_exh;
+                    } else {
+                        T ct, st, mag;
+                        if (ell == 1) { ct = cac; st = sac; mag = kabs; }
+                        else {
+                            const bool op = (ell == 2 || ell == 3);
+                            const T hw = op ? c.hw_o : c.hw_k;
+                            const T de = (ell == 2 || ell == 4) ? -hw : hw;
+                            if (op) { ct = cop; st = sop; } else { ct = -cac; st = -sac; }
+                            if (c.final_state == 1) {
+                                mag = kabs + de;
+                            } else {
+                                const T e1 = e + de;     // energy-conserving final state
+                                mag = sqrt((e1 - e0) * (e1 + e0));
+                            }
+                        }
+                        px = mag * (ct * cin - st * sin_);
+                        py = mag * (st * cin + ct * sin_);
+                    }
+                    if (ok) {
+                        ++n_ev;
+                        const T f = c.pauli ? pauli_f<T>(h_read, hmax_read, L, c, q, px, py, dt_grid)
+                                            : (T)0;
+                        if (f < eta) { nx = px; ny = py; } else { ++n_rej; }
+                    }
+                }
+                // k_h = sum_q w_q Psi_h(z_q) k_q, summed over the nodes in order
+#pragma unroll
+                for (int h = 0; h < PMAX; ++h) {
+                    ax[h] += L.wpsi[q * PMAX + h] * nx;
+                    ay[h] += L.wpsi[q * PMAX + h] * ny;
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < PMAX; ++h) {
+                cx[h] = h < P ? ax[h] : (T)0;
+                cy[h] = h < P ? ay[h] : (T)0;
+            }
+            tc += dtc;
+            ++coll;
+            if (coll >= (uint32_t)c.c_max) { ++n_cmax; return false; }
+            return true;
+        };
+        while (__ballot(live))
+            if (live) live = iterate();
+        if (cid < total) {
+#pragma unroll
+            for (int h = 0; h < PMAX; ++h)
+                if (h < P) {
+                    a.kx[(size_t)h * a.n + i] = cx[h] - L.pdrift[h];
+                    a.ky[(size_t)h * a.n + i] = cy[h];
+                }
+        }
+    }
+    if (n_coll) atomicAdd(&L.cnt[SGPM_CNT_COLLISIONS], n_coll);
+    if (n_ev) atomicAdd(&L.cnt[SGPM_CNT_EVENTS], n_ev);
+    if (n_rej) atomicAdd(&L.cnt[SGPM_CNT_PAULI_REJ], n_rej);
+    if (n_exh) atomicAdd(&L.cnt[SGPM_CNT_EDGE_EXH], n_exh);
+    if (n_cmax) atomicAdd(&L.cnt[SGPM_CNT_CMAX], n_cmax);
+    __syncthreads();
+    if (tid < 8 && L.cnt[tid]) atomicAdd(&a.counters[tid], (unsigned long long)L.cnt[tid]);
+    __syncthreads();
+}
+
 // Collider grid of a group.  The passes of all instances, concatenated in
 // instance order, are dealt out round-robin.  Workgroup 0 advances the
 // finalize kernel's copy of the step of every instance (that kernel is done).
-template <typename T, int PMAX, int NPL>
+template <typename T, int PMAX, int NPL, bool LANES>
+__device__ __forceinline__ void k2_run(const K2Args<T>& a, unsigned char* smem, uint32_t step,
+                                       uint32_t total, uint32_t first, uint32_t stride) {
+    if constexpr (LANES) k2_lanes_instance<T, PMAX>(a, smem, step, total, first, stride);
+    else k2_instance<T, PMAX, NPL>(a, smem, step, total, first, stride);
+}
+
+template <typename T, int PMAX, int NPL, bool LANES = false>
 __device__ __forceinline__ void k2_body(const K2Args<T>* __restrict__ all, int n_inst) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     constexpr int kPer = (SGPM_MAX_INSTANCES + kBlock - 1) / kBlock;   // instances per thread
@@ -1017,7 +1598,7 @@ __device__ __forceinline__ void k2_body(const K2Args<T>* __restrict__ all, int n
         if (blockIdx.x == 0 && tid == 0) a.dyn->step_k3 = step + 1u;   // the finalize kernel is done
         const uint32_t per_pass = (uint32_t)(kBlock / a.G);
         if (blockIdx.x < (total + per_pass - 1) / per_pass)
-            k2_instance<T, PMAX, NPL>(a, smem, step, total, blockIdx.x, grid);
+            k2_run<T, PMAX, NPL, LANES>(a, smem, step, total, blockIdx.x, grid);
         return;
     }
     // every instance's step, list length and pass count, read in parallel
@@ -1081,7 +1662,7 @@ __device__ __forceinline__ void k2_body(const K2Args<T>* __restrict__ all, int n
         const int j = (int)s_list[t];
         const uint32_t r = (blockIdx.x + grid - s_base[j] % grid) % grid;
         const K2Args<T> a = load_desc(all, j);
-        k2_instance<T, PMAX, NPL>(a, smem, s_step[j], s_total[j], r, grid);
+        k2_run<T, PMAX, NPL, LANES>(a, smem, s_step[j], s_total[j], r, grid);
     }
 }
 
@@ -1106,7 +1687,24 @@ __global__ void __launch_bounds__(kBlock) k2_collide_wide(const K2Args<T>* __res
     k2_body<T, PMAX, NPL>(all, n_inst);
 }
 
+// a lane per candidate (at most 12 nodes)
+template <typename T, int PMAX>
+__global__ void __launch_bounds__(kBlock) k2_lanes(const K2Args<T>* __restrict__ all, int n_inst) {
+    k2_body<T, PMAX, 1, true>(all, n_inst);
+}
+
 // ===================================================== K3: finalize kernel
+// Node counted in half hi of window plane p, or -1 if that half is unused:
+// two consecutive nodes per plane, or (mirror) node p low and Q-1-p high.
+__device__ __forceinline__ int win_node(int mirror, int Q, int p, int hi) {
+    if (mirror) {
+        if (hi) return p < (Q >> 1) ? Q - 1 - p : -1;
+        return p < ((Q + 1) >> 1) ? p : -1;
+    }
+    const int q = 2 * p + hi;
+    return q < Q ? q : -1;
+}
+
 // Workgroups [0, n_win_wg): kK3Words window words each (two cells per word),
 // every slab summed, plus the overflow count, into H^n.  Workgroups after
 // that: kK3Rest cells of the rest of the grid (overflow count only).  Every
@@ -1161,8 +1759,8 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
                 // of plane p (the window layout of win_word)
                 const int word = word0 + (k >> 1);
                 const int p = word / wcells, rem = word - p * wcells;
-                const int q = 2 * p + (k & 1);
-                const bool ok = word < wwords && q < a.Q;
+                const int q = win_node(a.mirror, a.Q, p, k & 1);
+                const bool ok = word < wwords && q >= 0;
                 const int r = a.win_r0 + rem / a.win, l = a.win_l0 + rem % a.win;
                 qc[k] = ok ? q : -1;
                 gc[k] = ok ? (size_t)q * cells + (size_t)r * a.nk + l : 0;
@@ -1196,8 +1794,8 @@ __global__ void __launch_bounds__(kBlock) k3_finalize(const K3Args* __restrict__
             // half tid & 1 of the block's word tid >> 1 (the window layout of win_word)
             const int word = wb * kK3Words + (tid >> 1);
             const int p = word / wcells, rem = word - p * wcells;
-            const int q = 2 * p + (tid & 1);
-            if (word < wwords && q < a.Q) {
+            const int q = win_node(a.mirror, a.Q, p, tid & 1);
+            if (word < wwords && q >= 0) {
                 q_set = q;
                 const int r = a.win_r0 + rem / a.win, l = a.win_l0 + rem % a.win;
                 g_set = (size_t)q_set * cells + (size_t)r * a.nk + l;
@@ -1330,8 +1928,38 @@ static int launch_k1_any(int pmax, int qmax, const void* args, const uint32_t* w
     }
 }
 
-int launch_k1(int fp32, int pmax, int qmax, const void* args, const uint32_t* wg0, int n_inst,
-              int moving, unsigned grid, size_t lds, void* stream) {
+template <typename T, int PMAX, int QMAX>
+static int launch_k1p_t(const void* args, const uint32_t* wg0, int n_inst, int moving,
+                        unsigned grid, size_t lds, void* stream) {
+    hipLaunchKernelGGL((k1_pairs<T, PMAX, QMAX>), dim3(grid), dim3(K1PBlock<T, PMAX, QMAX>::value), lds,
+                       (hipStream_t)stream, static_cast<const K1Args<T>*>(args), wg0, n_inst,
+                       moving);
+    return (int)hipGetLastError();
+}
+
+template <typename T>
+static int launch_k1p_any(int pmax, int qmax, const void* args, const uint32_t* wg0, int n_inst,
+                          int moving, unsigned grid, size_t lds, void* stream) {
+    const bool q12 = qmax == 12;
+    switch (pmax) {
+    case 3: return q12 ? launch_k1p_t<T, 3, 12>(args, wg0, n_inst, moving, grid, lds, stream)
+                       : launch_k1p_t<T, 3, 8>(args, wg0, n_inst, moving, grid, lds, stream);
+    case 6: return q12 ? launch_k1p_t<T, 6, 12>(args, wg0, n_inst, moving, grid, lds, stream)
+                       : launch_k1p_t<T, 6, 8>(args, wg0, n_inst, moving, grid, lds, stream);
+    case 9: return q12 ? launch_k1p_t<T, 9, 12>(args, wg0, n_inst, moving, grid, lds, stream)
+                       : launch_k1p_t<T, 9, 8>(args, wg0, n_inst, moving, grid, lds, stream);
+    default: return q12 ? launch_k1p_t<T, 16, 12>(args, wg0, n_inst, moving, grid, lds, stream)
+                        : launch_k1p_t<T, 16, 8>(args, wg0, n_inst, moving, grid, lds, stream);
+    }
+}
+
+int launch_k1(int fp32, int pmax, int qmax, int paired, const void* args, const uint32_t* wg0,
+              int n_inst, int moving, unsigned grid, size_t lds, void* stream) {
+    if (paired) {
+        if (!k1p_buckets(pmax, qmax)) return (int)hipErrorInvalidValue;
+        if (fp32) return launch_k1p_any<float>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream);
+        return launch_k1p_any<double>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream);
+    }
     if (fp32) return launch_k1_any<float>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream);
     return launch_k1_any<double>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream);
 }
@@ -1359,10 +1987,32 @@ static int launch_k2_n(int pmax, const K2Args<T>* a, int n_inst, unsigned grid, 
     return (int)hipGetLastError();
 }
 
-// npl: nodes per lane, 2 when some instance of the group has more than 64 nodes
-int launch_k2(int fp32, int pmax, int npl, const void* args, int n_inst, unsigned grid,
-              size_t lds, void* stream) {
+template <typename T>
+static int launch_k2l(int pmax, const K2Args<T>* a, int n_inst, unsigned grid, size_t lds,
+                      hipStream_t s) {
+    const dim3 g(grid), b(kBlock);
+    switch (pmax) {
+    case 1: hipLaunchKernelGGL((k2_lanes<T, 1>), g, b, lds, s, a, n_inst); break;
+    case 3: hipLaunchKernelGGL((k2_lanes<T, 3>), g, b, lds, s, a, n_inst); break;
+    case 6: hipLaunchKernelGGL((k2_lanes<T, 6>), g, b, lds, s, a, n_inst); break;
+    case 9: hipLaunchKernelGGL((k2_lanes<T, 9>), g, b, lds, s, a, n_inst); break;
+    case 16: hipLaunchKernelGGL((k2_lanes<T, 16>), g, b, lds, s, a, n_inst); break;
+    default: hipLaunchKernelGGL((k2_lanes<T, 32>), g, b, lds, s, a, n_inst); break;
+    }
+    return (int)hipGetLastError();
+}
+
+// npl: nodes per lane, 2 when some instance of the group has more than 64
+// nodes; lanes: a lane per candidate (every instance has at most 12 nodes)
+int launch_k2(int fp32, int pmax, int npl, int lanes, const void* args, int n_inst,
+              unsigned grid, size_t lds, void* stream) {
     const hipStream_t s = (hipStream_t)stream;
+    if (lanes) {
+        if (fp32) return launch_k2l<float>(pmax, static_cast<const K2Args<float>*>(args), n_inst,
+                                           grid, lds, s);
+        return launch_k2l<double>(pmax, static_cast<const K2Args<double>*>(args), n_inst, grid,
+                                  lds, s);
+    }
     if (fp32) {
         const K2Args<float>* a = static_cast<const K2Args<float>*>(args);
         return npl > 1 ? launch_k2_n<float, 2>(pmax, a, n_inst, grid, lds, s)

@@ -200,3 +200,81 @@ def test_autotune_keeps_the_run(sg, batched):
             for k in ("E_vx", "E_energy", "SE_E_vx"):
                 assert np.array_equal(ma[k], mb[k]), (j, k)
             assert np.array_equal(ea, eb), j
+
+
+@pytest.mark.parametrize("kw", [
+    dict(),                                                             # 6 modes, 8 nodes
+    dict(precision="fp32", degree=8, nodes_1d=12, nk=256, field0=4e6),  # 9 modes, 12 nodes
+    dict(dim_z=0, degree=0, nodes_1d=1, gap_dim=-1, gap_rel=0.0),        # one node
+    dict(dim_z=2, degree=2, nodes_1d=3, field_dim=1, field_rel=0.2),     # 2-D, 9 nodes
+    dict(pauli=0, final_state=1, field0=5e6, degree=3, nodes_1d=4),
+    dict(splitting=1, field0=5e6, rate_scale=(3.0,) * 6),
+])
+def test_collider_lanes_match_node_groups(sg, kw):
+    """The collider with a lane per candidate and the one with a group of lanes
+    per candidate compute the same quantities by the same expressions: the
+    runs are identical bit for bit."""
+    cfg = cfg_of(n_particles=20_000, **kw)
+    print(f"\n[gpu case] collider lanes vs node groups {kw}", flush=True)
+    out = []
+    for lanes in (True, False):
+        sim = sg.Simulation(cfg, max_steps=60)
+        sim.set_collider_lanes(lanes)
+        sim.init_particles()
+        sim.step(60)
+        out.append(snapshot(sim))
+    assert out[0]["cnt"]["collisions"] > 0
+    assert_same(out[0], out[1], "lanes vs groups")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_node_pairs_match_the_generic_stream_kernel(sg, prec):
+    """The mirror-pair stream kernel against the generic one: the node values
+    differ only by rounding (even and odd modes summed apart), so histograms
+    and event counters agree exactly and the trajectories to rounding.  The
+    candidate count differs: the pair kernel bounds the energies after the
+    drift by the bound before it plus the largest drift, a looser bound that
+    hands more particles to the collider, whose exact test rejects them."""
+    cfg = cfg_of(n_particles=50_000, precision=prec, degree=8, nodes_1d=12, nk=256, field0=4e6)
+    print(f"\n[gpu case] node pairs vs generic {prec}", flush=True)
+    out = []
+    for on in (True, False):
+        sim = sg.Simulation(cfg, max_steps=40)
+        sim.set_node_pairs(on)
+        assert sim.node_pairs() == on
+        sim.init_particles()
+        sim.step(40)
+        out.append(snapshot(sim))
+    a, b = out
+    tol = 1e-9 if prec == "fp64" else 2e-4
+    scale = np.maximum(np.sqrt((b["kx"] ** 2 + b["ky"] ** 2).sum(axis=0)), 1e-3)
+    err = np.maximum(np.abs(a["kx"] - b["kx"]).max(axis=0), np.abs(a["ky"] - b["ky"]).max(axis=0))
+    flips = int(np.count_nonzero(err / scale > tol))
+    print(f"  flipped particles {flips}", flush=True)
+    assert flips <= (2 if prec == "fp64" else 50)
+    if flips == 0:
+        assert np.array_equal(a["H"], b["H"]) and np.array_equal(a["M"], b["M"])
+        ca, cb = dict(a["cnt"]), dict(b["cnt"])
+        assert ca.pop("candidates") >= cb.pop("candidates")
+        assert ca == cb
+    assert np.allclose(a["rec"], b["rec"], rtol=1e-6 if prec == "fp32" else 1e-9)
+
+
+def test_automatic_kernel_choice(sg):
+    """The mirror-pair stream kernel is chosen by default only for shape
+    groups of 2^22 particles or more; either choice can be forced."""
+    small = sg.Simulation(cfg_of(degree=8, nodes_1d=12, nk=256), max_steps=4)
+    assert small.node_pairs() is False
+    small.init_particles()
+    small.set_node_pairs(True)
+    assert small.node_pairs() is True
+    small.step(2)
+    del small
+    big = sg.Simulation(cfg_of(degree=8, nodes_1d=12, nk=256, n_particles=1 << 22), max_steps=4)
+    assert big.node_pairs() is True
+    big.init_particles()
+    big.set_node_pairs(False)
+    assert big.node_pairs() is False
+    big.set_node_pairs(None)
+    assert big.node_pairs() is True
+    big.step(2)
