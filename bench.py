@@ -30,6 +30,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -39,11 +40,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "sg_gap_m8_q12_n3e7"
 SECONDARY = "sg_gap_m5_q8_n1e6"
-KERNEL_SYMBOLS = {"stream": "sgpm::k1_stream", "finalize": "sgpm::k3_finalize",
-                  "collide": "sgpm::k2_collide"}
 # kernel-name patterns of the headline's FP64 launches in a profiler's output
-HEADLINE_KERNELS = {"stream": "k1_stream<double", "finalize": "k3_finalize",
-                    "collide": "k2_collide"}
+# (the stream kernel in its generic or mirror-pair form, the collider with a
+# group of lanes or a lane per candidate)
+HEADLINE_KERNELS = {"stream": r"k1_(stream|pairs)<double", "finalize": r"k3_finalize",
+                    "collide": r"k2_(collide|collide_wide|lanes)<double"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_sg_gap_m8_q12_n3e7.json")
 OBSERVABLES = ("E_vx", "Var_vx", "E_jx", "Var_jx", "E_energy")
 
@@ -58,6 +59,14 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, "paper_2404_19602_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def kernel_symbols(sim, inst: int = 0) -> dict:
+    """The kernel each step role of instance inst is launched as (template
+    arguments left out: precision, mode and node buckets)."""
+    return {"stream": "sgpm::k1_pairs" if sim.node_pairs(inst) else "sgpm::k1_stream",
+            "finalize": "sgpm::k3_finalize",
+            "collide": "sgpm::k2_lanes" if sim.collider_lanes(inst) else "sgpm::k2_collide"}
 
 
 def kernel_bytes(cfg: dict, P: int, Q: int, n_drift: int, cand: float) -> dict:
@@ -123,6 +132,7 @@ def run_gpu(cfgs, steps: int, warmup: int, profile: bool = True, tune: bool = Tr
         sim.step(steps, dt)
         out["kernels"] = sim.kernel_times()
         sim.set_profiling(False)
+    out["symbols"] = kernel_symbols(sim)
     return out
 
 
@@ -139,7 +149,7 @@ def roofline_of(cfg, r, P, Q) -> tuple:
     dom = max(per, key=lambda k: per[k]["avg_ms"])
     ach = per[dom]["GBps"]
     roof = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": KERNEL_SYMBOLS[dom],
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": r["symbols"][dom],
             "kernel_ms": per[dom]["avg_ms"], "bytes_per_launch": per[dom]["bytes_per_launch"],
             "timing": "HIP events around each launch on the library's stream, "
                       "in a replay of the timed steps from the same state"}
@@ -304,7 +314,8 @@ def pmc_summary(fetch_csv: str, write_csv: str, out_path: str = TRAFFIC_FILE,
                     continue
                 v = float(r["Counter_Value"])
                 by.setdefault(r["Kernel_Name"], []).append(v)
-                key = next((k for k, pat in names.items() if pat in r["Kernel_Name"]), None)
+                key = next((k for k, pat in names.items() if re.search(pat, r["Kernel_Name"])),
+                           None)
                 if key is not None and r.get("Dispatch_Id"):
                     wgs = None
                     if r.get("Grid_Size") and r.get("Workgroup_Size"):
@@ -351,8 +362,8 @@ def pmc_summary(fetch_csv: str, write_csv: str, out_path: str = TRAFFIC_FILE,
             fk = [s[j][2] for s in fsteps]
             wk = [s[j][2] for s in wsteps]
         else:
-            fk = [v for k, vs in f.items() if pat in k for v in vs]
-            wk = [v for k, vs in w.items() if pat in k for v in vs]
+            fk = [v for k, vs in f.items() if re.search(pat, k) for v in vs]
+            wk = [v for k, vs in w.items() if re.search(pat, k) for v in vs]
         out["kernels"][key] = {"dispatches": len(fk),
                                "fetch_bytes": statistics.median(fk) * 1024 * cf,
                                "write_bytes": statistics.median(wk) * 1024 * cw}

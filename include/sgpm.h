@@ -198,6 +198,10 @@ sgpm_status sgpm_set_collider_lanes(sgpm_ctx* ctx, int32_t on);
 /* *paired = 1 if instance inst is stepped by the mirror-pair stream kernel. */
 sgpm_status sgpm_node_pairs(const sgpm_ctx* ctx, int32_t inst, int32_t* paired);
 
+/* *lanes = 1 if the candidates of instance inst are collided a lane per
+ * candidate, 0 if a group of lanes per candidate. */
+sgpm_status sgpm_collider_lanes(const sgpm_ctx* ctx, int32_t inst, int32_t* lanes);
+
 /* Launch mode of sgpm_step: 0 = every kernel launched on the stream; B >= 1
  * = blocks of B steps captured once as a HIP graph (on a private stream) and
  * replayed on the context's stream, remainders from a graph of their own

@@ -128,6 +128,11 @@ class Simulation:
         check(lib().sgpm_node_pairs(self._ctx, inst, C.byref(v)), self._ctx, "node_pairs")
         return bool(v.value)
 
+    def collider_lanes(self, inst: int = 0) -> bool:
+        v = C.c_int32(0)
+        check(lib().sgpm_collider_lanes(self._ctx, inst, C.byref(v)), self._ctx, "collider_lanes")
+        return bool(v.value)
+
     def set_graph(self, steps_per_graph: int):
         """0: launch every kernel; B >= 1: replay captured graphs of B steps."""
         check(lib().sgpm_set_graph(self._ctx, steps_per_graph), self._ctx, "set_graph")

@@ -74,6 +74,7 @@ def lib():
             "sgpm_set_stream_lds": (i32, [vp, i32, i32]),
             "sgpm_window": (i32, [vp, i32, C.POINTER(i32), C.POINTER(i32)]),
             "sgpm_node_pairs": (i32, [vp, i32, C.POINTER(i32)]),
+            "sgpm_collider_lanes": (i32, [vp, i32, C.POINTER(i32)]),
             "sgpm_set_profiling": (i32, [vp, i32]),
             "sgpm_kernel_times": (i32, [vp, vp, vp]),
             "sgpm_autotune": (i32, [vp, dbl, i32, C.POINTER(dbl)]),

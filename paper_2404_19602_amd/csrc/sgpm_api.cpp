@@ -1087,6 +1087,12 @@ sgpm_status sgpm_node_pairs(const sgpm_ctx* c, int32_t inst, int32_t* paired) {
     return SGPM_OK;
 }
 
+sgpm_status sgpm_collider_lanes(const sgpm_ctx* c, int32_t inst, int32_t* lanes) {
+    if (!c || inst < 0 || inst >= (int32_t)c->inst.size() || !lanes) return SGPM_EINVAL;
+    *lanes = c->groups[c->inst[inst].grp].lanes ? 1 : 0;
+    return SGPM_OK;
+}
+
 sgpm_status sgpm_set_graph(sgpm_ctx* c, int32_t steps_per_graph) {
     if (!c) return SGPM_EINVAL;
     if (steps_per_graph < 0 || steps_per_graph > kMaxGraphSteps)

@@ -45,14 +45,16 @@ def test_kernel_bytes_of_the_headline_workload():
 
 
 def _run(kernels, wall=2.0, steps=1000):
-    return {"n_drift": 1, "cand": (350_000.0,), "kernels": kernels, "wall": wall, "steps": steps}
+    return {"n_drift": 1, "cand": (350_000.0,), "kernels": kernels, "wall": wall, "steps": steps,
+            "symbols": {"stream": "sgpm::k1_pairs", "finalize": "sgpm::k3_finalize",
+                        "collide": "sgpm::k2_lanes"}}
 
 
 def test_roofline_is_the_longest_kernel():
     cfg = headline()
     r = _run({"stream": (1.50, 1000), "finalize": (0.05, 1000), "collide": (1.00, 1000)})
     roof, per, step = bench.roofline_of(cfg, r, 9, 12)
-    assert roof["kernel"] == "sgpm::k1_stream"
+    assert roof["kernel"] == "sgpm::k1_pairs"
     assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
     want = per["stream"]["bytes_per_launch"] / 1.5e-3 / 1e9
     assert roof["achieved"] == pytest.approx(want)
@@ -60,7 +62,7 @@ def test_roofline_is_the_longest_kernel():
     # no margin in favour of any kernel: a collider 1 % longer takes the roofline
     r["kernels"]["collide"] = (1.515, 1000)
     roof, _, _ = bench.roofline_of(cfg, r, 9, 12)
-    assert roof["kernel"] == "sgpm::k2_collide"
+    assert roof["kernel"] == "sgpm::k2_lanes"
 
 
 def test_roofline_of_the_whole_step():
