@@ -187,7 +187,7 @@ sgpm_status sgpm_window(const sgpm_ctx* ctx, int32_t inst, int32_t* win, int32_t
  * is re-recorded). */
 sgpm_status sgpm_set_node_pairs(sgpm_ctx* ctx, int32_t on);
 
-/* Collider of the instances with at most 12 nodes: on > 0 a lane per
+/* Collider of the instances with at most 12 nodes and 16 modes: on > 0 a lane per
  * candidate, which loops over the candidate's nodes; 0 a group of lanes per
  * candidate, a node per lane (the form used beyond 12 nodes); on < 0 (the
  * default) the lane form for shape groups of 2^22 particles or more.  The

@@ -524,7 +524,9 @@ sgpm_status upload_args(sgpm_ctx* c) {
         uint32_t *t1 = tab(kTabK1, off), *t3 = tab(kTabK3, off);
         t1[0] = t3[0] = 0u;
         G.k1_lds = 0; G.k2_lds = 0; G.npl = 1;
-        G.lanes = G.qmax >= 1 && G.qmax <= 12 &&
+        // a lane per candidate for at most 12 nodes and 16 modes (its LDS holds
+        // the modes of a workgroup's candidates beside the node totals)
+        G.lanes = G.qmax >= 1 && G.qmax <= 12 && G.pmax <= 16 &&
                   (c->lanes_mode > 0 || (c->lanes_mode < 0 && large_group(c, G)));
         for (size_t m = 0; m < G.members.size(); ++m) {
             Instance& I = c->inst[G.members[m]];

@@ -1323,14 +1323,20 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
 // quantity is computed by the same expressions as in k2_instance, sums over
 // the modes and the projection's sums over the nodes in the same order, and
 // the node maxima are exact, so the results are the same bit for bit.  The
-// exact edge rates of a collision wait in LDS (a column per lane) between the
-// pass that takes their maximum and the pass that selects the mechanisms.
+// exact rates of an iteration (the 17 exponentials of every node's edge
+// integral dominate the kernel) are evaluated as (candidate, node) pairs dealt
+// out over the whole wave, a pair per lane, from the candidates' modes staged
+// in LDS: the wave evaluates about as many integrals as its candidates need,
+// not Q whenever any lane needs them.  The node totals wait in LDS (a column
+// per lane) for the pass that takes their maximum and selects the mechanisms.
 // The first edge proposal of a collision, shared by all of its nodes, is
 // drawn once and kept.
-// the lanes' edge rates [Q][kBlock] in the layout of k2_lds: as many of its
-// per-group scratch blocks (2 Q + 2 PMAX values each) as they take
+// LDS of the lanes: the node totals [Q][kBlock], the coefficients of the
+// candidates whose exact rates are evaluated [kBlock][2 PMAX] and the lanes of
+// those candidates [kBlock], in the layout of k2_lds: as many of its per-group
+// scratch blocks (2 Q + 2 PMAX values each) as they take
 __host__ __device__ constexpr int k2l_groups(int Q, int PM) {
-    return Q * kBlock / (2 * Q + 2 * PM) + 1;
+    return (Q + 2 * PM + 1) * kBlock / (2 * Q + 2 * PM) + 1;
 }
 size_t k2l_lds_bytes(int P, int Q, int fp32) {
     const size_t s = fp32 ? 4 : 8;
@@ -1352,8 +1358,11 @@ __device__ __forceinline__ void k2_lanes_instance(const K2Args<T>& a, unsigned c
     const int P = a.P, Q = a.Q;
     // tables as in k2_instance; the per-group scratch holds the edge rates
     const K2Lds<T> L = k2_lds<T>(smem, PMAX, Q, k2l_groups(Q, PMAX));
-    T* edge = L.scratch;                           // [Q][kBlock]
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    T* tot = L.scratch;                            // [Q][kBlock] node totals of the rates
+    T* wcoef = tot + (size_t)Q * kBlock + (size_t)wave * 64 * 2 * PMAX;   // [64][2 PMAX]
+    int* wslot = reinterpret_cast<int*>(tot + (size_t)Q * kBlock + (size_t)kBlock * 2 * PMAX) +
+                 wave * 64;                        // [64]
     const T dt = (T)a.dyn->dt;
     const double vfdt = a.dyn->vfdt;
     const uint32_t* h_read = a.H + (size_t)(step % 3u) * a.hstride;
@@ -1395,10 +1404,12 @@ __device__ __forceinline__ void k2_lanes_instance(const K2Args<T>& a, unsigned c
         T tc = (T)0;
         uint32_t coll = 0;
         const uint32_t ctr0 = (uint32_t)i;
-        // one collision iteration of this lane's candidate; false ends it
-        auto iterate = [&]() -> bool {
-            // node values, phonon rates and a bound of Gamma~ (the edge
-            // integral is at most 2 pi), as in k2_instance
+        // The first part of a collision iteration of this lane's candidate:
+        // node values, phonon rates and a bound of Gamma~ (the edge integral
+        // is at most 2 pi), as in k2_instance, and the free flight under the
+        // bound.  True if the flight may end inside the step (the exact rates
+        // are needed); lxi = -log(xi).
+        auto bound_test = [&](T& lxi) -> bool {
             T sb = (T)0;
             for (int q = 0; q < Q; ++q) {
                 T kx, ky;
@@ -1415,22 +1426,16 @@ __device__ __forceinline__ void k2_lanes_instance(const K2Args<T>& a, unsigned c
             }
             const Words wx = k2_draw<T>(ctr0, step, (coll << 8) | kPurXi, a.instance, a.seed_lo,
                                         a.seed_hi);
-            const T lxi = -dlog(uni<T>(wx.w0, wx.w1));
-            if (!(tc + lxi / (c.alpha1 * sb * ((T)1 + (T)16 * Num<T>::eps)) < dt)) return false;
-            // exact rates: the edge integral of every node
+            lxi = -dlog(uni<T>(wx.w0, wx.w1));
+            return tc + lxi / (c.alpha1 * sb * ((T)1 + (T)16 * Num<T>::eps)) < dt;
+        };
+        // The rest of the iteration, after the exact node totals are in tot:
+        // the exact free flight and, if it ends inside the step, the collision
+        // and projection.  False ends the candidate.
+        auto collide = [&](T lxi) -> bool {
             T smax = (T)0;
             for (int q = 0; q < Q; ++q) {
-                T kx, ky;
-                eval_node<T, PMAX>(L.psi + q * PMAX, cx, cy, kx, ky);
-                const T ne = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
-                T r[5];
-                phonon_rates<T>(c, ne, L.eps0[q], r);
-                T run = (T)0;
-#pragma unroll
-                for (int m = 0; m < 5; ++m) run += r[m];
-                const T e = edge_rate<T>(c, L.ecos, L.cedge[q], L.eps0[q], kx, ky, ne);
-                edge[q * kBlock + tid] = e;
-                run = run + e;
+                const T run = tot[q * kBlock + tid];
                 smax = run > smax ? run : smax;
             }
             const T Gt = c.alpha1 * smax;
@@ -1466,7 +1471,7 @@ __device__ __forceinline__ void k2_lanes_instance(const K2Args<T>& a, unsigned c
                 T run = (T)0;
 #pragma unroll
                 for (int m = 0; m < 5; ++m) { run += r[m]; cum[m] = run; }
-                cum[5] = cum[4] + edge[q * kBlock + tid];
+                cum[5] = tot[q * kBlock + tid];   // cum[4] + the edge rate, as summed above
                 int ell = 7;
 #pragma unroll
                 for (int m = 5; m >= 0; --m)
@@ -1546,8 +1551,53 @@ __device__ __forceinline__ void k2_lanes_instance(const K2Args<T>& a, unsigned c
             if (coll >= (uint32_t)c.c_max) { ++n_cmax; return false; }
             return true;
         };
-        while (__ballot(live))
-            if (live) live = iterate();
+        while (__ballot(live)) {
+            T lxi = (T)0;
+            bool exact = false;
+            if (live) {
+                exact = bound_test(lxi);
+                live = exact;
+            }
+            // exact rates, the edge integral of every node: the (candidate,
+            // node) pairs of the lanes that need them are dealt out over the
+            // whole wave, a pair per lane, so the wave evaluates about as many
+            // integrals as are needed rather than Q whenever one lane needs any
+            const uint64_t need = __ballot(exact);
+            if (!need) continue;
+            if (exact) {
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+                wslot[rank] = lane;
+#pragma unroll
+                for (int h = 0; h < PMAX; ++h) {
+                    wcoef[lane * 2 * PMAX + h] = cx[h];
+                    wcoef[lane * 2 * PMAX + PMAX + h] = cy[h];
+                }
+            }
+            wave_lds_fence();
+            const uint32_t items = (uint32_t)__popcll(need) * (uint32_t)Q;
+            for (uint32_t t = (uint32_t)lane; t < items; t += 64) {
+                const uint32_t o = t / (uint32_t)Q;
+                const int q = (int)(t - o * (uint32_t)Q);
+                const int own = wslot[o];
+                const T* oc = wcoef + own * 2 * PMAX;
+                const T* row = L.psi + q * PMAX;
+                // the node value as eval_node forms it from the owner's modes
+                T kx = (T)0, ky = (T)0;
+#pragma unroll
+                for (int h = 0; h < PMAX; ++h) { kx += oc[h] * row[h]; ky += oc[PMAX + h] * row[h]; }
+                const T ne = sqrt(kx * kx + ky * ky + L.eps0sq[q]);
+                T r[5];
+                phonon_rates<T>(c, ne, L.eps0[q], r);
+                T run = (T)0;
+#pragma unroll
+                for (int m = 0; m < 5; ++m) run += r[m];
+                const T e = edge_rate<T>(c, L.ecos, L.cedge[q], L.eps0[q], kx, ky, ne);
+                tot[q * kBlock + wave * 64 + own] = run + e;
+            }
+            wave_lds_fence();
+            if (exact) live = collide(lxi);
+        }
         if (cid < total) {
 #pragma unroll
             for (int h = 0; h < PMAX; ++h)
@@ -1582,8 +1632,6 @@ __device__ __forceinline__ void k2_body(const K2Args<T>* __restrict__ all, int n
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     constexpr int kPer = (SGPM_MAX_INSTANCES + kBlock - 1) / kBlock;   // instances per thread
     __shared__ uint32_t s_base[SGPM_MAX_INSTANCES + 1];   // first global pass of instance j
-    __shared__ uint32_t s_step[SGPM_MAX_INSTANCES];
-    __shared__ uint32_t s_total[SGPM_MAX_INSTANCES];
     __shared__ uint32_t s_scan[kBlock];
     __shared__ uint32_t s_list[SGPM_MAX_INSTANCES];   // instances holding a pass of this workgroup
     __shared__ uint32_t s_nlist;
@@ -1614,8 +1662,6 @@ __device__ __forceinline__ void k2_body(const K2Args<T>* __restrict__ all, int n
             const uint32_t total = ((CA*)all)[j].qc[2 * (step & 1u)];
             const uint32_t per_pass = (uint32_t)(kBlock / ((CA*)all)[j].G);
             passes = (total + per_pass - 1) / per_pass;
-            s_step[j] = step;
-            s_total[j] = total;
             if (blockIdx.x == 0) dyn->step_k3 = step + 1u;   // the finalize kernel is done
         }
         loc[u] = passes;
@@ -1662,7 +1708,10 @@ __device__ __forceinline__ void k2_body(const K2Args<T>* __restrict__ all, int n
         const int j = (int)s_list[t];
         const uint32_t r = (blockIdx.x + grid - s_base[j] % grid) % grid;
         const K2Args<T> a = load_desc(all, j);
-        k2_run<T, PMAX, NPL, LANES>(a, smem, s_step[j], s_total[j], r, grid);
+        // the step and list length read again (neither changes while the
+        // collider runs), which keeps the static LDS small
+        const uint32_t step = a.dyn->step_k2;
+        k2_run<T, PMAX, NPL, LANES>(a, smem, step, a.qc[2 * (step & 1u)], r, grid);
     }
 }
 
@@ -1687,9 +1736,12 @@ __global__ void __launch_bounds__(kBlock) k2_collide_wide(const K2Args<T>* __res
     k2_body<T, PMAX, NPL>(all, n_inst);
 }
 
-// a lane per candidate (at most 12 nodes)
+// a lane per candidate (at most 12 nodes).  Held to two waves per SIMD: the
+// FP64 forms otherwise take a few registers past 256 and run one wave per SIMD,
+// a third slower; three waves would spill hundreds of bytes per lane.
 template <typename T, int PMAX>
-__global__ void __launch_bounds__(kBlock) k2_lanes(const K2Args<T>* __restrict__ all, int n_inst) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+k2_lanes(const K2Args<T>* __restrict__ all, int n_inst) {
     k2_body<T, PMAX, 1, true>(all, n_inst);
 }
 

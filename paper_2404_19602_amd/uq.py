@@ -13,8 +13,15 @@ the particles are stepped by the library's kernels.
   numbers (the collisional tree is replayed).
 * ``percentile_bands``: bands over z of the mean energy and velocity from the
   particle expansion evaluated at sampled z (Sec. 5 Test 2, Sec. 4.2).
+* ``error_versus_cost``: the error of E_z[V_x](t) of the sG-PM (MC-sG) for
+  truncation orders M1 and of MC-MC for sample counts M2, both at N particles,
+  against a reference sG-PM run with many particles and a high order, beside
+  the cost per particle of each (M1^2 and M2 by the paper's cost model, and
+  the measured device time per step) (Sec. 5 Test 4).
 """
 from __future__ import annotations
+
+import time
 
 import numpy as np
 
@@ -119,4 +126,94 @@ def percentile_bands(sim: Simulation, percentiles=(10.0, 90.0), n_z: int = 256, 
         out[k + "_mean"] = float(np.mean(m[k]))
         out[k + "_bands"] = np.percentile(m[k], percentiles)
     out["percentiles"] = tuple(percentiles)
+    return out
+
+
+def _timed_steps(sim: Simulation, steps: int, dt: float) -> float:
+    """Steps the simulation and returns the wall time per step in ms (the
+    stream is synchronised before and after)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps, dt)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+
+
+def error_versus_cost(cfg: dict, n: int, steps: int, sg_orders, mc_samples, n_ref: int,
+                      m_ref: int, nodes_for=lambda m: m + 3, seed: int = 7,
+                      dt: float | None = None) -> dict:
+    """Sec. 5 Test 4 for one uncertain input: Error = |E_z[V_x](t) -
+    E_z[V_x^ref](t)| at t = steps dt.
+
+    * Reference: the sG-PM of order m_ref with n_ref particles.
+    * MC-sG: the sG-PM of each order M1 in sg_orders with n particles (every
+      order in one context, on the same random streams); cost per particle
+      M1^2.
+    * MC-MC: max(mc_samples) deterministic runs of n particles at z drawn
+      uniformly (one batched context); the estimate of M2 samples is the mean
+      of the first M2 runs; cost per particle M2.
+
+    Besides the errors: the Monte Carlo standard errors of the estimates (the
+    reference's and the MC-sG's from their batch means; MC-MC's from the
+    spread over its samples), and the measured device time per step of each
+    run.  The reference and the MC-sG runs use different random streams
+    (instance words 1 and 0)."""
+    if int(cfg.get("dim_z", 0)) != 1:
+        raise ValueError("error_versus_cost takes workloads with one uncertain input")
+    dt = cfg.get("dt", 2e-15) if dt is None else dt
+    sg_orders = [int(m) for m in sg_orders]
+    mc_samples = sorted(int(m) for m in mc_samples)
+    out = {"steps": steps, "t_s": steps * dt, "n": n, "n_ref": n_ref, "m_ref": m_ref}
+
+    ref = Simulation(dict(cfg, degree=m_ref, nodes_1d=nodes_for(m_ref), n_particles=n_ref,
+                          instance=1), max_steps=steps)
+    ref.init_particles()
+    out["ref_ms_per_step"] = _timed_steps(ref, steps, dt)
+    m = ref.moments(steps, 1)
+    e_ref, se_ref = float(m["E_vx"][0]), float(m["SE_E_vx"][0])
+    out["ref_E_vx"], out["ref_SE"] = e_ref, se_ref
+    del ref
+
+    cfgs = [dict(cfg, degree=m1, nodes_1d=nodes_for(m1), n_particles=n, instance=0)
+            for m1 in sg_orders]
+    sim = Simulation(cfgs, max_steps=steps)
+    sim.init_particles()
+    out["sg_ms_per_step_all_orders"] = _timed_steps(sim, steps, dt)
+    sg = []
+    for k, m1 in enumerate(sg_orders):
+        mk = sim.moments(steps, 1, inst=k)
+        sg.append({"M1": m1, "cost_per_particle": m1 * m1, "E_vx": float(mk["E_vx"][0]),
+                   "SE": float(mk["SE_E_vx"][0]),
+                   "error": abs(float(mk["E_vx"][0]) - e_ref)})
+    del sim
+    # per-order device time: each order alone
+    for row in sg:
+        one = Simulation(dict(cfg, degree=row["M1"], nodes_1d=nodes_for(row["M1"]),
+                              n_particles=n, instance=0), max_steps=steps)
+        one.init_particles()
+        row["ms_per_step"] = _timed_steps(one, steps, dt)
+        del one
+    out["mc_sg"] = sg
+
+    z = sample_z(max(mc_samples), 1, seed)
+    dcfgs = deterministic_at(cfg, z)
+    for k, c in enumerate(dcfgs):
+        c.update(instance=k, n_particles=n)
+    det = Simulation(dcfgs, max_steps=steps)
+    det.init_particles()
+    out["mc_ms_per_step_all_samples"] = _timed_steps(det, steps, dt)
+    vx = np.array([float(det.moments(steps, 1, inst=k)["E_vx"][0]) for k in range(len(dcfgs))])
+    se_part = np.array([float(det.moments(steps, 1, inst=k)["SE_E_vx"][0])
+                        for k in range(len(dcfgs))])
+    del det
+    mc = []
+    for m2 in mc_samples:
+        est = float(vx[:m2].mean())
+        spread = float(vx[:m2].std(ddof=1) / np.sqrt(m2)) if m2 > 1 else float("nan")
+        mc.append({"M2": m2, "cost_per_particle": m2, "E_vx": est, "error": abs(est - e_ref),
+                   "SE_particles": float(np.sqrt(np.sum(se_part[:m2] ** 2)) / m2),
+                   "SE_samples": spread})
+    out["mc_mc"] = mc
+    out["std_z_vx_samples"] = float(vx.std(ddof=1)) if len(vx) > 1 else float("nan")
     return out

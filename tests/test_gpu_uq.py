@@ -87,3 +87,58 @@ def test_percentile_bands(uq):
     b = uq.percentile_bands(flat, n_z=32)
     lo, hi = b["energy_bands"]
     assert hi - lo <= 1e-10 * abs(b["energy_mean"])
+
+
+def test_error_versus_cost(uq):
+    """Sec. 5 Test 4 at reduced size (uncertain width of Test 3, N = 2e4,
+    0.25 ps, reference M = 12 with 4e5 particles): every estimate of
+    E_z[V_x] is consistent with the reference within its Monte Carlo error
+    (particle noise of both runs, plus for MC-MC the sampling error over z),
+    and the cost columns follow the paper's cost model (M1^2, M2)."""
+    from test_gpu_accuracy import _test3_cfg
+    cfg = _test3_cfg("width", 20_000)
+    print("\n[gpu case] Test 4 error vs cost, N = 2e4, reference 4e5 particles M = 12", flush=True)
+    r = uq.error_versus_cost(cfg, n=20_000, steps=100, sg_orders=[0, 1, 2, 4, 6],
+                             mc_samples=[1, 2, 4, 8, 16, 32], n_ref=400_000, m_ref=12)
+    se_ref = r["ref_SE"]
+    for row in r["mc_sg"]:
+        print(f"  MC-sG M1={row['M1']}: cost {row['cost_per_particle']}, error {row['error']:.3e}, "
+              f"SE {row['SE']:.2e}, {row['ms_per_step']:.3f} ms/step", flush=True)
+        assert row["cost_per_particle"] == row["M1"] ** 2
+        if row["M1"] >= 4:
+            assert row["error"] < 4.0 * np.hypot(row["SE"], se_ref), row
+    var_z = r["std_z_vx_samples"] ** 2
+    for row in r["mc_mc"]:
+        print(f"  MC-MC M2={row['M2']}: error {row['error']:.3e}, SE(z) {row['SE_samples']:.2e}",
+              flush=True)
+        assert row["cost_per_particle"] == row["M2"]
+        bound = 4.0 * np.sqrt(var_z / row["M2"] + row["SE_particles"] ** 2 + se_ref ** 2)
+        assert row["error"] < bound, row
+    assert r["ref_ms_per_step"] > 0 and r["mc_ms_per_step_all_samples"] > 0
+
+
+def test_percentile_bands_match_oracle(uq):
+    """The bands of a GPU run equal the same percentiles of the oracle's
+    particle expansion evaluated at the same z after the same steps (a run
+    whose trajectories agree with the oracle's to rounding)."""
+    import oracle
+    import paper_2404_19602_amd as sg
+    cfg = gap_cfg(n_particles=3_000)
+    steps = 20
+    print("\n[gpu case] percentile bands vs oracle, N = 3000, 20 steps", flush=True)
+    sim = sg.Simulation(cfg, max_steps=steps)
+    sim.init_particles()
+    sim.step(steps)
+    pct = (10.0, 50.0, 80.0, 90.0)
+    b = uq.percentile_bands(sim, percentiles=pct, n_z=64)
+    ref = oracle.OracleSim(cfg, threads=8)
+    ref.init()
+    ref.run(cfg["dt"], steps)
+    m = ref.moments_at(b["z"][:, 0])
+    for k in ("energy", "V_x"):
+        want = np.percentile(m[k], pct)
+        scale = np.max(np.abs(m[k]))
+        err = np.max(np.abs(b[k + "_bands"] - want)) / scale
+        print(f"  {k}: bands {b[k + '_bands']}, oracle {want}, max rel err {err:.1e}", flush=True)
+        assert err < 1e-9, k
+        assert abs(b[k + "_mean"] - float(np.mean(m[k]))) < 1e-9 * scale
