@@ -498,6 +498,44 @@ def sweep_forms(steps: int, warmup: int = 10) -> dict:
     return res
 
 
+def late_window(cfg: dict, after: int = 1000, steps: int = 100) -> dict:
+    """The headline later in a run: `after` steps from the initial datum (the
+    distribution heats under the field and the candidate count grows), then
+    `steps` graph-replayed steps timed on the wall clock and, again from the
+    same state, with a HIP event around every launch."""
+    import torch
+    import paper_2404_19602_amd as sg
+    log(f"late window: {after} steps, then {steps} timed + {steps} profiled steps")
+    sim = sg.Simulation(cfg, max_steps=after + 2 * steps)
+    sim.init_particles()
+    sim.step(after, cfg["dt"])
+    s0 = sim.step_count
+    kx, ky = sim.get_state()
+    c0 = sim.counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps, cfg["dt"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    c1 = sim.counters()
+    sim.set_state(kx, ky, step=s0)
+    del kx, ky
+    sim.set_profiling(True)
+    sim.step(steps, cfg["dt"])
+    kt = sim.kernel_times()
+    sim.set_profiling(False)
+    P, Q = sim.P, sim.Q
+    out = {"after_steps": after, "t_ps": after * cfg["dt"] * 1e12, "steps": steps,
+           "ms_per_step": wall * 1e3 / steps,
+           "value": cfg["n_particles"] * Q * steps / wall,
+           "kernels_us": {k: round(v[0] * 1e3, 1) for k, v in kt.items()},
+           "candidates_per_step": (c1["candidates"] - c0["candidates"]) / steps,
+           "collisions_per_step": (c1["collisions"] - c0["collisions"]) / steps}
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def secondary_line(steps: int, warmup: int) -> dict:
     """The 8-node workload (1e6 particles, M = 5) in FP64: per-step rate and
     the rooflines of its dominant kernel and of its whole step."""
@@ -526,6 +564,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32 comparison run")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance sweep")
     ap.add_argument("--batched-steps", type=int, default=100)
+    ap.add_argument("--late-steps", type=int, default=1000,
+                    help="steps before the headline's late window (0: skip it)")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the 8-node, 1e6-particle FP64 line")
     ap.add_argument("--no-uq", action="store_true", help="skip the MC-MC / moments-at-z timings")
@@ -553,6 +593,7 @@ def main():
     if args.headline_only:
         args.no_cpu = args.no_fp32 = args.no_batched = args.no_secondary = True
         args.no_uq = args.no_configs = True
+        args.late_steps = 0
 
     from workloads import workload
 
@@ -603,6 +644,9 @@ def main():
     del r64
     import torch
     torch.cuda.empty_cache()
+
+    if args.late_steps > 0:
+        out["late"] = late_window(cfg, after=args.late_steps)
 
     if not args.no_fp32:
         log("FP32 run of the same steps")

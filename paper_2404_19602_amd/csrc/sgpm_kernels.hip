@@ -538,8 +538,10 @@ k1_stream(const K1Args<T>* __restrict__ all,
                                     acc[q][0] += kx * rs;
                                     acc[q][1] += ky * rs;
                                 } else {
-                                    // FP32 products, summed exactly in FP64: the sums
-                                    // do not depend on how the particles are chunked
+                                    // FP32 products summed in FP64: deterministic for
+                                    // a fixed launch shape; exact (and then independent
+                                    // of the chunking) only while the addends and the
+                                    // running sum span at most 53 bits of exponent
                                     acc[q][0] += (double)(c.v_f * kx * rs);
                                     acc[q][1] += (double)(c.v_f * ky * rs);
                                 }
@@ -1052,20 +1054,44 @@ __device__ __forceinline__ K2Lds<T> k2_lds(unsigned char* smem, int PM, int Q, i
     return L;
 }
 
-// Pauli occupation f = H^n / max H^n of node q at the candidate's cell on the
-// grid moved with this step's drift (lookup at k' + v_F E(z_q) dt x^)
+// Comparisons with a rounded quotient c / g (c >= 0, g > 0, s > 0) decided by
+// the product s g against c where that is safe: a product outside c (1 -+ 2 eps)
+// (four units of rounding) lies on the same side of c as the exact s g, and the
+// rounded quotient lies within one unit of the exact one, so the comparison with
+// the rounded quotient comes out the same.  Inside the margin (rare) the
+// quotient is formed.  A division costs about a dozen dependent instructions.
 template <typename T>
-__device__ __forceinline__ T pauli_f(const uint32_t* __restrict__ h_read,
-                                     const uint32_t* __restrict__ hmax_read, const K2Lds<T>& L,
-                                     const Consts<T>& c, int q, T px, T py, T dt) {
+__device__ __forceinline__ bool lt_quot(T s, T c, T g) {   // s < c / g
+    const T p = s * g;
+    if (p < c * ((T)1 - (T)2 * Num<T>::eps)) return true;
+    if (p > c * ((T)1 + (T)2 * Num<T>::eps)) return false;
+    return s < c / g;
+}
+template <typename T>
+__device__ __forceinline__ bool quot_lt(T c, T g, T s) {   // c / g < s
+    const T p = s * g;
+    if (p > c * ((T)1 + (T)2 * Num<T>::eps)) return true;
+    if (p < c * ((T)1 - (T)2 * Num<T>::eps)) return false;
+    return c / g < s;
+}
+
+// Pauli acceptance: is the occupation f = H^n / max H^n of node q at the
+// candidate's cell, on the grid moved with this step's drift (lookup at
+// k' + v_F E(z_q) dt x^), below eta?  f = 0 for an empty histogram and off
+// the grid.
+template <typename T>
+__device__ __forceinline__ bool pauli_accepts(const uint32_t* __restrict__ h_read,
+                                              const uint32_t* __restrict__ hmax_read,
+                                              const K2Lds<T>& L, const Consts<T>& c, int q, T px,
+                                              T py, T dt, T eta) {
     const uint32_t mx = hmax_read[q];
-    if (mx == 0u) return (T)0;
+    if (mx == 0u) return true;
     const T shift = L.vfield[q] * dt;
     const int r = cell_coord<T>(px + shift, c.lk, c.inv_dk);
     const int l = cell_coord<T>(py, c.lk, c.inv_dk);
-    if (r < 0 || l < 0 || r >= c.nk || l >= c.nk) return (T)0;
+    if (r < 0 || l < 0 || r >= c.nk || l >= c.nk) return true;
     const uint32_t h = h_read[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l];
-    return (T)h / (T)mx;
+    return quot_lt<T>((T)h, (T)mx, eta);
 }
 
 
@@ -1217,7 +1243,7 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
                 int ell = 7;
 #pragma unroll
                 for (int m = 5; m >= 0; --m)
-                    if (su < cum[j][m] / Gt) ell = m + 1;
+                    if (lt_quot<T>(su, cum[j][m], Gt)) ell = m + 1;
                 T nx = kx, ny = ky;
                 if (ell != 7) {
                     const T kabs = sqrt(kx * kx + ky * ky);
@@ -1263,9 +1289,12 @@ __device__ __forceinline__ void k2_instance(const K2Args<T>& a, unsigned char* s
                     }
                     if (ok) {
                         ++nev;
-                        const T f = c.pauli ? pauli_f<T>(h_read, hmax_read, L, c, q, px, py, dt_grid)
-                                            : (T)0;
-                        if (f < eta) { nx = px; ny = py; } else { ++nrej; }
+                        if (!c.pauli ||
+                            pauli_accepts<T>(h_read, hmax_read, L, c, q, px, py, dt_grid, eta)) {
+                            nx = px; ny = py;
+                        } else {
+                            ++nrej;
+                        }
                     }
                 }
                 nodes[q] = nx;
@@ -1475,7 +1504,7 @@ __device__ __forceinline__ void k2_lanes_instance(const K2Args<T>& a, unsigned c
                 int ell = 7;
 #pragma unroll
                 for (int m = 5; m >= 0; --m)
-                    if (su < cum[m] / Gt) ell = m + 1;
+                    if (lt_quot<T>(su, cum[m], Gt)) ell = m + 1;
                 T nx = kx, ny = ky;
                 if (ell != 7) {
                     const T kabs = sqrt(kx * kx + ky * ky);
@@ -1529,9 +1558,12 @@ __device__ __forceinline__ void k2_lanes_instance(const K2Args<T>& a, unsigned c
                     }
                     if (ok) {
                         ++n_ev;
-                        const T f = c.pauli ? pauli_f<T>(h_read, hmax_read, L, c, q, px, py, dt_grid)
-                                            : (T)0;
-                        if (f < eta) { nx = px; ny = py; } else { ++n_rej; }
+                        if (!c.pauli ||
+                            pauli_accepts<T>(h_read, hmax_read, L, c, q, px, py, dt_grid, eta)) {
+                            nx = px; ny = py;
+                        } else {
+                            ++n_rej;
+                        }
                     }
                 }
                 // k_h = sum_q w_q Psi_h(z_q) k_q, summed over the nodes in order
