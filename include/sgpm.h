@@ -202,6 +202,17 @@ sgpm_status sgpm_node_pairs(const sgpm_ctx* ctx, int32_t inst, int32_t* paired);
  * candidate, 0 if a group of lanes per candidate. */
 sgpm_status sgpm_collider_lanes(const sgpm_ctx* ctx, int32_t inst, int32_t* lanes);
 
+/* Threads per workgroup of the mirror-pair stream kernel: alt = 0 the default
+ * form of each instantiation (1024, 768 or 512 threads, by the registers it
+ * needs), 1 the other one (512 for a default of 768, else 768); sgpm_autotune
+ * tries both and keeps the faster.  The state, histograms and counters are the
+ * same in both; the FP64 moment sums group the particles by lane differently
+ * (they agree to rounding).  Allowed at any time after sgpm_create. */
+sgpm_status sgpm_set_pair_block(sgpm_ctx* ctx, int32_t alt);
+
+/* *threads = threads per workgroup of the stream kernel of instance inst. */
+sgpm_status sgpm_stream_threads(const sgpm_ctx* ctx, int32_t inst, int32_t* threads);
+
 /* Launch mode of sgpm_step: 0 = every kernel launched on the stream; B >= 1
  * = blocks of B steps captured once as a HIP graph (on a private stream) and
  * replayed on the context's stream, remainders from a graph of their own
@@ -324,6 +335,9 @@ sgpm_status sgpm_set_chunk(sgpm_ctx* ctx, int32_t inst, int32_t chunk);
  * (within the limits of sgpm_set_chunk), times 512, 1024 or 2048 collider
  * workgroups.  A grid other than 1024 must be more than 3 % faster, and so
  * must chunks other than the automatic ones (the two margins multiply).
+ * Then, if some instance is stepped by the mirror-pair stream kernel, the
+ * other workgroup size of that kernel (sgpm_set_pair_block) at the best
+ * shape, kept if it is more than 3 % faster.
  * Between trials and at the end it puts back the particle state, the step
  * counter and the counters, and rebuilds the histogram.
  * Keeps the fastest shape (results do not depend on it; see sgpm_set_chunk)

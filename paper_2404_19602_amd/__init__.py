@@ -128,6 +128,16 @@ class Simulation:
         check(lib().sgpm_node_pairs(self._ctx, inst, C.byref(v)), self._ctx, "node_pairs")
         return bool(v.value)
 
+    def set_pair_block(self, alt: int):
+        """0: the default workgroup size of the mirror-pair stream kernel; 1:
+        the other one (the autotuner tries both)."""
+        check(lib().sgpm_set_pair_block(self._ctx, int(alt)), self._ctx, "set_pair_block")
+
+    def stream_threads(self, inst: int = 0) -> int:
+        v = C.c_int32(0)
+        check(lib().sgpm_stream_threads(self._ctx, inst, C.byref(v)), self._ctx, "stream_threads")
+        return int(v.value)
+
     def collider_lanes(self, inst: int = 0) -> bool:
         v = C.c_int32(0)
         check(lib().sgpm_collider_lanes(self._ctx, inst, C.byref(v)), self._ctx, "collider_lanes")

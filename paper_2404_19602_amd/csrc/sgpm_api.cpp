@@ -194,7 +194,10 @@ bool pair_capable(const HostTables& t) {
 // flushes its whole window).
 void window_for(int P, int Q, int nk, double lk_eV, bool fp32, bool paired, int64_t chunk,
                 int budget, int* win, int* r0, int* l0, int* words) {
-    const size_t fixed = k1_lds_bytes(P, Q, fp32 ? 1 : 0, paired ? 1 : 0, 0, chunk) + 64;
+    // the larger fixed part of the two workgroup sizes, so the window fits either
+    const size_t fixed = std::max(k1_lds_bytes(P, Q, fp32 ? 1 : 0, paired ? 1 : 0, 0, chunk, 0),
+                                  k1_lds_bytes(P, Q, fp32 ? 1 : 0, paired ? 1 : 0, 0, chunk, 1)) +
+                         64;
     const double room = fixed < (size_t)budget ? (double)(budget - fixed) : 0.0;
     // node q counts in half (q & 1) of word (q >> 1) w^2 + r w + l: ceil(Q/2) planes of w^2 words
     const int planes = (Q + 1) / 2;
@@ -305,6 +308,9 @@ struct sgpm_ctx {
     // particles or more
     int pairs_mode = -1;
     int lanes_mode = -1;
+    // threads per workgroup of the mirror-pair stream kernel: 0 the default
+    // form of each instantiation, 1 the other one (k1p_block)
+    int k1_alt = 0;
     Prof prof;
 };
 
@@ -533,7 +539,7 @@ sgpm_status upload_args(sgpm_ctx* c) {
             t1[m + 1] = t1[m] + (uint32_t)I.nwg;
             t3[m + 1] = t3[m] + (uint32_t)k3_grid(I);
             G.k1_lds = std::max(G.k1_lds, k1_lds_bytes(I.P, I.Q, I.fp32, I.paired, I.hwin_words,
-                                                       I.chunk));
+                                                       I.chunk, c->k1_alt));
             G.k2_lds = std::max(G.k2_lds, G.lanes ? k2l_lds_bytes(I.P, I.Q, I.fp32)
                                                   : k2_lds_bytes(I.P, I.Q, I.fp32));
             if (I.Q > 64) G.npl = 2;
@@ -594,7 +600,7 @@ sgpm_status enqueue_step(sgpm_ctx* c, hipStream_t s, bool prof) {
         const Group& G = c->groups[g];
         const int m = (int)G.members.size(), off = G.pos0 + (int)g;
         int e = launch_k1(G.fp32, G.pmax, G.qmax, G.paired, k1_args(c, G.fp32, G.pos0),
-                          wg_table(c, kTabK1, off), m, 1, G.k1_grid, G.k1_lds, s);
+                          wg_table(c, kTabK1, off), m, 1, G.k1_grid, G.k1_lds, s, c->k1_alt);
         if (e) return dev_fail(c, (hipError_t)e, "stream kernel launch");
         if (prof) { sgpm_status r = prof_mark(c, s, SGPM_KERNEL_STREAM); if (r) return r; }
         e = launch_k3(c->k3 + G.pos0, wg_table(c, kTabK3, off), m, 1, G.k3_grid, s);
@@ -614,7 +620,7 @@ sgpm_status enqueue_state_pass(sgpm_ctx* c, hipStream_t s) {
         const Group& G = c->groups[g];
         const int m = (int)G.members.size(), off = G.pos0 + (int)g;
         int e = launch_k1(G.fp32, G.pmax, G.qmax, G.paired, k1_args(c, G.fp32, G.pos0),
-                          wg_table(c, kTabK1, off), m, 0, G.k1_grid, G.k1_lds, s);
+                          wg_table(c, kTabK1, off), m, 0, G.k1_grid, G.k1_lds, s, c->k1_alt);
         if (!e) e = launch_k3(c->k3 + G.pos0, wg_table(c, kTabK3, off), m, 0, G.k3_grid, s);
         if (e) return dev_fail(c, (hipError_t)e, "state pass launch");
     }
@@ -626,8 +632,8 @@ sgpm_status state_pass_one(sgpm_ctx* c, const Instance& I) {
     const Group& G = c->groups[I.grp];
     int e = launch_k1(I.fp32, G.pmax, G.qmax, G.paired, k1_args(c, I.fp32, I.pos),
                       wg_table(c, kTabK1One, 2 * I.pos), 1, 0, (unsigned)I.nwg,
-                      k1_lds_bytes(I.P, I.Q, I.fp32, I.paired, I.hwin_words, I.chunk),
-                      c->stream);
+                      k1_lds_bytes(I.P, I.Q, I.fp32, I.paired, I.hwin_words, I.chunk, c->k1_alt),
+                      c->stream, c->k1_alt);
     if (!e)
         e = launch_k3(c->k3 + I.pos, wg_table(c, kTabK3One, 2 * I.pos), 1, 0,
                       (unsigned)k3_grid(I), c->stream);
@@ -1089,6 +1095,23 @@ sgpm_status sgpm_node_pairs(const sgpm_ctx* c, int32_t inst, int32_t* paired) {
     return SGPM_OK;
 }
 
+sgpm_status sgpm_set_pair_block(sgpm_ctx* c, int32_t alt) {
+    if (!c) return SGPM_EINVAL;
+    if (c->poisoned) return fail(c, SGPM_ESTATE, "context poisoned");
+    if (alt != 0 && alt != 1) return fail(c, SGPM_EINVAL, "alt must be 0 or 1");
+    c->k1_alt = alt;
+    return upload_args(c);
+}
+
+sgpm_status sgpm_stream_threads(const sgpm_ctx* c, int32_t inst, int32_t* threads) {
+    if (!c || inst < 0 || inst >= (int32_t)c->inst.size() || !threads) return SGPM_EINVAL;
+    const Instance& I = c->inst[inst];
+    const Group& G = c->groups[I.grp];
+    *threads = G.paired ? k1p_block(G.fp32, G.pmax, G.qmax, c->k1_alt)
+                        : 64 * k1_waves(G.fp32 != 0, G.pmax, G.qmax);
+    return SGPM_OK;
+}
+
 sgpm_status sgpm_collider_lanes(const sgpm_ctx* c, int32_t inst, int32_t* lanes) {
     if (!c || inst < 0 || inst >= (int32_t)c->inst.size() || !lanes) return SGPM_EINVAL;
     *lanes = c->groups[c->inst[inst].grp].lanes ? 1 : 0;
@@ -1188,6 +1211,24 @@ sgpm_status sgpm_autotune(sgpm_ctx* c, double dt, int32_t trial_steps, double* b
             if (score < best_score) { best_score = score; best = ms; best_f = f; best_g = g; }
         }
         if (st) break;
+    }
+    // the other workgroup size of the mirror-pair stream kernel, at the best
+    // chunk and grid, kept only if it wins by more than 3 %
+    bool any_paired = false;
+    for (const Group& G : c->groups) any_paired = any_paired || G.paired;
+    if (!st && any_paired) {
+        const int cur = c->k1_alt;
+        for (Instance& I : c->inst) set_chunk(I, scaled_chunk(I, best_f));
+        c->k2_grid = best_g;
+        c->k1_alt = 1 - cur;
+        st = upload_args(c);
+        for (size_t k = 0; k < c->inst.size() && !st; ++k)
+            st = restore_instance(c, c->inst[k], saved[k], !room);
+        if (!st) st = sgpm_step(c, dt, trial_steps);
+        double ms = 0.0;
+        if (!st) st = sgpm_last_step_ms(c, &ms);
+        if (!st && ms * 1.03 < best) best = ms;
+        else c->k1_alt = cur;
     }
     c->profiling = prof;
     c->graph_steps = graph_steps;

@@ -101,8 +101,8 @@ constexpr int k1_waves(bool fp32, int pmax, int qmax) {
 }
 // Threads per workgroup of the stream kernel with mirror node pairs for a
 // precision and bucket (1024, 768 or 512: four, three or two waves per SIMD,
-// one workgroup per compute unit).
-int k1p_block(int fp32, int pmax, int qmax);
+// one workgroup per compute unit); alt: the other form the autotuner may pick.
+int k1p_block(int fp32, int pmax, int qmax, int alt);
 constexpr int kLdsPairBudget = 150 * 1024;   // LDS bytes of a mirror-pair stream workgroup
 constexpr int64_t kMaxPairChunk = (int64_t)1 << 24;   // its largest chunk
 // Mode and node buckets the mirror-pair stream kernel is built for.
@@ -256,7 +256,7 @@ struct MomAtArgs {
 // batched launchers take device arrays of descriptors of n_inst instances of
 // one shape group and wg0[n_inst + 1], the first workgroup of each instance.
 int launch_k1(int fp32, int pmax, int qmax, int paired, const void* args, const uint32_t* wg0,
-              int n_inst, int moving, unsigned grid, size_t lds, void* stream);
+              int n_inst, int moving, unsigned grid, size_t lds, void* stream, int alt);
 int launch_k2(int fp32, int pmax, int npl, int lanes, const void* args, int n_inst,
               unsigned grid, size_t lds, void* stream);
 int launch_k3(const K3Args* args, const uint32_t* wg0, int n_inst, int moving, unsigned grid,
@@ -271,7 +271,8 @@ int launch_moments_at(const MomAtArgs& a, int nwg, void* stream);
 double density_at(double eps0, double mu, double kT);   // electrons per m^2
 int launch_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out, int64_t n,
                   void* stream);
-size_t k1_lds_bytes(int P, int Q, int fp32, int paired, int hwin_words, int64_t chunk);
+size_t k1_lds_bytes(int P, int Q, int fp32, int paired, int hwin_words, int64_t chunk,
+                    int alt);
 size_t k2_lds_bytes(int P, int Q, int fp32);
 size_t k2l_lds_bytes(int P, int Q, int fp32);   // the collider with a lane per candidate
 int k3_grid_of(int Q, int nk, int n_win_wg, int nb);

@@ -347,10 +347,10 @@ __host__ __device__ constexpr size_t k1_fixed_bytes(int PM, int QA, size_t s, in
 
 constexpr int kK1PSeg = 256;      // candidate list entries per wave of the mirror-pair kernel
 
-size_t k1_lds_bytes(int P, int Q, int fp32, int paired, int hwin_words, int64_t chunk) {
+size_t k1_lds_bytes(int P, int Q, int fp32, int paired, int hwin_words, int64_t chunk, int alt) {
     const int PM = pmax_bucket(P), qb = qmax_bucket(Q);
     if (paired) {
-        const int waves = k1p_block(fp32, PM, qb) / 64;
+        const int waves = k1p_block(fp32, PM, qb, alt) / 64;
         return k1_fixed_bytes(PM, qb, fp32 ? 4 : 8, waves) + (size_t)hwin_words * 4 +
                (size_t)waves * kK1PSeg * 4;   // window, candidate lists of the waves
     }
@@ -703,18 +703,24 @@ k1_stream(const K1Args<T>* __restrict__ all,
 // bits of plane (Q-1)/2.  The finalize kernel decodes it by the instance's
 // mirror flag.
 // VGPRs of the kernel, estimated: FP64 moment sums of every node, the
-// coefficients and the temporaries (measured on the compiler's output)
+// coefficients and the temporaries (measured on the compiler's output; at 9
+// modes and 12 nodes FP64 needs 174 and would spill 26 registers at 168)
 __host__ __device__ constexpr int k1p_regs(int fp32, int pmax, int qmax) {
-    return 2 * (3 * qmax + 3) + 2 * pmax * (fp32 ? 1 : 2) + (fp32 ? 44 : 52);
+    return 2 * (3 * qmax + 3) + 2 * pmax * (fp32 ? 1 : 2) + (fp32 ? 44 : 60);
 }
-int k1p_block(int fp32, int pmax, int qmax) {
+// Threads per workgroup of an instantiation: the default, four, three or two
+// waves per SIMD by the estimate, and (alt) the other occupancy the autotuner
+// may pick, 512 for 768 and 768 for the others (where the default would spill
+// or one more wave per SIMD may hide more latency)
+__host__ __device__ constexpr int k1p_block_of(int fp32, int pmax, int qmax, int alt) {
     const int r = k1p_regs(fp32, pmax, qmax);
-    return r <= 128 ? 1024 : (r <= 168 ? 768 : 512);
+    const int b = r <= 128 ? 1024 : (r <= 168 ? 768 : 512);
+    return alt ? (b == 768 ? 512 : 768) : b;
 }
-template <typename T, int PMAX, int QMAX>
+int k1p_block(int fp32, int pmax, int qmax, int alt) { return k1p_block_of(fp32, pmax, qmax, alt); }
+template <typename T, int PMAX, int QMAX, int ALT>
 struct K1PBlock {
-    static constexpr int r = k1p_regs(sizeof(T) == 4, PMAX, QMAX);
-    static constexpr int value = r <= 128 ? 1024 : (r <= 168 ? 768 : 512);
+    static constexpr int value = k1p_block_of(sizeof(T) == 4, PMAX, QMAX, ALT);
 };
 
 // Wave sums of V per-lane values; store(k, s) receives the sum s of v[k] over
@@ -753,12 +759,12 @@ __device__ __forceinline__ void wave_sums_map(const double (&v)[V], int lane, F&
     }
 }
 
-template <typename T, int PMAX, int QMAX>
-__global__ void __launch_bounds__((K1PBlock<T, PMAX, QMAX>::value))
+template <typename T, int PMAX, int QMAX, int ALT>
+__global__ void __launch_bounds__((K1PBlock<T, PMAX, QMAX, ALT>::value))
 k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, int n_inst,
          int moving) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    constexpr int BLOCK = K1PBlock<T, PMAX, QMAX>::value, WAVES = BLOCK / 64;
+    constexpr int BLOCK = K1PBlock<T, PMAX, QMAX, ALT>::value, WAVES = BLOCK / 64;
     constexpr int NP = QMAX / 2;            // pair slots
     __shared__ T s_shmax;
     const int slot = find_slot(wg0, n_inst, blockIdx.x);
@@ -2014,35 +2020,43 @@ static int launch_k1_any(int pmax, int qmax, const void* args, const uint32_t* w
 
 template <typename T, int PMAX, int QMAX>
 static int launch_k1p_t(const void* args, const uint32_t* wg0, int n_inst, int moving,
-                        unsigned grid, size_t lds, void* stream) {
-    hipLaunchKernelGGL((k1_pairs<T, PMAX, QMAX>), dim3(grid), dim3(K1PBlock<T, PMAX, QMAX>::value), lds,
-                       (hipStream_t)stream, static_cast<const K1Args<T>*>(args), wg0, n_inst,
-                       moving);
+                        unsigned grid, size_t lds, void* stream, int alt) {
+    if (alt)
+        hipLaunchKernelGGL((k1_pairs<T, PMAX, QMAX, 1>), dim3(grid),
+                           dim3(K1PBlock<T, PMAX, QMAX, 1>::value), lds, (hipStream_t)stream,
+                           static_cast<const K1Args<T>*>(args), wg0, n_inst, moving);
+    else
+        hipLaunchKernelGGL((k1_pairs<T, PMAX, QMAX, 0>), dim3(grid),
+                           dim3(K1PBlock<T, PMAX, QMAX, 0>::value), lds, (hipStream_t)stream,
+                           static_cast<const K1Args<T>*>(args), wg0, n_inst, moving);
     return (int)hipGetLastError();
 }
 
 template <typename T>
 static int launch_k1p_any(int pmax, int qmax, const void* args, const uint32_t* wg0, int n_inst,
-                          int moving, unsigned grid, size_t lds, void* stream) {
+                          int moving, unsigned grid, size_t lds, void* stream, int alt) {
     const bool q12 = qmax == 12;
     switch (pmax) {
-    case 3: return q12 ? launch_k1p_t<T, 3, 12>(args, wg0, n_inst, moving, grid, lds, stream)
-                       : launch_k1p_t<T, 3, 8>(args, wg0, n_inst, moving, grid, lds, stream);
-    case 6: return q12 ? launch_k1p_t<T, 6, 12>(args, wg0, n_inst, moving, grid, lds, stream)
-                       : launch_k1p_t<T, 6, 8>(args, wg0, n_inst, moving, grid, lds, stream);
-    case 9: return q12 ? launch_k1p_t<T, 9, 12>(args, wg0, n_inst, moving, grid, lds, stream)
-                       : launch_k1p_t<T, 9, 8>(args, wg0, n_inst, moving, grid, lds, stream);
-    default: return q12 ? launch_k1p_t<T, 16, 12>(args, wg0, n_inst, moving, grid, lds, stream)
-                        : launch_k1p_t<T, 16, 8>(args, wg0, n_inst, moving, grid, lds, stream);
+    case 3: return q12 ? launch_k1p_t<T, 3, 12>(args, wg0, n_inst, moving, grid, lds, stream, alt)
+                       : launch_k1p_t<T, 3, 8>(args, wg0, n_inst, moving, grid, lds, stream, alt);
+    case 6: return q12 ? launch_k1p_t<T, 6, 12>(args, wg0, n_inst, moving, grid, lds, stream, alt)
+                       : launch_k1p_t<T, 6, 8>(args, wg0, n_inst, moving, grid, lds, stream, alt);
+    case 9: return q12 ? launch_k1p_t<T, 9, 12>(args, wg0, n_inst, moving, grid, lds, stream, alt)
+                       : launch_k1p_t<T, 9, 8>(args, wg0, n_inst, moving, grid, lds, stream, alt);
+    default: return q12 ? launch_k1p_t<T, 16, 12>(args, wg0, n_inst, moving, grid, lds, stream, alt)
+                        : launch_k1p_t<T, 16, 8>(args, wg0, n_inst, moving, grid, lds, stream, alt);
     }
 }
 
 int launch_k1(int fp32, int pmax, int qmax, int paired, const void* args, const uint32_t* wg0,
-              int n_inst, int moving, unsigned grid, size_t lds, void* stream) {
+              int n_inst, int moving, unsigned grid, size_t lds, void* stream, int alt) {
     if (paired) {
         if (!k1p_buckets(pmax, qmax)) return (int)hipErrorInvalidValue;
-        if (fp32) return launch_k1p_any<float>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream);
-        return launch_k1p_any<double>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream);
+        if (fp32)
+            return launch_k1p_any<float>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream,
+                                         alt);
+        return launch_k1p_any<double>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream,
+                                      alt);
     }
     if (fp32) return launch_k1_any<float>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream);
     return launch_k1_any<double>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream);

@@ -278,3 +278,31 @@ def test_automatic_kernel_choice(sg):
     big.set_node_pairs(None)
     assert big.node_pairs() is True
     big.step(2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_pair_kernel_workgroup_sizes_agree(sg, prec):
+    """The two workgroup sizes of the mirror-pair stream kernel (the default
+    and the other one the autotuner may pick) give the same particle states,
+    histograms and counters; the FP64 moment sums, grouped by lane
+    differently, agree to rounding."""
+    cfg = cfg_of(n_particles=60_000, precision=prec, degree=8, nodes_1d=12, nk=256, field0=4e6)
+    print(f"\n[gpu case] pair kernel workgroup sizes {prec}", flush=True)
+    out, threads = [], []
+    for alt in (0, 1):
+        sim = sg.Simulation(cfg, max_steps=40)
+        sim.set_node_pairs(True)
+        sim.set_pair_block(alt)
+        sim.init_particles()
+        sim.step(40)
+        threads.append(sim.stream_threads())
+        out.append(snapshot(sim))
+        out[-1]["m"] = sim.moments()
+    print(f"  threads per workgroup {threads}", flush=True)
+    assert threads[0] != threads[1] and set(threads) <= {512, 768, 1024}
+    a, b = out
+    for k in ("kx", "ky", "H", "M"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["cnt"] == b["cnt"]
+    for k, tol in (("E_vx", 1e-12), ("E_energy", 1e-12), ("Var_vx", 1e-9)):
+        assert np.allclose(a["m"][k], b["m"][k], rtol=tol, atol=0.0), k
