@@ -1445,6 +1445,14 @@ __device__ __forceinline__ void k2_lanes_instance(const K2Args<T>& a, unsigned c
         // bound.  True if the flight may end inside the step (the exact rates
         // are needed); lxi = -log(xi).
         auto bound_test = [&](T& lxi) -> bool {
+            const Words wx = k2_draw<T>(ctr0, step, (coll << 8) | kPurXi, a.instance, a.seed_lo,
+                                        a.seed_hi);
+            lxi = -dlog(uni<T>(wx.w0, wx.w1));
+            // The first iteration's draw is the one the stream kernel tested
+            // against its own bound to list this candidate, and nearly every
+            // candidate collides then: the exact rates are evaluated at once
+            // (the bound only filters; the exact test decides either way).
+            if (coll == 0) return true;
             T sb = (T)0;
             for (int q = 0; q < Q; ++q) {
                 T kx, ky;
@@ -1459,9 +1467,6 @@ __device__ __forceinline__ void k2_lanes_instance(const K2Args<T>& a, unsigned c
                            ? L.cedge[q] * ne * ((T)kEdgePts * Num<T>::trap) : (T)0;
                 sb = run > sb ? run : sb;
             }
-            const Words wx = k2_draw<T>(ctr0, step, (coll << 8) | kPurXi, a.instance, a.seed_lo,
-                                        a.seed_hi);
-            lxi = -dlog(uni<T>(wx.w0, wx.w1));
             return tc + lxi / (c.alpha1 * sb * ((T)1 + (T)16 * Num<T>::eps)) < dt;
         };
         // The rest of the iteration, after the exact node totals are in tot:
