@@ -421,9 +421,13 @@ __device__ __forceinline__ void k1_bin(const K1Args<T>& a, const K1Lds<T>& L, co
 }
 
 // Is a collision possible in this step?  ub: upper bound of every nodal
-// energy after the drift.  No collision iff -log(xi) / G~ >= dt; with
-// G~ <= gb and -log(xi) >= 1 - xi the test needs the logarithm only when
-// xi > 1 - gb dt.
+// energy after the drift.  No collision iff -log(xi) / G~ >= dt, which holds
+// when -log(xi) >= t = gb dt with gb >= G~.  With u = 1 - xi, -log(xi) >=
+// u + u^2/2 >= u: the particle is cleared when xi <= 1 - t (with the bound's
+// margin) or when u + u^2/2, rounded, exceeds t by more than its rounding.
+// The test is conservative only (a particle just inside it is listed); the
+// collider decides every candidate with the exact rates, so no logarithm is
+// needed here.  For xi >= 1/2, u is exact.
 template <typename T>
 __device__ __forceinline__ bool k1_candidate(const K1Args<T>& a, const Consts<T>& c, int64_t i, T ub,
                                              uint32_t step, T dt, uint32_t seed_lo, uint32_t seed_hi) {
@@ -431,7 +435,8 @@ __device__ __forceinline__ bool k1_candidate(const K1Args<T>& a, const Consts<T>
     const Words wx = philox10((uint32_t)i, step, kPurXi, a.instance, seed_lo, seed_hi);
     const T xi = uni<T>(wx.w0, wx.w1);
     if (xi <= (T)1 - t * c.b_margin) return false;
-    return !(-dlog(xi) >= t);
+    const T u = (T)1 - xi;
+    return !(u + (T)0.5 * u * u >= t * ((T)1 + (T)4 * Num<T>::eps));
 }
 
 // Threads per stream workgroup of an instantiation (k1_waves); 1024 and 512
