@@ -371,20 +371,23 @@ def pmc_summary(fetch_csv: str, write_csv: str, out_path: str = TRAFFIC_FILE,
         return by, sorted(seq)
 
     def moving_steps(seq):
-        """(stream, finalize, collide) rows of the last 2 * steps moving steps."""
+        """(stream, finalize, collide) rows of the last 2 * steps moving steps; the
+        collide row sums the step's collider launches (the lane collider's main
+        and leftover passes)."""
         out = []
         for k, (_, key, _, _) in enumerate(seq):
             if key != "stream":
                 continue
-            fin = col = None
+            fin, cols = None, []
             for row in seq[k + 1:]:
                 if row[1] == "stream":
                     break
                 if row[1] == "finalize" and fin is None:
                     fin = row
-                if row[1] == "collide" and col is None:
-                    col = row
-            if fin is not None and col is not None:
+                if row[1] == "collide":
+                    cols.append(row)
+            if fin is not None and cols:
+                col = (cols[0][0], "collide", sum(r[2] for r in cols), cols[0][3])
                 out.append((seq[k], fin, col))
         return out[-2 * steps:]
 

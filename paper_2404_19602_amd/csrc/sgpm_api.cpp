@@ -102,11 +102,10 @@ struct Group {
 // Bytes of every device region of one instance, in carving order.
 struct Layout {
     size_t total = 0;
-    size_t off[40];
-    int k = 0;
+    std::vector<size_t> off;   // offset of region k
     size_t add(size_t bytes) {
-        size_t o = total;
-        off[k++] = o;
+        const size_t o = total;
+        off.push_back(o);
         total = align256(total + (bytes ? bytes : 1));
         return o;
     }

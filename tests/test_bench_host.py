@@ -188,3 +188,33 @@ def test_traffic_only_for_the_same_launch_shape(monkeypatch, tmp_path):
     assert bench.measured_traffic("stream", 245) == 3.0
     assert bench.measured_traffic("stream", 490) is None
     assert bench.measured_traffic("stream") == 3.0
+
+
+def test_pmc_summary_sums_the_collider_launches_of_a_step(tmp_path):
+    """The lane collider runs as a main and a leftover launch per step: the
+    collide row of a step is the sum of both."""
+    head = ("Dispatch_Id,Grid_Size,Workgroup_Size,Kernel_Name,Counter_Name,Counter_Value\n")
+    copy_kib = 268435456 / 1024
+    k1, k3 = "void sgpm::k1_pairs<double, 9, 12, 0>(x)", "sgpm::k3_finalize(x)"
+    k2a, k2b = "void sgpm::k2_lanes<double, 9, false>(x)", "void sgpm::k2_lanes<double, 9, true>(x)"
+
+    def runs(counter, copy_val):
+        rows, d = [], 0
+        for _ in range(3):
+            d += 1; rows.append((d, 1024, 1024, "__amd_rocclr_copyBuffer", copy_val))
+        for s in range(4):
+            d += 1; rows.append((d, 255 * 512, 512, k1, 100.0))
+            d += 1; rows.append((d, 256, 256, k3, 10.0))
+            d += 1; rows.append((d, 256, 256, k2a, 7.0))
+            d += 1; rows.append((d, 256, 256, k2b, 2.0))
+        return head + "".join(f'{a},{g},{wg},"{k}",{counter},{v}\n' for a, g, wg, k, v in rows)
+
+    fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
+    fp.write_text(runs("FETCH_SIZE", copy_kib / 2))
+    wp.write_text(runs("WRITE_SIZE", copy_kib))
+    out = bench.pmc_summary(str(fp), str(wp), str(tmp_path / "t.json"), steps=2)
+    k = out["kernels"]
+    assert k["collide"]["dispatches"] == 4
+    assert k["collide"]["write_bytes"] == pytest.approx(9.0 * 1024)
+    assert k["stream"]["write_bytes"] == pytest.approx(100.0 * 1024)
+    assert out["stream_workgroups"] == 255
