@@ -1391,10 +1391,14 @@ size_t k2l_lds_bytes(int P, int Q, int fp32) {
     return off;
 }
 
+// deal: null to take the passes first, first + stride, ... of kBlock
+// candidates; else a counter (zero at the launch) from which each wave takes
+// its next 64 candidates as it finishes the last, so that waves whose
+// candidates collide more often do not hold up the end of the launch
 template <typename T, int PMAX>
 __device__ __forceinline__ void k2_lanes_instance(const K2Args<T>& a, unsigned char* smem,
                                                   uint32_t step, uint32_t total, uint32_t first,
-                                                  uint32_t stride) {
+                                                  uint32_t stride, uint32_t* deal) {
     const int P = a.P, Q = a.Q;
     // tables as in k2_instance; the per-group scratch holds the edge rates
     const K2Lds<T> L = k2_lds<T>(smem, PMAX, Q, k2l_groups(Q, PMAX));
@@ -1430,8 +1434,14 @@ __device__ __forceinline__ void k2_lanes_instance(const K2Args<T>& a, unsigned c
     const T dt_grid = strang ? dt * (T)0.5 : dt;
     uint32_t n_coll = 0, n_ev = 0, n_rej = 0, n_exh = 0, n_cmax = 0;
 
-    for (uint32_t p0 = first * kBlock; p0 < total; p0 += stride * kBlock) {
-        const uint32_t cid = p0 + tid;
+    auto take = [&]() -> uint32_t {
+        uint32_t b = 0;
+        if (lane == 0) b = atomicAdd(deal, 64u);
+        return __shfl(b, 0, 64);
+    };
+    for (uint32_t p0 = deal ? take() : first * kBlock + wave * 64; p0 < total;
+         p0 = deal ? take() : p0 + stride * kBlock) {
+        const uint32_t cid = p0 + lane;
         bool live = cid < total;
         int64_t i = 0;
         T cx[PMAX], cy[PMAX];
@@ -1671,7 +1681,7 @@ __device__ __forceinline__ void k2_lanes_instance(const K2Args<T>& a, unsigned c
 template <typename T, int PMAX, int NPL, bool LANES>
 __device__ __forceinline__ void k2_run(const K2Args<T>& a, unsigned char* smem, uint32_t step,
                                        uint32_t total, uint32_t first, uint32_t stride) {
-    if constexpr (LANES) k2_lanes_instance<T, PMAX>(a, smem, step, total, first, stride);
+    if constexpr (LANES) k2_lanes_instance<T, PMAX>(a, smem, step, total, first, stride, nullptr);
     else k2_instance<T, PMAX, NPL>(a, smem, step, total, first, stride);
 }
 
@@ -1693,8 +1703,15 @@ __device__ __forceinline__ void k2_body(const K2Args<T>* __restrict__ all, int n
         const uint32_t total = a.qc[2 * (step & 1u)];
         if (blockIdx.x == 0 && tid == 0) a.dyn->step_k3 = step + 1u;   // the finalize kernel is done
         const uint32_t per_pass = (uint32_t)(kBlock / a.G);
-        if (blockIdx.x < (total + per_pass - 1) / per_pass)
+        if constexpr (LANES) {
+            // the waves take their candidates from the spare word of the
+            // step's counters, cleared by the last finalize kernel
+            if (blockIdx.x < (total + per_pass - 1) / per_pass)
+                k2_lanes_instance<T, PMAX>(a, smem, step, total, 0, grid,
+                                           a.qc + 2 * (step & 1u) + 1);
+        } else if (blockIdx.x < (total + per_pass - 1) / per_pass) {
             k2_run<T, PMAX, NPL, LANES>(a, smem, step, total, blockIdx.x, grid);
+        }
         return;
     }
     // every instance's step, list length and pass count, read in parallel
