@@ -707,11 +707,13 @@ k1_stream(const K1Args<T>* __restrict__ all,
 // Q-1-p in the high 16 bits of a word, the middle node of an odd Q in the low
 // bits of plane (Q-1)/2.  The finalize kernel decodes it by the instance's
 // mirror flag.
-// VGPRs of the kernel, estimated: FP64 moment sums of every node, the
-// coefficients and the temporaries (measured on the compiler's output; at 9
-// modes and 12 nodes FP64 needs 174 and would spill 26 registers at 168)
+// VGPRs of the kernel, estimated: the FP64 moment sums a lane keeps (half of
+// the pairs' and the middle node's), the coefficients and the temporaries,
+// fitted to the compiler's output (at 9 modes and 12 nodes FP64 takes 144, so
+// three waves per SIMD; 16 modes take more per mode than the others)
 __host__ __device__ constexpr int k1p_regs(int fp32, int pmax, int qmax) {
-    return 2 * (3 * qmax + 3) + 2 * pmax * (fp32 ? 1 : 2) + (fp32 ? 44 : 60);
+    return 2 * (6 * ((qmax / 2 + 1) / 2) + 3) + pmax * (fp32 ? 2 : 4) + (fp32 ? 56 : 66) +
+           (pmax >= 16 ? (fp32 ? 2 : 14) : 0);
 }
 // Threads per workgroup of an instantiation: the default, four, three or two
 // waves per SIMD by the estimate, and (alt) the other occupancy the autotuner
@@ -823,9 +825,15 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
     int* seg = L.cbuf + wave * kK1PSeg;      // this wave's candidates
     uint32_t nseg = 0;                       // wave-uniform
 
-    double acc[NP][2][3], accm[3] = {0.0, 0.0, 0.0};
+    // The moment sums of the pairs are split between the two lanes of each
+    // lane pair: the even lane keeps those of pairs 0 .. NH-1 for both
+    // particles, the odd lane those of the other pairs.  That halves the
+    // registers they take (with them the kernel fits three waves per SIMD).
+    constexpr int NH = (NP + 1) / 2;
+    const bool odd_lane = (lane & 1) != 0;
+    double acc[NH][2][3], accm[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int p = 0; p < NP; ++p)
+    for (int p = 0; p < NH; ++p)
 #pragma unroll
         for (int j = 0; j < 2; ++j) { acc[p][j][0] = 0.0; acc[p][j][1] = 0.0; acc[p][j][2] = 0.0; }
 
@@ -854,20 +862,19 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
         T e2max = (T)0;
         uint32_t outmask = 0u;
         // one nodal value of the state at t^n: window and moment sums
-        auto node = [&](int q, int plane, int j, T kx, T ky, double (&m)[3], int bit) {
+        // t: the node's moment terms (zero for a lane past the end)
+        auto node = [&](int q, int plane, int j, T kx, T ky, double (&t)[3], int bit) {
             const T e0sq = L.eps0sq[q];
             const T e2 = kx * kx + ky * ky + e0sq;
             const T rs = rsqrt_nr(e2);
-            if (act) {
-                if constexpr (sizeof(T) == 8) {
-                    m[0] += kx * rs;          // v_F applied to the lane's sums at the end
-                    m[1] += ky * rs;
-                } else {
-                    m[0] += (double)(c.v_f * kx * rs);
-                    m[1] += (double)(c.v_f * ky * rs);
-                }
-                m[2] += (double)(e2 * rs);
+            if constexpr (sizeof(T) == 8) {
+                t[0] = act ? (double)(kx * rs) : 0.0;    // v_F applied to the sums at the end
+                t[1] = act ? (double)(ky * rs) : 0.0;
+            } else {
+                t[0] = act ? (double)(c.v_f * kx * rs) : 0.0;
+                t[1] = act ? (double)(c.v_f * ky * rs) : 0.0;
             }
+            t[2] = act ? (double)(e2 * rs) : 0.0;
             const T fr = floor((kx + c.lk) * c.inv_dk) - (T)a.win_r0;
             const T fl = floor((ky + c.lk) * c.inv_dk) - (T)a.win_l0;
             const T w = (T)W;
@@ -892,8 +899,24 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
             if (p < npairs) {
                 T ex, ox, ey, oy;
                 eo(p, ex, ox, ey, oy);
-                node(p, p, 0, ex + ox, ey + oy, acc[p][0], 2 * p);
-                node(Qt - 1 - p, p, 1, ex - ox, ey - oy, acc[p][1], 2 * p + 1);
+                double t[2][3];
+                node(p, p, 0, ex + ox, ey + oy, t[0], 2 * p);
+                node(Qt - 1 - p, p, 1, ex - ox, ey - oy, t[1], 2 * p + 1);
+                // the terms of both particles of the lane pair (the exchange
+                // with every lane active; the same sum on either lane), added
+                // by the lane that keeps this pair
+                double u[2][3];
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int m = 0; m < 3; ++m) u[j][m] = t[j][m] + dpp_f64<0xB1>(t[j][m]);
+                const int slot = p < NH ? p : p - NH;
+                if (odd_lane == (p >= NH)) {
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+#pragma unroll
+                        for (int m = 0; m < 3; ++m) acc[slot][j][m] += u[j][m];
+                }
             }
             // one pair after the other: overlapping them buys little with three
             // or four waves per SIMD and costs the registers of another wave
@@ -902,7 +925,9 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
         if (Qt & 1) {
             T ex, ox, ey, oy;
             eo(npairs, ex, ox, ey, oy);
-            node(npairs, npairs, 0, ex + ox, ey + oy, accm, 2 * NP);
+            double t[3];
+            node(npairs, npairs, 0, ex + ox, ey + oy, t, 2 * NP);
+            accm[0] += t[0]; accm[1] += t[1]; accm[2] += t[2];
         }
         // nodes outside the window (rare): the same values again, into the
         // overflow grid or counted outside the grid
@@ -973,13 +998,16 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
         double v[V];
         const double vf = sizeof(T) == 8 ? (double)c.v_f : 1.0;
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+        for (int p = 0; p < NP; ++p) {
+            const int slot = p < NH ? p : p - NH;
+            const bool mine = odd_lane == (p >= NH);
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                v[(2 * p + j) * 3] = vf * acc[p][j][0];
-                v[(2 * p + j) * 3 + 1] = vf * acc[p][j][1];
-                v[(2 * p + j) * 3 + 2] = acc[p][j][2];
+                v[(2 * p + j) * 3] = mine ? vf * acc[slot][j][0] : 0.0;
+                v[(2 * p + j) * 3 + 1] = mine ? vf * acc[slot][j][1] : 0.0;
+                v[(2 * p + j) * 3 + 2] = mine ? acc[slot][j][2] : 0.0;
             }
+        }
         v[6 * NP] = vf * accm[0]; v[6 * NP + 1] = vf * accm[1]; v[6 * NP + 2] = accm[2];
         const int npairs = Q >> 1;
         double* red = L.red + (size_t)wave * Q * 3;
