@@ -227,16 +227,21 @@ def test_collider_lanes_match_node_groups(sg, kw):
     assert_same(out[0], out[1], "lanes vs groups")
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_node_pairs_match_the_generic_stream_kernel(sg, prec):
+@pytest.mark.parametrize("prec,degree,nodes", [
+    ("fp64", 8, 12), ("fp32", 8, 12),
+    ("fp64", 5, 8),                     # four pairs: two kept by each lane of a lane pair
+    ("fp64", 4, 7), ("fp32", 2, 5),     # odd node counts: three and two pairs, a middle node
+])
+def test_node_pairs_match_the_generic_stream_kernel(sg, prec, degree, nodes):
     """The mirror-pair stream kernel against the generic one: the node values
     differ only by rounding (even and odd modes summed apart), so histograms
     and event counters agree exactly and the trajectories to rounding.  The
     candidate count differs: the pair kernel bounds the energies after the
     drift by the bound before it plus the largest drift, a looser bound that
     hands more particles to the collider, whose exact test rejects them."""
-    cfg = cfg_of(n_particles=50_000, precision=prec, degree=8, nodes_1d=12, nk=256, field0=4e6)
-    print(f"\n[gpu case] node pairs vs generic {prec}", flush=True)
+    cfg = cfg_of(n_particles=50_000, precision=prec, degree=degree, nodes_1d=nodes, nk=256,
+                 field0=4e6)
+    print(f"\n[gpu case] node pairs vs generic {prec} degree {degree} nodes {nodes}", flush=True)
     out = []
     for on in (True, False):
         sim = sg.Simulation(cfg, max_steps=40)
