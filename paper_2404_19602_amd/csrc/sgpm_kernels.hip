@@ -139,13 +139,16 @@ __device__ __forceinline__ void swap16_f64(double& a, double& b) {
     b = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
 }
 
-// x read from another lane of the same 16-lane row (DPP control CTRL)
+// x read from another lane of the same 16-lane row (DPP control CTRL).  Every
+// call is made with the whole wave active and a control whose source lane
+// always exists (quad permutations, row mirrors), so no lane keeps its old
+// value and none has to be set beforehand.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double x) {
     const uint64_t u = (uint64_t)__double_as_longlong(x);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF,
-                                                              0xF, false);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF,
+                                                           false);
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
@@ -707,13 +710,13 @@ k1_stream(const K1Args<T>* __restrict__ all,
 // Q-1-p in the high 16 bits of a word, the middle node of an odd Q in the low
 // bits of plane (Q-1)/2.  The finalize kernel decodes it by the instance's
 // mirror flag.
-// VGPRs of the kernel, estimated: the FP64 moment sums a lane keeps (half of
-// the pairs' and the middle node's), the coefficients and the temporaries,
-// fitted to the compiler's output (at 9 modes and 12 nodes FP64 takes 144, so
+// VGPRs of the kernel, estimated: the FP64 moment sums a lane keeps (one node
+// of every pair, and the middle node), the coefficients and the temporaries,
+// fitted to the compiler's output (at 9 modes and 12 nodes FP64 takes 155, so
 // three waves per SIMD; 16 modes take more per mode than the others)
 __host__ __device__ constexpr int k1p_regs(int fp32, int pmax, int qmax) {
-    return 2 * (6 * ((qmax / 2 + 1) / 2) + 3) + pmax * (fp32 ? 2 : 4) + (fp32 ? 56 : 66) +
-           (pmax >= 16 ? (fp32 ? 2 : 14) : 0);
+    return 2 * (3 * (qmax / 2) + 3) + pmax * (fp32 ? 2 : 5) + (fp32 ? 60 : 66) +
+           (pmax >= 16 ? (fp32 ? 6 : 14) : 0);
 }
 // Threads per workgroup of an instantiation: the default, four, three or two
 // waves per SIMD by the estimate, and (alt) the other occupancy the autotuner
@@ -826,16 +829,15 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
     uint32_t nseg = 0;                       // wave-uniform
 
     // The moment sums of the pairs are split between the two lanes of each
-    // lane pair: the even lane keeps those of pairs 0 .. NH-1 for both
-    // particles, the odd lane those of the other pairs.  That halves the
-    // registers they take (with them the kernel fits three waves per SIMD).
-    constexpr int NH = (NP + 1) / 2;
+    // lane pair: the even lane keeps those of node p of every pair for both
+    // particles, the odd lane those of node Q-1-p.  That halves the registers
+    // they take (with them the kernel fits three waves per SIMD).  Each lane
+    // evaluates the node it keeps first and hands the other's terms to its
+    // partner.
     const bool odd_lane = (lane & 1) != 0;
-    double acc[NH][2][3], accm[3] = {0.0, 0.0, 0.0};
+    double acc[NP][3], accm[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int p = 0; p < NH; ++p)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) { acc[p][j][0] = 0.0; acc[p][j][1] = 0.0; acc[p][j][2] = 0.0; }
+    for (int p = 0; p < NP; ++p) { acc[p][0] = 0.0; acc[p][1] = 0.0; acc[p][2] = 0.0; }
 
     // this wave's list into the global one (one reservation)
     auto flush = [&]() {
@@ -863,6 +865,7 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
         uint32_t outmask = 0u;
         // one nodal value of the state at t^n: window and moment sums
         // t: the node's moment terms (zero for a lane past the end)
+        // j: the node's half of the window word (0 for node p, 1 for Q-1-p)
         auto node = [&](int q, int plane, int j, T kx, T ky, double (&t)[3], int bit) {
             const T e0sq = L.eps0sq[q];
             const T e2 = kx * kx + ky * ky + e0sq;
@@ -899,24 +902,19 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
             if (p < npairs) {
                 T ex, ox, ey, oy;
                 eo(p, ex, ox, ey, oy);
-                double t[2][3];
-                node(p, p, 0, ex + ox, ey + oy, t[0], 2 * p);
-                node(Qt - 1 - p, p, 1, ex - ox, ey - oy, t[1], 2 * p + 1);
-                // the terms of both particles of the lane pair (the exchange
-                // with every lane active; the same sum on either lane), added
-                // by the lane that keeps this pair
-                double u[2][3];
+                // node a (kept: p on an even lane, Q-1-p on an odd one) and
+                // node b (handed over); sg * ox is exact, so k(a) and k(b) are
+                // E + O and E - O rounded as written
+                const int ja = odd_lane ? 1 : 0;
+                const T sg = odd_lane ? (T)-1 : (T)1;
+                double ta[3], tb[3];
+                node(odd_lane ? Qt - 1 - p : p, p, ja, ex + sg * ox, ey + sg * oy, ta, 2 * p + ja);
+                node(odd_lane ? p : Qt - 1 - p, p, 1 - ja, ex - sg * ox, ey - sg * oy, tb,
+                     2 * p + 1 - ja);
+                // the partner's terms of the node this lane keeps (the exchange
+                // with every lane active)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-#pragma unroll
-                    for (int m = 0; m < 3; ++m) u[j][m] = t[j][m] + dpp_f64<0xB1>(t[j][m]);
-                const int slot = p < NH ? p : p - NH;
-                if (odd_lane == (p >= NH)) {
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-#pragma unroll
-                        for (int m = 0; m < 3; ++m) acc[slot][j][m] += u[j][m];
-                }
+                for (int m = 0; m < 3; ++m) acc[p][m] += ta[m] + dpp_f64<0xB1>(tb[m]);
             }
             // one pair after the other: overlapping them buys little with three
             // or four waves per SIMD and costs the registers of another wave
@@ -999,13 +997,12 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
         const double vf = sizeof(T) == 8 ? (double)c.v_f : 1.0;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            const int slot = p < NH ? p : p - NH;
-            const bool mine = odd_lane == (p >= NH);
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                v[(2 * p + j) * 3] = mine ? vf * acc[slot][j][0] : 0.0;
-                v[(2 * p + j) * 3 + 1] = mine ? vf * acc[slot][j][1] : 0.0;
-                v[(2 * p + j) * 3 + 2] = mine ? acc[slot][j][2] : 0.0;
+                const bool mine = odd_lane == (j == 1);
+                v[(2 * p + j) * 3] = mine ? vf * acc[p][0] : 0.0;
+                v[(2 * p + j) * 3 + 1] = mine ? vf * acc[p][1] : 0.0;
+                v[(2 * p + j) * 3 + 2] = mine ? acc[p][2] : 0.0;
             }
         }
         v[6 * NP] = vf * accm[0]; v[6 * NP + 1] = vf * accm[1]; v[6 * NP + 2] = accm[2];
