@@ -807,8 +807,12 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
     for (int k = tid; k < WAVES * Q * 3; k += BLOCK) L.red[k] = 0.0;
     if (tid < 16) L.cnt[tid] = 0u;
     __syncthreads();
+    // eps0^2 by pairs: node p at 2p, node Q-1-p at 2p+1, the middle node of an
+    // odd Q last, so that a lane reads its node of pair p at 2p plus its parity
     for (int k = tid; k < Q; k += BLOCK) {
-        L.eps0sq[k] = a.tab.eps0sq[k];
+        const int half = Q >> 1;
+        L.eps0sq[k < half ? 2 * k : (k >= Q - half ? 2 * (Q - 1 - k) + 1 : 2 * half)] =
+            a.tab.eps0sq[k];
         T d = (T)0;
         for (int h = 0; h < PMAX; ++h) d += L.drift[h] * L.psi[k * PMAX + h];
         L.shift[k] = d;
@@ -865,9 +869,10 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
         uint32_t outmask = 0u;
         // one nodal value of the state at t^n: window and moment sums
         // t: the node's moment terms (zero for a lane past the end)
-        // j: the node's half of the window word (0 for node p, 1 for Q-1-p)
-        auto node = [&](int q, int plane, int j, T kx, T ky, double (&t)[3], int bit) {
-            const T e0sq = L.eps0sq[q];
+        // e: the node's slot in the eps0^2 table; j: its half of the window
+        // word (0 for node p, 1 for Q-1-p)
+        auto node = [&](int e, int plane, int j, T kx, T ky, double (&t)[3], int bit) {
+            const T e0sq = L.eps0sq[e];
             const T e2 = kx * kx + ky * ky + e0sq;
             const T rs = rsqrt_nr(e2);
             if constexpr (sizeof(T) == 8) {
@@ -908,9 +913,8 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
                 const int ja = odd_lane ? 1 : 0;
                 const T sg = odd_lane ? (T)-1 : (T)1;
                 double ta[3], tb[3];
-                node(odd_lane ? Qt - 1 - p : p, p, ja, ex + sg * ox, ey + sg * oy, ta, 2 * p + ja);
-                node(odd_lane ? p : Qt - 1 - p, p, 1 - ja, ex - sg * ox, ey - sg * oy, tb,
-                     2 * p + 1 - ja);
+                node(2 * p + ja, p, ja, ex + sg * ox, ey + sg * oy, ta, 2 * p + ja);
+                node(2 * p + 1 - ja, p, 1 - ja, ex - sg * ox, ey - sg * oy, tb, 2 * p + 1 - ja);
                 // the partner's terms of the node this lane keeps (the exchange
                 // with every lane active)
 #pragma unroll
@@ -924,7 +928,7 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
             T ex, ox, ey, oy;
             eo(npairs, ex, ox, ey, oy);
             double t[3];
-            node(npairs, npairs, 0, ex + ox, ey + oy, t, 2 * NP);
+            node(2 * npairs, npairs, 0, ex + ox, ey + oy, t, 2 * NP);
             accm[0] += t[0]; accm[1] += t[1]; accm[2] += t[2];
         }
         // nodes outside the window (rare): the same values again, into the
