@@ -276,6 +276,17 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ row, const T (&c
     kx = x; ky = y;
 }
 
+// A cell coordinate relative to a window origin r0 >= 0, before the floor:
+// x - r0 for x = (k + L) / dk.  For x >= r0 the difference is exact (x and
+// the integer r0 are multiples of x's unit in the last place, and the
+// difference is smaller than x), so x - r0 lies in [0, W) exactly when
+// floor(x) - r0 does, and truncating it gives floor(x) - r0; for x < r0 it is
+// negative, and a NaN stays a NaN.  The floor itself is then not needed.
+template <typename T>
+__device__ __forceinline__ T win_offset(T x, int r0) {
+    return x - (T)r0;
+}
+
 // the coefficients of the particles of one tile: base is the tile's first
 // particle (the same for the whole workgroup), t this lane's offset in it, so
 // every mode is one uniform pointer plus a 32-bit lane offset.  Modes past P
@@ -558,9 +569,11 @@ k1_stream(const K1Args<T>* __restrict__ all,
                             {
                                 // the node's cell: inside the LDS window (compared in
                                 // floating point, so a NaN fails) one packed increment,
-                                // else its bit in outmask for the general path below
-                                const T fr = floor((kx + c.lk) * c.inv_dk) - (T)a.win_r0;
-                                const T fl = floor((ky + c.lk) * c.inv_dk) - (T)a.win_l0;
+                                // else its bit in outmask for the general path below.
+                                // fr, fl: the coordinates less the window's origin
+                                // before the floor (see win_offset)
+                                const T fr = win_offset<T>((kx + c.lk) * c.inv_dk, a.win_r0);
+                                const T fl = win_offset<T>((ky + c.lk) * c.inv_dk, a.win_l0);
                                 const T w = (T)a.win;
                                 const bool in = (fr >= (T)0) & (fr < w) & (fl >= (T)0) & (fl < w);
                                 if (on && in)
@@ -883,8 +896,8 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
                 t[1] = act ? (double)(c.v_f * ky * rs) : 0.0;
             }
             t[2] = act ? (double)(e2 * rs) : 0.0;
-            const T fr = floor((kx + c.lk) * c.inv_dk) - (T)a.win_r0;
-            const T fl = floor((ky + c.lk) * c.inv_dk) - (T)a.win_l0;
+            const T fr = win_offset<T>((kx + c.lk) * c.inv_dk, a.win_r0);
+            const T fl = win_offset<T>((ky + c.lk) * c.inv_dk, a.win_l0);
             const T w = (T)W;
             const bool in = (fr >= (T)0) & (fr < w) & (fl >= (T)0) & (fl < w);
             if (act && in)
