@@ -276,6 +276,18 @@ __device__ __forceinline__ void eval_node(const T* __restrict__ row, const T (&c
     kx = x; ky = y;
 }
 
+// The modes whose drift is not zero, as bits in a scalar register (the field
+// drives only some of them: the mean mode for a deterministic field), so that
+// the stores of the drift test a bit rather than read the table every tile.
+template <typename T, int PMAX>
+__device__ __forceinline__ uint32_t drift_modes(const T* drift, int P) {
+    uint32_t m = 0u;
+#pragma unroll
+    for (int h = 0; h < PMAX; ++h)
+        if (h < P && drift[h] != (T)0) m |= 1u << h;
+    return __builtin_amdgcn_readfirstlane(m);
+}
+
 // A cell coordinate relative to a window origin r0 >= 0, before the floor:
 // x - r0 for x = (k + L) / dk.  For x >= r0 the difference is exact (x and
 // the integer r0 are multiples of x's unit in the last place, and the
@@ -508,6 +520,7 @@ k1_stream(const K1Args<T>* __restrict__ all,
     }
     __syncthreads();
     const Consts<T>& c = *L.c;
+    const uint32_t dmask = drift_modes<T, PMAX>(L.drift, P);
 
     const int64_t begin = (int64_t)wg * a.chunk;
     const int64_t end = begin + a.chunk < a.n ? begin + a.chunk : a.n;
@@ -648,7 +661,7 @@ k1_stream(const K1Args<T>* __restrict__ all,
                 __asm__ volatile("" : "+v"(t));
     #pragma unroll
                 for (int h = 0; h < PMAX; ++h)
-                    if (h < P && L.drift[h] != (T)0)
+                    if ((dmask >> h) & 1u)
                         (a.kx + ((size_t)h * a.n + base))[t] = (cx[h] - L.drift[h]) - L.pdrift[h];
             }
             // candidates of this workgroup collected in LDS
@@ -839,6 +852,7 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
     __syncthreads();
     const Consts<T>& c = *L.c;
     const T shmax = s_shmax;
+    const uint32_t dmask = drift_modes<T, PMAX>(L.drift, P);
     const int64_t begin = (int64_t)wg * a.chunk;
     const int64_t end = begin + a.chunk < a.n ? begin + a.chunk : a.n;
     const int W = a.win;
@@ -974,7 +988,7 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
             __asm__ volatile("" : "+v"(tt));
 #pragma unroll
             for (int h = 0; h < PMAX; ++h)
-                if (h < P && L.drift[h] != (T)0)
+                if ((dmask >> h) & 1u)
                     (a.kx + ((size_t)h * a.n + base))[tt] = (cx[h] - L.drift[h]) - L.pdrift[h];
         }
         const uint64_t mask = __ballot(cand);
