@@ -288,6 +288,27 @@ __device__ __forceinline__ uint32_t drift_modes(const T* drift, int P) {
     return __builtin_amdgcn_readfirstlane(m);
 }
 
+// The LDS word a stream-kernel lane increments in place of a window cell when
+// its node is outside the window or it holds no particle: one of the
+// workgroup's counter words that are never read (the first eight are the
+// counters), so that the increment needs no branch around it.
+constexpr int kWinSink = 15;
+
+// A value that is the same on every lane, moved into scalar registers.  The
+// stream kernels keep the cell map's constants there: read from LDS inside
+// the node loop, they would be read again after every window increment (the
+// compiler must assume that the increment may change them), and the wait for
+// that read would also wait for the increment.
+__device__ __forceinline__ double uniform_of(double x) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ float uniform_of(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
 // A cell coordinate relative to a window origin r0 >= 0, before the floor:
 // x - r0 for x = (k + L) / dk.  For x >= r0 the difference is exact (x and
 // the integer r0 are multiples of x's unit in the last place, and the
@@ -521,6 +542,7 @@ k1_stream(const K1Args<T>* __restrict__ all,
     __syncthreads();
     const Consts<T>& c = *L.c;
     const uint32_t dmask = drift_modes<T, PMAX>(L.drift, P);
+    const T lk = uniform_of(c.lk), inv_dk = uniform_of(c.inv_dk);
 
     const int64_t begin = (int64_t)wg * a.chunk;
     const int64_t end = begin + a.chunk < a.n ? begin + a.chunk : a.n;
@@ -585,13 +607,16 @@ k1_stream(const K1Args<T>* __restrict__ all,
                                 // else its bit in outmask for the general path below.
                                 // fr, fl: the coordinates less the window's origin
                                 // before the floor (see win_offset)
-                                const T fr = win_offset<T>((kx + c.lk) * c.inv_dk, a.win_r0);
-                                const T fl = win_offset<T>((ky + c.lk) * c.inv_dk, a.win_l0);
+                                const T fr = win_offset<T>((kx + lk) * inv_dk, a.win_r0);
+                                const T fl = win_offset<T>((ky + lk) * inv_dk, a.win_l0);
                                 const T w = (T)a.win;
                                 const bool in = (fr >= (T)0) & (fr < w) & (fl >= (T)0) & (fl < w);
-                                if (on && in)
-                                    atomicAdd(&L.hwin[win_word(q, a.win, (int)fr, (int)fl)],
-                                              (q & 1) ? 65536u : 1u);
+                                // every lane adds (see kWinSink): no branch, so the
+                                // wait for a later LDS read need not cover the add
+                                atomicAdd((on && in)
+                                              ? &L.hwin[win_word(q, a.win, (int)fr, (int)fl)]
+                                              : &L.cnt[kWinSink],
+                                          (q & 1) ? 65536u : 1u);
                                 outmask |= (on && !in) ? (1u << q) : 0u;
                             }
                             // after the drift, for the rate bound
@@ -853,6 +878,7 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
     const Consts<T>& c = *L.c;
     const T shmax = s_shmax;
     const uint32_t dmask = drift_modes<T, PMAX>(L.drift, P);
+    const T lk = uniform_of(c.lk), inv_dk = uniform_of(c.inv_dk);
     const int64_t begin = (int64_t)wg * a.chunk;
     const int64_t end = begin + a.chunk < a.n ? begin + a.chunk : a.n;
     const int W = a.win;
@@ -896,10 +922,9 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
         uint32_t outmask = 0u;
         // one nodal value of the state at t^n: window and moment sums
         // t: the node's moment terms (zero for a lane past the end)
-        // e: the node's slot in the eps0^2 table; j: its half of the window
-        // word (0 for node p, 1 for Q-1-p)
-        auto node = [&](int e, int plane, int j, T kx, T ky, double (&t)[3], int bit) {
-            const T e0sq = L.eps0sq[e];
+        // e0sq: the node's eps0^2 (read before the pair's first increment);
+        // j: its half of the window word (0 for node p, 1 for Q-1-p)
+        auto node = [&](T e0sq, int plane, int j, T kx, T ky, double (&t)[3], int bit) {
             const T e2 = kx * kx + ky * ky + e0sq;
             const T rs = rsqrt_nr(e2);
             if constexpr (sizeof(T) == 8) {
@@ -910,13 +935,15 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
                 t[1] = act ? (double)(c.v_f * ky * rs) : 0.0;
             }
             t[2] = act ? (double)(e2 * rs) : 0.0;
-            const T fr = win_offset<T>((kx + c.lk) * c.inv_dk, a.win_r0);
-            const T fl = win_offset<T>((ky + c.lk) * c.inv_dk, a.win_l0);
+            const T fr = win_offset<T>((kx + lk) * inv_dk, a.win_r0);
+            const T fl = win_offset<T>((ky + lk) * inv_dk, a.win_l0);
             const T w = (T)W;
             const bool in = (fr >= (T)0) & (fr < w) & (fl >= (T)0) & (fl < w);
-            if (act && in)
-                atomicAdd(&L.hwin[__mul24(plane, W * W) + __mul24((int)fr, W) + (int)fl],
-                          j ? 65536u : 1u);
+            // every lane adds (see kWinSink): no branch, so the wait for a
+            // later LDS read need not cover the add
+            atomicAdd((act && in) ? &L.hwin[__mul24(plane, W * W) + __mul24((int)fr, W) + (int)fl]
+                                  : &L.cnt[kWinSink],
+                      j ? 65536u : 1u);
             outmask |= (act && !in) ? (1u << bit) : 0u;
             e2max = fmax(e2, e2max);    // a NaN e2 is passed over
         };
@@ -940,8 +967,9 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
                 const int ja = odd_lane ? 1 : 0;
                 const T sg = odd_lane ? (T)-1 : (T)1;
                 double ta[3], tb[3];
-                node(2 * p + ja, p, ja, ex + sg * ox, ey + sg * oy, ta, 2 * p + ja);
-                node(2 * p + 1 - ja, p, 1 - ja, ex - sg * ox, ey - sg * oy, tb, 2 * p + 1 - ja);
+                const T e0a = L.eps0sq[2 * p + ja], e0b = L.eps0sq[2 * p + 1 - ja];
+                node(e0a, p, ja, ex + sg * ox, ey + sg * oy, ta, 2 * p + ja);
+                node(e0b, p, 1 - ja, ex - sg * ox, ey - sg * oy, tb, 2 * p + 1 - ja);
                 // the partner's terms of the node this lane keeps (the exchange
                 // with every lane active)
 #pragma unroll
@@ -955,7 +983,7 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
             T ex, ox, ey, oy;
             eo(npairs, ex, ox, ey, oy);
             double t[3];
-            node(2 * npairs, npairs, 0, ex + ox, ey + oy, t, 2 * NP);
+            node(L.eps0sq[2 * npairs], npairs, 0, ex + ox, ey + oy, t, 2 * NP);
             accm[0] += t[0]; accm[1] += t[1]; accm[2] += t[2];
         }
         // nodes outside the window (rare): the same values again, into the
