@@ -271,7 +271,7 @@ def other_configs(steps: int = 50) -> dict:
             sim = sg.Simulation(cfg, max_steps=2 * steps + 40)
             sim.init_particles()
             sim.step(10, cfg["dt"])
-            sim.autotune(trial_steps=5, dt=cfg["dt"])
+            sim.autotune(trial_steps=10, dt=cfg["dt"])
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             sim.step(steps, cfg["dt"])
