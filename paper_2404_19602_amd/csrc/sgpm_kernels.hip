@@ -449,6 +449,23 @@ __device__ __forceinline__ int win_word(int q, int W, int wr, int wl) {
     return __mul24(q >> 1, W * W) + __mul24(wr, W) + wl;
 }
 
+// An increment of an LDS word, at workgroup scope.  The scope differs from
+// that of the global increments (device scope), so the compiler does not join
+// an LDS and a global increment on the two sides of a branch into one flat
+// atomic, which counts against both memory counters: the wave's next wait for
+// an LDS read would then wait for the global increment to complete.
+__device__ __forceinline__ void lds_add(uint32_t* p, uint32_t v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// An increment of cell (q, r, l) of the overflow grid: the offset in 32 bits
+// (Q nk^2 < 2^30) from the uniform base, so the address takes no 64-bit
+// register pair.
+__device__ __forceinline__ void extra_add(uint32_t* extra, int q, int r, int l, int nk) {
+    const uint32_t off = (uint32_t)(q * nk * nk + r * nk + l) << 2;
+    atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(extra) + off), 1u);
+}
+
 // one nodal value into H^n: LDS window when inside it, else the overflow grid
 template <typename T>
 __device__ __forceinline__ void k1_bin(const K1Args<T>& a, const K1Lds<T>& L, const Consts<T>& c,
@@ -456,14 +473,14 @@ __device__ __forceinline__ void k1_bin(const K1Args<T>& a, const K1Lds<T>& L, co
     const int r = cell_coord<T>(kx, c.lk, c.inv_dk);
     const int l = cell_coord<T>(ky, c.lk, c.inv_dk);
     if (r < 0 || l < 0 || r >= c.nk || l >= c.nk) {
-        atomicAdd(&L.cnt[SGPM_CNT_OUT_OF_GRID], 1u);
+        lds_add(&L.cnt[SGPM_CNT_OUT_OF_GRID], 1u);
         return;
     }
     const int wr = r - a.win_r0, wl = l - a.win_l0;
     if ((unsigned)wr < (unsigned)a.win && (unsigned)wl < (unsigned)a.win) {
-        atomicAdd(&L.hwin[win_word(q, a.win, wr, wl)], (q & 1) ? 65536u : 1u);
+        lds_add(&L.hwin[win_word(q, a.win, wr, wl)], (q & 1) ? 65536u : 1u);
     } else {
-        atomicAdd(&a.extra[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l], 1u);
+        extra_add(a.extra, q, r, l, c.nk);
     }
 }
 
@@ -613,7 +630,7 @@ k1_stream(const K1Args<T>* __restrict__ all,
                                 const bool in = (fr >= (T)0) & (fr < w) & (fl >= (T)0) & (fl < w);
                                 // every lane adds (see kWinSink): no branch, so the
                                 // wait for a later LDS read need not cover the add
-                                atomicAdd((on && in)
+                                lds_add((on && in)
                                               ? &L.hwin[win_word(q, a.win, (int)fr, (int)fl)]
                                               : &L.cnt[kWinSink],
                                           (q & 1) ? 65536u : 1u);
@@ -941,7 +958,7 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
             const bool in = (fr >= (T)0) & (fr < w) & (fl >= (T)0) & (fl < w);
             // every lane adds (see kWinSink): no branch, so the wait for a
             // later LDS read need not cover the add
-            atomicAdd((act && in) ? &L.hwin[__mul24(plane, W * W) + __mul24((int)fr, W) + (int)fl]
+            lds_add((act && in) ? &L.hwin[__mul24(plane, W * W) + __mul24((int)fr, W) + (int)fl]
                                   : &L.cnt[kWinSink],
                       j ? 65536u : 1u);
             outmask |= (act && !in) ? (1u << bit) : 0u;
@@ -997,12 +1014,12 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
                 eo(p, ex, ox, ey, oy);
                 const T kx = j ? ex - ox : ex + ox, ky = j ? ey - oy : ey + oy;
                 const int q = j ? Qt - 1 - p : p;
-                const int r = cell_coord<T>(kx, c.lk, c.inv_dk);
-                const int l = cell_coord<T>(ky, c.lk, c.inv_dk);
+                const int r = cell_coord<T>(kx, lk, inv_dk);
+                const int l = cell_coord<T>(ky, lk, inv_dk);
                 if (r < 0 || l < 0 || r >= c.nk || l >= c.nk)
-                    atomicAdd(&L.cnt[SGPM_CNT_OUT_OF_GRID], 1u);
+                    lds_add(&L.cnt[SGPM_CNT_OUT_OF_GRID], 1u);
                 else
-                    atomicAdd(&a.extra[(size_t)q * c.nk * c.nk + (size_t)r * c.nk + l], 1u);
+                    extra_add(a.extra, q, r, l, c.nk);
             }
         }
         // after the drift every nodal wave-vector moves by at most shmax, so
