@@ -133,6 +133,17 @@ class Simulation:
         the other one (the autotuner tries both)."""
         check(lib().sgpm_set_pair_block(self._ctx, int(alt)), self._ctx, "set_pair_block")
 
+    def set_stream_nontemporal(self, mode):
+        """True/False: non-temporal hints on the stream kernels' state access
+        always / never; None: when the state exceeds the last-level cache."""
+        m = -1 if mode is None else (1 if mode else 0)
+        check(lib().sgpm_set_stream_nontemporal(self._ctx, m), self._ctx, "set_stream_nontemporal")
+
+    def stream_nontemporal(self) -> bool:
+        v = C.c_int32(0)
+        check(lib().sgpm_stream_nontemporal(self._ctx, C.byref(v)), self._ctx, "stream_nontemporal")
+        return bool(v.value)
+
     def stream_threads(self, inst: int = 0) -> int:
         v = C.c_int32(0)
         check(lib().sgpm_stream_threads(self._ctx, inst, C.byref(v)), self._ctx, "stream_threads")

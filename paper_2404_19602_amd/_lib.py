@@ -76,6 +76,8 @@ def lib():
             "sgpm_node_pairs": (i32, [vp, i32, C.POINTER(i32)]),
             "sgpm_collider_lanes": (i32, [vp, i32, C.POINTER(i32)]),
             "sgpm_set_pair_block": (i32, [vp, i32]),
+            "sgpm_set_stream_nontemporal": (i32, [vp, i32]),
+            "sgpm_stream_nontemporal": (i32, [vp, C.POINTER(i32)]),
             "sgpm_stream_threads": (i32, [vp, i32, C.POINTER(i32)]),
             "sgpm_set_profiling": (i32, [vp, i32]),
             "sgpm_kernel_times": (i32, [vp, vp, vp]),

@@ -29,6 +29,11 @@ constexpr double kECharge = 1.602176634e-19;
 constexpr int kMaxBins = 4096;
 constexpr int kDefaultGraphSteps = 16;
 constexpr int kMaxLdsBudget = 80 * 1024;   // largest window budget the slabs are sized for
+// state bytes of a context above which the stream kernels read the state and
+// write its drift with non-temporal hints: a state that does not fit in the
+// last-level cache (256 MB on MI355X) is streamed through it once per step,
+// and caching it only evicts what the collider and the next step could reuse
+constexpr size_t kStreamNtBytes = (size_t)192 << 20;
 constexpr int kMaxGraphSteps = 256;
 constexpr double kWinEv = 2.0;     // half-width (eV) beyond which the LDS window does not grow
 
@@ -310,6 +315,9 @@ struct sgpm_ctx {
     // threads per workgroup of the mirror-pair stream kernel: 0 the default
     // form of each instantiation, 1 the other one (k1p_block)
     int k1_alt = 0;
+    // non-temporal state access of the stream kernels: 1 always, 0 never, -1
+    // when the context's state exceeds kStreamNtBytes
+    int nt_mode = -1;
     Prof prof;
 };
 
@@ -414,6 +422,14 @@ Consts<T> make_consts(const sgpm_instance_desc& d, const HostTables& t) {
     c.c_max = d.c_max;
     c.splitting = d.splitting;
     return c;
+}
+
+// whether the stream kernels access the state with non-temporal hints
+bool stream_nt(const sgpm_ctx* cx) {
+    if (cx->nt_mode >= 0) return cx->nt_mode == 1;
+    size_t b = 0;
+    for (const Instance& J : cx->inst) b += (size_t)J.P * (size_t)J.n * 2 * (J.fp32 ? 4 : 8);
+    return b > kStreamNtBytes;
 }
 
 template <typename T>
@@ -599,7 +615,8 @@ sgpm_status enqueue_step(sgpm_ctx* c, hipStream_t s, bool prof) {
         const Group& G = c->groups[g];
         const int m = (int)G.members.size(), off = G.pos0 + (int)g;
         int e = launch_k1(G.fp32, G.pmax, G.qmax, G.paired, k1_args(c, G.fp32, G.pos0),
-                          wg_table(c, kTabK1, off), m, 1, G.k1_grid, G.k1_lds, s, c->k1_alt);
+                          wg_table(c, kTabK1, off), m, 1, G.k1_grid, G.k1_lds, s, c->k1_alt,
+                          stream_nt(c));
         if (e) return dev_fail(c, (hipError_t)e, "stream kernel launch");
         if (prof) { sgpm_status r = prof_mark(c, s, SGPM_KERNEL_STREAM); if (r) return r; }
         e = launch_k3(c->k3 + G.pos0, wg_table(c, kTabK3, off), m, 1, G.k3_grid, s);
@@ -619,7 +636,8 @@ sgpm_status enqueue_state_pass(sgpm_ctx* c, hipStream_t s) {
         const Group& G = c->groups[g];
         const int m = (int)G.members.size(), off = G.pos0 + (int)g;
         int e = launch_k1(G.fp32, G.pmax, G.qmax, G.paired, k1_args(c, G.fp32, G.pos0),
-                          wg_table(c, kTabK1, off), m, 0, G.k1_grid, G.k1_lds, s, c->k1_alt);
+                          wg_table(c, kTabK1, off), m, 0, G.k1_grid, G.k1_lds, s, c->k1_alt,
+                          stream_nt(c));
         if (!e) e = launch_k3(c->k3 + G.pos0, wg_table(c, kTabK3, off), m, 0, G.k3_grid, s);
         if (e) return dev_fail(c, (hipError_t)e, "state pass launch");
     }
@@ -632,7 +650,7 @@ sgpm_status state_pass_one(sgpm_ctx* c, const Instance& I) {
     int e = launch_k1(I.fp32, G.pmax, G.qmax, G.paired, k1_args(c, I.fp32, I.pos),
                       wg_table(c, kTabK1One, 2 * I.pos), 1, 0, (unsigned)I.nwg,
                       k1_lds_bytes(I.P, I.Q, I.fp32, I.paired, I.hwin_words, I.chunk, c->k1_alt),
-                      c->stream, c->k1_alt);
+                      c->stream, c->k1_alt, stream_nt(c));
     if (!e)
         e = launch_k3(c->k3 + I.pos, wg_table(c, kTabK3One, 2 * I.pos), 1, 0,
                       (unsigned)k3_grid(I), c->stream);
@@ -1100,6 +1118,20 @@ sgpm_status sgpm_set_pair_block(sgpm_ctx* c, int32_t alt) {
     if (alt != 0 && alt != 1) return fail(c, SGPM_EINVAL, "alt must be 0 or 1");
     c->k1_alt = alt;
     return upload_args(c);
+}
+
+sgpm_status sgpm_set_stream_nontemporal(sgpm_ctx* c, int32_t mode) {
+    if (!c) return SGPM_EINVAL;
+    if (c->poisoned) return fail(c, SGPM_ESTATE, "context poisoned");
+    if (mode < -1 || mode > 1) return fail(c, SGPM_EINVAL, "mode must be -1, 0 or 1");
+    c->nt_mode = mode;
+    return upload_args(c);
+}
+
+sgpm_status sgpm_stream_nontemporal(const sgpm_ctx* c, int32_t* on) {
+    if (!c || !on) return SGPM_EINVAL;
+    *on = stream_nt(c) ? 1 : 0;
+    return SGPM_OK;
 }
 
 sgpm_status sgpm_stream_threads(const sgpm_ctx* c, int32_t inst, int32_t* threads) {

@@ -256,7 +256,7 @@ struct MomAtArgs {
 // batched launchers take device arrays of descriptors of n_inst instances of
 // one shape group and wg0[n_inst + 1], the first workgroup of each instance.
 int launch_k1(int fp32, int pmax, int qmax, int paired, const void* args, const uint32_t* wg0,
-              int n_inst, int moving, unsigned grid, size_t lds, void* stream, int alt);
+              int n_inst, int moving, unsigned grid, size_t lds, void* stream, int alt, int nt);
 int launch_k2(int fp32, int pmax, int npl, int lanes, const void* args, int n_inst,
               unsigned grid, size_t lds, void* stream);
 int launch_k3(const K3Args* args, const uint32_t* wg0, int n_inst, int moving, unsigned grid,

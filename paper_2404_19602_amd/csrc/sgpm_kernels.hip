@@ -324,7 +324,11 @@ __device__ __forceinline__ T win_offset(T x, int r0) {
 // particle (the same for the whole workgroup), t this lane's offset in it, so
 // every mode is one uniform pointer plus a 32-bit lane offset.  Modes past P
 // repeat mode P-1; the padded basis tables are zero there, so they add nothing.
-template <typename T, int PMAX>
+// NT: non-temporal loads, for a state that does not fit in the last-level
+// cache and is streamed through it once per step (a compile-time choice: two
+// forms of one load in the branches of a run-time test would be merged into
+// one by the compiler, dropping the hint)
+template <typename T, int PMAX, bool NT = false>
 __device__ __forceinline__ void load_tile_coeffs(const T* __restrict__ kxa, const T* __restrict__ kya,
                                                  int64_t n, int P, int64_t base, uint32_t t,
                                                  T (&cx)[PMAX], T (&cy)[PMAX]) {
@@ -333,9 +337,21 @@ __device__ __forceinline__ void load_tile_coeffs(const T* __restrict__ kxa, cons
         const int hh = h < P ? h : P - 1;
         const T* px = kxa + ((size_t)hh * n + base);
         const T* py = kya + ((size_t)hh * n + base);
-        cx[h] = px[t];
-        cy[h] = py[t];
+        if constexpr (NT) {
+            cx[h] = __builtin_nontemporal_load(px + t);
+            cy[h] = __builtin_nontemporal_load(py + t);
+        } else {
+            cx[h] = px[t];
+            cy[h] = py[t];
+        }
     }
+}
+
+// a drift store of the stream kernels, with the hint of the state's loads
+template <bool NT, typename T>
+__device__ __forceinline__ void store_state(T* p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 // coefficients of particle i (drift applied), zero past P, branch-free loads
@@ -837,7 +853,8 @@ __device__ __forceinline__ void wave_sums_map(const double (&v)[V], int lane, F&
     }
 }
 
-template <typename T, int PMAX, int QMAX, int ALT>
+// NT: non-temporal state access (see load_tile_coeffs)
+template <typename T, int PMAX, int QMAX, int ALT, int NT>
 __global__ void __launch_bounds__((K1PBlock<T, PMAX, QMAX, ALT>::value))
 k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, int n_inst,
          int moving) {
@@ -934,7 +951,8 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
         __asm__ volatile("" : "+s"(Qt), "+s"(key_lo), "+s"(key_hi));
         const int npairs = Qt >> 1;
         T cx[PMAX], cy[PMAX];
-        load_tile_coeffs<T, PMAX>(a.kx, a.ky, a.n, P, base, act ? (uint32_t)tid : 0u, cx, cy);
+        load_tile_coeffs<T, PMAX, NT != 0>(a.kx, a.ky, a.n, P, base, act ? (uint32_t)tid : 0u,
+                                           cx, cy);
         T e2max = (T)0;
         uint32_t outmask = 0u;
         // one nodal value of the state at t^n: window and moment sums
@@ -1034,7 +1052,8 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
 #pragma unroll
             for (int h = 0; h < PMAX; ++h)
                 if ((dmask >> h) & 1u)
-                    (a.kx + ((size_t)h * a.n + base))[tt] = (cx[h] - L.drift[h]) - L.pdrift[h];
+                    store_state<NT != 0>((a.kx + ((size_t)h * a.n + base)) + tt,
+                                         (cx[h] - L.drift[h]) - L.pdrift[h]);
         }
         const uint64_t mask = __ballot(cand);
         if (mask) {
@@ -2146,45 +2165,53 @@ static int launch_k1_any(int pmax, int qmax, const void* args, const uint32_t* w
     }
 }
 
+template <typename T, int PMAX, int QMAX, int ALT, int NT>
+static void launch_k1p_f(const void* args, const uint32_t* wg0, int n_inst, int moving,
+                         unsigned grid, size_t lds, void* stream) {
+    hipLaunchKernelGGL((k1_pairs<T, PMAX, QMAX, ALT, NT>), dim3(grid),
+                       dim3(K1PBlock<T, PMAX, QMAX, ALT>::value), lds, (hipStream_t)stream,
+                       static_cast<const K1Args<T>*>(args), wg0, n_inst, moving);
+}
+
 template <typename T, int PMAX, int QMAX>
 static int launch_k1p_t(const void* args, const uint32_t* wg0, int n_inst, int moving,
-                        unsigned grid, size_t lds, void* stream, int alt) {
-    if (alt)
-        hipLaunchKernelGGL((k1_pairs<T, PMAX, QMAX, 1>), dim3(grid),
-                           dim3(K1PBlock<T, PMAX, QMAX, 1>::value), lds, (hipStream_t)stream,
-                           static_cast<const K1Args<T>*>(args), wg0, n_inst, moving);
-    else
-        hipLaunchKernelGGL((k1_pairs<T, PMAX, QMAX, 0>), dim3(grid),
-                           dim3(K1PBlock<T, PMAX, QMAX, 0>::value), lds, (hipStream_t)stream,
-                           static_cast<const K1Args<T>*>(args), wg0, n_inst, moving);
+                        unsigned grid, size_t lds, void* stream, int alt, int nt) {
+    if (alt) {
+        if (nt) launch_k1p_f<T, PMAX, QMAX, 1, 1>(args, wg0, n_inst, moving, grid, lds, stream);
+        else launch_k1p_f<T, PMAX, QMAX, 1, 0>(args, wg0, n_inst, moving, grid, lds, stream);
+    } else {
+        if (nt) launch_k1p_f<T, PMAX, QMAX, 0, 1>(args, wg0, n_inst, moving, grid, lds, stream);
+        else launch_k1p_f<T, PMAX, QMAX, 0, 0>(args, wg0, n_inst, moving, grid, lds, stream);
+    }
     return (int)hipGetLastError();
 }
 
 template <typename T>
 static int launch_k1p_any(int pmax, int qmax, const void* args, const uint32_t* wg0, int n_inst,
-                          int moving, unsigned grid, size_t lds, void* stream, int alt) {
+                          int moving, unsigned grid, size_t lds, void* stream, int alt,
+                          int nt) {
     const bool q12 = qmax == 12;
     switch (pmax) {
-    case 3: return q12 ? launch_k1p_t<T, 3, 12>(args, wg0, n_inst, moving, grid, lds, stream, alt)
-                       : launch_k1p_t<T, 3, 8>(args, wg0, n_inst, moving, grid, lds, stream, alt);
-    case 6: return q12 ? launch_k1p_t<T, 6, 12>(args, wg0, n_inst, moving, grid, lds, stream, alt)
-                       : launch_k1p_t<T, 6, 8>(args, wg0, n_inst, moving, grid, lds, stream, alt);
-    case 9: return q12 ? launch_k1p_t<T, 9, 12>(args, wg0, n_inst, moving, grid, lds, stream, alt)
-                       : launch_k1p_t<T, 9, 8>(args, wg0, n_inst, moving, grid, lds, stream, alt);
-    default: return q12 ? launch_k1p_t<T, 16, 12>(args, wg0, n_inst, moving, grid, lds, stream, alt)
-                        : launch_k1p_t<T, 16, 8>(args, wg0, n_inst, moving, grid, lds, stream, alt);
+    case 3: return q12 ? launch_k1p_t<T, 3, 12>(args, wg0, n_inst, moving, grid, lds, stream, alt, nt)
+                       : launch_k1p_t<T, 3, 8>(args, wg0, n_inst, moving, grid, lds, stream, alt, nt);
+    case 6: return q12 ? launch_k1p_t<T, 6, 12>(args, wg0, n_inst, moving, grid, lds, stream, alt, nt)
+                       : launch_k1p_t<T, 6, 8>(args, wg0, n_inst, moving, grid, lds, stream, alt, nt);
+    case 9: return q12 ? launch_k1p_t<T, 9, 12>(args, wg0, n_inst, moving, grid, lds, stream, alt, nt)
+                       : launch_k1p_t<T, 9, 8>(args, wg0, n_inst, moving, grid, lds, stream, alt, nt);
+    default: return q12 ? launch_k1p_t<T, 16, 12>(args, wg0, n_inst, moving, grid, lds, stream, alt, nt)
+                        : launch_k1p_t<T, 16, 8>(args, wg0, n_inst, moving, grid, lds, stream, alt, nt);
     }
 }
 
 int launch_k1(int fp32, int pmax, int qmax, int paired, const void* args, const uint32_t* wg0,
-              int n_inst, int moving, unsigned grid, size_t lds, void* stream, int alt) {
+              int n_inst, int moving, unsigned grid, size_t lds, void* stream, int alt, int nt) {
     if (paired) {
         if (!k1p_buckets(pmax, qmax)) return (int)hipErrorInvalidValue;
         if (fp32)
             return launch_k1p_any<float>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream,
-                                         alt);
+                                         alt, nt);
         return launch_k1p_any<double>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream,
-                                      alt);
+                                      alt, nt);
     }
     if (fp32) return launch_k1_any<float>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream);
     return launch_k1_any<double>(pmax, qmax, args, wg0, n_inst, moving, grid, lds, stream);

@@ -265,6 +265,28 @@ def test_node_pairs_match_the_generic_stream_kernel(sg, prec, degree, nodes):
     assert np.allclose(a["rec"], b["rec"], rtol=1e-6 if prec == "fp32" else 1e-9)
 
 
+@pytest.mark.parametrize("pairs", [True, False])
+def test_stream_nontemporal_hints_change_nothing(sg, pairs):
+    """The stream kernels' non-temporal state access (chosen for states larger
+    than the last-level cache) gives the same run bit for bit as the ordinary
+    one, in both stream kernels."""
+    cfg = cfg_of(n_particles=60_000, degree=8, nodes_1d=12, nk=256, field0=4e6)
+    print(f"\n[gpu case] stream non-temporal hints, pairs {pairs}", flush=True)
+    out = []
+    for nt in (True, False):
+        sim = sg.Simulation(cfg, max_steps=40)
+        sim.set_node_pairs(pairs)
+        sim.set_stream_nontemporal(nt)
+        assert sim.stream_nontemporal() == nt
+        sim.init_particles()
+        sim.step(40)
+        out.append(snapshot(sim))
+        sim.set_stream_nontemporal(None)
+        assert sim.stream_nontemporal() is False       # 60k particles fit in the cache
+    assert out[0]["cnt"]["collisions"] > 0
+    assert_same(out[0], out[1], "non-temporal vs ordinary")
+
+
 def test_automatic_kernel_choice(sg):
     """The mirror-pair stream kernel is chosen by default only for shape
     groups of 2^22 particles or more; either choice can be forced."""
