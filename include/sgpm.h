@@ -213,13 +213,13 @@ sgpm_status sgpm_set_pair_block(sgpm_ctx* ctx, int32_t alt);
 /* *threads = threads per workgroup of the stream kernel of instance inst. */
 sgpm_status sgpm_stream_threads(const sgpm_ctx* ctx, int32_t inst, int32_t* threads);
 
-/* Cache hints of the stream kernels' state access: mode 1 reads the state and
- * writes its drift with non-temporal hints, 0 with ordinary ones, -1 (the
- * default) non-temporal when the state of all instances exceeds 192 MiB
- * (larger than the last-level cache: it is streamed through once per step,
- * and caching it only evicts what the collider and the next step could
- * reuse).  The results are identical either way.  Allowed at any time after
- * sgpm_create; EINVAL for another mode. */
+/* Cache hints of the mirror-pair stream kernel's state access: mode 1 reads
+ * the state and writes its drift with non-temporal hints, 0 with ordinary
+ * ones, -1 (the default) non-temporal when the state of some instance exceeds
+ * 1 GiB (several times the last-level cache: it is streamed through once per
+ * step, and caching it only evicts what the collider could reuse).  The
+ * results are identical either way.  Allowed at any time after sgpm_create;
+ * EINVAL for another mode. */
 sgpm_status sgpm_set_stream_nontemporal(sgpm_ctx* ctx, int32_t mode);
 
 /* *on = 1 if the stream kernels use non-temporal hints now. */

@@ -135,7 +135,7 @@ class Simulation:
 
     def set_stream_nontemporal(self, mode):
         """True/False: non-temporal hints on the stream kernels' state access
-        always / never; None: when the state exceeds the last-level cache."""
+        always / never; None: when some instance's state exceeds 1 GiB."""
         m = -1 if mode is None else (1 if mode else 0)
         check(lib().sgpm_set_stream_nontemporal(self._ctx, m), self._ctx, "set_stream_nontemporal")
 

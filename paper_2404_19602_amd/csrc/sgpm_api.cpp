@@ -29,11 +29,13 @@ constexpr double kECharge = 1.602176634e-19;
 constexpr int kMaxBins = 4096;
 constexpr int kDefaultGraphSteps = 16;
 constexpr int kMaxLdsBudget = 80 * 1024;   // largest window budget the slabs are sized for
-// state bytes of a context above which the stream kernels read the state and
-// write its drift with non-temporal hints: a state that does not fit in the
+// state bytes of an instance above which the stream kernels read the state
+// and write its drift with non-temporal hints: a state several times the
 // last-level cache (256 MB on MI355X) is streamed through it once per step,
-// and caching it only evicts what the collider and the next step could reuse
-constexpr size_t kStreamNtBytes = (size_t)192 << 20;
+// and caching it only evicts what the collider could reuse.  Below that (and
+// for a batch of smaller instances, whose collider still finds a good part of
+// its candidates' lines in the cache) the plain hints do better.
+constexpr size_t kStreamNtBytes = (size_t)1 << 30;
 constexpr int kMaxGraphSteps = 256;
 constexpr double kWinEv = 2.0;     // half-width (eV) beyond which the LDS window does not grow
 
@@ -428,7 +430,8 @@ Consts<T> make_consts(const sgpm_instance_desc& d, const HostTables& t) {
 bool stream_nt(const sgpm_ctx* cx) {
     if (cx->nt_mode >= 0) return cx->nt_mode == 1;
     size_t b = 0;
-    for (const Instance& J : cx->inst) b += (size_t)J.P * (size_t)J.n * 2 * (J.fp32 ? 4 : 8);
+    for (const Instance& J : cx->inst)
+        b = std::max(b, (size_t)J.P * (size_t)J.n * 2 * (J.fp32 ? 4 : 8));
     return b > kStreamNtBytes;
 }
 

@@ -282,7 +282,7 @@ def test_stream_nontemporal_hints_change_nothing(sg, pairs):
         sim.step(40)
         out.append(snapshot(sim))
         sim.set_stream_nontemporal(None)
-        assert sim.stream_nontemporal() is False       # 60k particles fit in the cache
+        assert sim.stream_nontemporal() is False       # 60k particles: far below 1 GiB
     assert out[0]["cnt"]["collisions"] > 0
     assert_same(out[0], out[1], "non-temporal vs ordinary")
 
