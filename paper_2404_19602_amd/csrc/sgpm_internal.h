@@ -104,13 +104,16 @@ constexpr int k1_waves(bool fp32, int pmax, int qmax) {
 // one workgroup per compute unit); alt: the other form the autotuner may pick.
 int k1p_block(int fp32, int pmax, int qmax, int alt);
 constexpr int kLdsPairBudget = 150 * 1024;   // LDS bytes of a mirror-pair stream workgroup
-constexpr int64_t kMaxPairChunk = (int64_t)1 << 24;   // its largest chunk
+// its largest chunk (longer than the 65535 a 16-bit window count holds: the
+// kernel moves large counts to the overflow grid between segments)
+constexpr int64_t kMaxPairChunk = (int64_t)1 << 24;
 // Mode and node buckets the mirror-pair stream kernel is built for.
 constexpr bool k1p_buckets(int pmax, int qmax) {
     return (qmax == 8 || qmax == 12) && (pmax == 3 || pmax == 6 || pmax == 9 || pmax == 16);
 }
 constexpr int kMaxStreamWG = 4096;    // cap on stream workgroups of one instance (sizes the slabs)
 constexpr int kMaxChunk = 8192;       // cap on particles per stream workgroup (LDS list)
+static_assert(kMaxChunk <= 65535, "the generic stream kernel's 16-bit window counts");
 constexpr int kK2Grid = 1024;         // persistent collider workgroups of one launch
 
 // Per-instance values that change from step to step, resident in device

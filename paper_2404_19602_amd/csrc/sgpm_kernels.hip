@@ -477,9 +477,10 @@ __device__ __forceinline__ void lds_add(uint32_t* p, uint32_t v) {
 // An increment of cell (q, r, l) of the overflow grid: the offset in 32 bits
 // (Q nk^2 < 2^30) from the uniform base, so the address takes no 64-bit
 // register pair.
-__device__ __forceinline__ void extra_add(uint32_t* extra, int q, int r, int l, int nk) {
+__device__ __forceinline__ void extra_add(uint32_t* extra, int q, int r, int l, int nk,
+                                          uint32_t v = 1u) {
     const uint32_t off = (uint32_t)(q * nk * nk + r * nk + l) << 2;
-    atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(extra) + off), 1u);
+    atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(extra) + off), v);
 }
 
 // one nodal value into H^n: LDS window when inside it, else the overflow grid
@@ -790,6 +791,29 @@ k1_stream(const K1Args<T>* __restrict__ all,
 // LDS.  The workgroup owns a whole compute unit (three or four waves per
 // SIMD), and with it nearly all of the LDS for the histogram window.
 //
+// Counts of the mirror-pair window above thr (a workgroup's counts, between
+// two segments of its chunk) moved to the overflow grid, the same cells of
+// H^n.  Plane p holds node p in its low and node Q-1-p in its high half (the
+// high half of an odd Q's middle plane stays empty).  Not inlined: it runs
+// at most once per 65535 particles of a workgroup, and inlined it costs the
+// tile loop registers.
+__device__ __attribute__((noinline)) void win_spill(uint32_t* hwin, uint32_t* extra, int Q,
+                                                    int W, int r0, int l0, int nk, uint32_t thr,
+                                                    int tid, int nthreads) {
+    const int WW = W * W, words = ((Q + 1) >> 1) * WW;
+    for (int k = tid; k < words; k += nthreads) {
+        const uint32_t v = hwin[k];
+        const uint32_t lo = v & 0xFFFFu, hi = v >> 16;
+        if (lo > thr || hi > thr) {
+            const int p = k / WW, wr = (k - p * WW) / W, wl = k - p * WW - wr * W;
+            uint32_t keep = v;
+            if (lo > thr) { extra_add(extra, p, r0 + wr, l0 + wl, nk, lo); keep -= lo; }
+            if (hi > thr) { extra_add(extra, Q - 1 - p, r0 + wr, l0 + wl, nk, hi); keep -= hi << 16; }
+            hwin[k] = keep;
+        }
+    }
+}
+
 // LDS window of this kernel: pair p in plane p, node p in the low and node
 // Q-1-p in the high 16 bits of a word, the middle node of an odd Q in the low
 // bits of plane (Q-1)/2.  The finalize kernel decodes it by the instance's
@@ -1068,9 +1092,31 @@ k1_pairs(const K1Args<T>* __restrict__ all, const uint32_t* __restrict__ wg0, in
             if (nseg > (uint32_t)(kK1PSeg - 64)) flush();
         }
     };
-    int64_t base = begin;
-    for (; base + BLOCK <= end; base += BLOCK) tile(base, std::true_type{});
-    if (base < end) tile(base, std::false_type{});
+    // A 16-bit count of the window holds 65535, and a particle adds at most one
+    // to each: a chunk longer than that is taken in segments of SEG particles,
+    // and between two segments the counts that the next one could carry past
+    // 65535 move to the overflow grid (win_spill).
+    constexpr int64_t SEG = (int64_t)(65535 / BLOCK) * BLOCK;
+    int64_t base = begin, next = begin + SEG;
+    for (; base + BLOCK <= end; base += BLOCK) {
+        if (base == next) {
+            __syncthreads();
+            win_spill(L.hwin, a.extra, Q, W, a.win_r0, a.win_l0, c.nk,
+                      65535u - (uint32_t)(end - base < SEG ? end - base : SEG), tid, BLOCK);
+            __syncthreads();
+            next += SEG;
+        }
+        tile(base, std::true_type{});
+    }
+    if (base < end) {
+        if (base == next) {
+            __syncthreads();
+            win_spill(L.hwin, a.extra, Q, W, a.win_r0, a.win_l0, c.nk,
+                      65535u - (uint32_t)(end - base), tid, BLOCK);
+            __syncthreads();
+        }
+        tile(base, std::false_type{});
+    }
     // the waves' remaining candidates with one reservation for the workgroup
     // (waves ending together would otherwise queue on the list's counter)
     {

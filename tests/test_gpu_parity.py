@@ -196,6 +196,57 @@ def test_step_parity(sg, orc, name):
     assert np.allclose(m["E_jx"], q["E_jx"], rtol=1e-8, atol=1e-9 * np.abs(q["E_jx"]).max() + 1e-6)
 
 
+@pytest.mark.parametrize("degree,nodes", [(5, 8), (4, 7)])
+def test_window_counts_beyond_16_bits(sg, orc, degree, nodes):
+    """The mirror-pair stream kernel packs two nodes' window counts as 16-bit
+    halves of a word.  One workgroup here takes all 200 000 particles: 70 000
+    sit at k = 0 and 70 000 at an odd-mode offset (mirror cells at nodes p and
+    Q-1-p, and k = 0 again at the middle node of an odd Q), so at every node
+    one window cell gets more than 65535 of that workgroup's counts, in the low
+    and in the high halves.  The histogram is still the oracle's, after the
+    state is set and after two steps."""
+    n = 200_000
+    cfg = small_cfg(dim_z=1, degree=degree, nodes_1d=nodes, gap_dim=0, gap_rel=0.1,
+                    n_particles=n, field0=2e6)
+    announce(f"window counts beyond 16 bits, Q={nodes}", cfg)
+    ref = orc.OracleSim(cfg, threads=8)
+    P = ref.P
+    rng = np.random.default_rng(9)
+    kx = np.zeros((P, n)); ky = np.zeros((P, n))
+    kx[1, 70_000:140_000] = 0.15
+    kx[0, 140_000:] = rng.normal(0.0, 0.1, n - 140_000)
+    ky[0, 140_000:] = rng.normal(0.0, 0.1, n - 140_000)
+    kx[1:, 140_000:] = rng.normal(0.0, 0.01, (P - 1, n - 140_000))
+    sim = sg.Simulation(cfg, max_steps=4)
+    sim.set_node_pairs(True)
+    assert sim.node_pairs()
+    sim.set_chunk(200_704)
+    assert sim.launch_shape()["stream_workgroups"] == 1
+    # the concentrated cells (|k| < 0.3 eV) lie inside the LDS window
+    dk = 2 * cfg["lk_eV"] / cfg["nk"]
+    assert sim.window()["cells"] >= 2 * math.ceil(0.3 / dk) + 2
+    ref.set_state(kx, ky, step=0)
+    sim.set_state(kx, ky, step=0)
+    H, M = sim.histogram()
+    Ho, Mo = ref.histogram()
+    assert Ho.max() >= 70_000 and np.all(Ho.sum(axis=(1, 2)) == n)
+    assert np.array_equal(H, Ho) and np.array_equal(M, Mo)
+    sim.step(2, cfg["dt"])
+    ref.run(cfg["dt"], 2)
+    gx, gy = sim.get_state()
+    ox, oy = ref.get_state()
+    flips = int(np.count_nonzero(rel_err(gx, gy, ox, oy) > TOL))
+    print(f"  flipped particles {flips}, counters {sim.counters()}", flush=True)
+    assert flips <= max(2, n // 10_000)
+    H, M = sim.histogram()
+    Ho, Mo = ref.histogram()
+    assert Ho.max() > 65_535
+    if flips == 0:
+        assert np.array_equal(H, Ho) and np.array_equal(M, Mo)
+    else:
+        assert np.abs(H.astype(np.int64) - Ho).sum() <= 2 * flips * ref.Q
+
+
 def test_chunk_invariance(sg):
     """The launch shape does not change any particle's trajectory."""
     cfg = small_cfg(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, gap_rel=0.1, n_particles=30_000,
