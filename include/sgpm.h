@@ -112,7 +112,7 @@ typedef struct {
     double temp_K;          /* lattice temperature: Bose factors, acoustic rate    */
                             /* [300]                                                */
     double alpha;           /* self-scattering parameter of eq. gamma_tot [0.1]     */
-    int32_t nk;             /* histogram cells per axis [240]                       */
+    int32_t nk;             /* histogram cells per axis [240], 2..4096, Q nk^2 < 2^30 */
     double lk_eV;           /* grid half-width L_k hbar v_F [5]                     */
     int32_t pauli;          /* 1: Pauli acceptance on [1]                           */
     int32_t final_state;    /* 0: energy-conserving phonon final state [0]; 1: the  */

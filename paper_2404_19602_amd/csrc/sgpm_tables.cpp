@@ -150,6 +150,8 @@ const char* build_tables(const sgpm_instance_desc& d, HostTables& t) {
     t.Q = d.dim_z == 0 ? 1 : (d.dim_z == 1 ? t.nodes_1d : t.nodes_1d * t.nodes_1d);
     if (t.P > kMaxP) return "too many gPC modes (the kernels take P <= 32)";
     if (t.Q > kMaxQ) return "too many nodes (the kernels take Q <= 128)";
+    // cell offsets of H^n and the overflow grid are 32-bit byte offsets
+    if ((int64_t)t.Q * d.nk * d.nk >= ((int64_t)1 << 30)) return "Q nk^2 must be below 2^30";
     const int P = t.P, Q = t.Q, n1 = t.nodes_1d;
 
     std::vector<double> gx(n1), gw(n1);

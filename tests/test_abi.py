@@ -98,10 +98,15 @@ def test_workspace_bytes_and_validation():
     bad = [dict(n_particles=0), dict(dim_z=3), dict(temp_K=-1.0), dict(nk=1), dict(c_max=0),
            dict(c_max=300), dict(dim_z=1, gap_dim=1), dict(gap0=-0.1), dict(precision=7),
            dict(dim_z=1, degree=40, nodes_1d=41, gap_dim=0), dict(max_steps=-1),
-           dict(pauli=2), dict(alpha=-0.5)]
+           dict(pauli=2), dict(alpha=-0.5),
+           # Q nk^2 = 121 * 4096^2 > 2^30: cell offsets would leave 32 bits
+           dict(dim_z=2, degree=2, nodes_1d=11, gap_dim=0, nk=4096)]
     for b in bad:
         db = _desc(**b)
         assert lib.sgpm_workspace_bytes(C.byref(db), 1, C.byref(nb)) == 1, b
+    # the largest grid with 8 nodes stays within the 32-bit cell offsets
+    dbig = _desc(dim_z=1, degree=5, nodes_1d=8, gap_dim=0, nk=4096)
+    assert lib.sgpm_workspace_bytes(C.byref(dbig), 1, C.byref(nb)) == 0
     assert lib.sgpm_workspace_bytes(None, 1, C.byref(nb)) == 1
     assert lib.sgpm_workspace_bytes(C.byref(d), 0, C.byref(nb)) == 1
 
