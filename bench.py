@@ -169,8 +169,11 @@ def measured_traffic(kernel: str, stream_workgroups=None):
     """HBM bytes per launch of a kernel from the committed PMC summary, if the
     kernel source is the one the counters were taken on and, when both are
     known, the launch shape (stream workgroups) is the same: the window slabs
-    the stream kernel writes and the finalize kernel reads scale with it."""
-    if not os.path.exists(TRAFFIC_FILE):
+    the stream kernel writes and the finalize kernel reads scale with it.  The
+    collider's traffic scales with the candidate count, which grows through a
+    run: the counters, taken over the first 40 steps, do not hold for another
+    window, so none is reported for it."""
+    if kernel == "collide" or not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         rec = json.load(fh)

@@ -180,7 +180,8 @@ def test_pmc_summary_keeps_the_timed_passes(tmp_path):
 
 def test_traffic_only_for_the_same_launch_shape(monkeypatch, tmp_path):
     rec = {"source_sha256": "h", "stream_workgroups": 245,
-           "kernels": {"stream": {"fetch_bytes": 1.0, "write_bytes": 2.0}}}
+           "kernels": {"stream": {"fetch_bytes": 1.0, "write_bytes": 2.0},
+                       "collide": {"fetch_bytes": 4.0, "write_bytes": 5.0}}}
     path = tmp_path / "t.json"
     path.write_text(json.dumps(rec))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
@@ -188,6 +189,8 @@ def test_traffic_only_for_the_same_launch_shape(monkeypatch, tmp_path):
     assert bench.measured_traffic("stream", 245) == 3.0
     assert bench.measured_traffic("stream", 490) is None
     assert bench.measured_traffic("stream") == 3.0
+    # the collider's traffic depends on the step window's candidate count
+    assert bench.measured_traffic("collide", 245) is None
 
 
 def test_pmc_summary_sums_the_collider_launches_of_a_step(tmp_path):
